@@ -1,0 +1,235 @@
+/*
+ * dtm.h -- dead-time Markov stationary PDFs for asynchronous single-photon
+ * LiDAR on AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the accelerated Markov pipeline of Zhang,
+ * Weerasooriya, Chennuri and Chan, "Real-Time Markov Modeling for
+ * Single-Photon LiDAR: 1000x Acceleration and Convergence Analysis"
+ * (arXiv 2509.20500):
+ *
+ *   bin tables    lambda_j = lambda(s_j) and cumulative flux F_j = F(s_j)
+ *                 (Eq. arrival_flux; F is defined in Theorem 1),
+ *   base matrix   P~_base = rownorm((1 lambda^T) (.) exp(-Lambda L - D))
+ *                 (Section 3.4),
+ *   dead time     P~ = J_l P~_base, rows rolled by l = ceil(x_d / Delta)
+ *                 (Theorem 2, Section 3.4),
+ *   stationary    pi P~ = pi, the leading left eigenvector (Section 2.3),
+ *                 here by power iteration.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Units: time in ns; signal and background flux in expected photons per
+ *   laser period (S = alpha*calE, B = t_r*lambda_b of Section 2.1).
+ * - Bins are 0-based with centres s_j = (j + 1/2) Delta, Delta = t_r / n_b.
+ * - Matrices are dense, row-major, rows = current state, columns = next
+ *   state; element (i, j) lives at P[i*ld + j], ld >= n (in elements).
+ * - Row i of the dead-time matrix is row (i + l) mod n of the base matrix:
+ *   the reactivation bin of state s_i is l bins later (Theorem 2).
+ * - Lambda (the wrap term of Theorem 1) is the one-period integral F(t_r).
+ *   It equals S + B when the pulse lies inside [0, t_r).
+ * - "_dev" pointers are device memory, "_host" pointers host memory; the
+ *   caller owns every buffer.  No entry point allocates device memory.
+ * - Every function enqueues its work on `stream` (a hipStream_t; NULL is the
+ *   null stream) and returns without waiting, unless its comment says it
+ *   synchronises.
+ * - Argument, aliasing and size errors are detected on the host before any
+ *   launch and nothing is written.  A failed launch returns DTM_EHIP.
+ *   Non-convergence of one pixel is a soft, per-pixel status.
+ * - Thread safety: calls on different streams may run concurrently; a plan
+ *   must not be used by two threads at once.
+ */
+#ifndef DTM_H
+#define DTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define DTM_OK        0
+#define DTM_EINVAL   (-1)  /* invalid argument (scene, size, pointer, option) */
+#define DTM_ENOTCONV (-2)  /* power iteration stopped at max_iter (soft)      */
+#define DTM_EHIP     (-3)  /* a HIP runtime call or kernel launch failed      */
+#define DTM_EALIAS   (-4)  /* input and output buffers overlap                */
+#define DTM_ENOSPACE (-5)  /* workspace too small                             */
+#define DTM_ENOTSUP  (-6)  /* valid request this build does not support       */
+
+typedef void* dtm_stream_t; /* a hipStream_t */
+
+typedef enum dtm_dtype { DTM_F64 = 0, DTM_F32 = 1 } dtm_dtype;
+
+/* One pixel: the problem statement theta = (t_r, t_d, sigma_t, tau, S, B, n_b)
+ * of Section 2.2 with the flux model of Eq. (arrival_flux):
+ *   lambda(t) = S * N(t - tau; 0, sigma^2) + B / t_r,  t in [0, t_r).
+ * Valid: t_r > 0, t_d >= 0 (only t_d mod t_r matters), 0 <= tau < t_r,
+ * sigma > 0, S >= 0, B >= 0, S + B > 0, B > 0 or S > 0 with a reachable chain,
+ * 2 <= n_b <= DTM_MAX_BINS, reserved == 0, every field finite. */
+typedef struct dtm_scene {
+  double period_ns;       /* t_r */
+  double dead_time_ns;    /* t_d */
+  double pulse_center_ns; /* tau */
+  double pulse_sigma_ns;  /* sigma_t */
+  double signal_flux;     /* S */
+  double background_flux; /* B */
+  int32_t n_bins;         /* n_b */
+  int32_t reserved;       /* must be 0 */
+} dtm_scene;
+
+#define DTM_MAX_BINS 65536
+
+/* Stop rules of the power iteration (Section 4: the convergence rate is set
+ * by |lambda_2|, which the bound rule estimates from successive changes). */
+#define DTM_STOP_CHANGE 0 /* stop when ||x_{t+1} - x_t||_1 < tol_l1              */
+#define DTM_STOP_BOUND  1 /* stop when c_t * rho/(1-rho) <= safety * tol_l1, then
+                             confirm with a float64 residual sweep              */
+
+/* Option flags */
+#define DTM_FLAG_NO_FINAL_CHECK 0x1 /* skip the float64 residual sweep            */
+
+typedef struct dtm_solve_opts {
+  double tol_l1;       /* target L1 distance (rule 1) or change threshold (rule 0) */
+  double safety;       /* rule 1: fraction of tol_l1 the bound must reach (0,1]   */
+  int32_t max_iter;    /* sweeps, >= 1                                             */
+  int32_t check_every; /* single-pixel path: host polls every this many sweeps    */
+  int32_t stop_rule;   /* DTM_STOP_CHANGE or DTM_STOP_BOUND                        */
+  int32_t flags;       /* DTM_FLAG_*                                               */
+} dtm_solve_opts;
+
+/* Per-pixel solver report.  status is DTM_OK or DTM_ENOTCONV (or DTM_EINVAL
+ * for an invalid warm start that was replaced; see flags). */
+#define DTM_INFO_WARM_REJECTED 0x1 /* x0 was not a positive finite vector: uniform used */
+#define DTM_INFO_RESTARTED     0x2 /* warm start did not converge: re-ran from uniform   */
+#define DTM_INFO_CHECKED       0x4 /* residual_l1 comes from a float64 check sweep       */
+typedef struct dtm_solve_info {
+  int32_t iterations;  /* sweeps performed (each reads the matrix once)         */
+  int32_t status;
+  int32_t flags;       /* DTM_INFO_*                                            */
+  int32_t reserved;
+  double change_l1;    /* ||x_T - x_{T-1}||_1 of the last iterate             */
+  double residual_l1;  /* ||x P~ - x||_1 of the input of the last sweep        */
+  double rho_hat;      /* estimate of |lambda_2| from successive changes       */
+} dtm_solve_info;
+
+const char* dtm_status_string(int status);
+int dtm_version(void); /* major*10000 + minor*100 + patch */
+
+/* Host only, pure.  Returns DTM_OK or DTM_EINVAL for an invalid scene. */
+int dtm_validate_scene(const dtm_scene* s);
+
+/* Host only, pure: the dead-time shift of Theorem 2,
+ *   l = ceil(x_d / Delta) mod n_b,  x_d = t_d mod t_r,
+ * evaluated as q = x_d * n_b / t_r, with q snapped to the nearest integer when
+ * it is one to 1e-9 relative (a dead time of whole bins is not rounded up). */
+int dtm_shift_bins(const dtm_scene* s, int32_t* l_out);
+
+/* ---- single pixel ------------------------------------------------------- */
+
+/* Device workspace every single-pixel call below needs, in bytes, for a
+ * matrix of n bins.  Holds the bin tables and the solver's partial sums. */
+size_t dtm_workspace_bytes(int32_t n, dtm_dtype dt);
+
+/* Bin tables (Eq. arrival_flux, Theorem 1): writes lambda_dev[j] = lambda(s_j)
+ * in dt (n elements) and F_dev[j] = F(s_j) in float64 (n + 1 elements; the
+ * last one is Lambda = F(t_r)).  F comes from per-bin flux integrals (erf /
+ * erfc differences) and a float64 exclusive prefix scan, plus the half-bin
+ * integral up to the centre.  Either output may be NULL. */
+int dtm_bin_tables(const dtm_scene* s, dtm_dtype dt, void* lambda_dev, double* F_dev,
+                   void* workspace_dev, size_t workspace_bytes, dtm_stream_t stream);
+
+/* Base matrix (Section 3.4): P_base_dev[k*ld + j] =
+ *   lambda_j exp(-Lambda [k > j] - F_j + F_k) / R_k,
+ * R_k the row sum (wavefront reduction; compensated in float32).  n x n. */
+int dtm_build_base(const dtm_scene* s, dtm_dtype dt, void* P_base_dev, int64_t ld,
+                   void* workspace_dev, size_t workspace_bytes, dtm_stream_t stream);
+
+/* Dead time as a row permutation (Theorem 2): P_dev[i, :] =
+ * P_base_dev[(i + l) mod n, :].  Out of place; overlapping buffers give
+ * DTM_EALIAS.  Both matrices use the same ld. */
+int dtm_apply_deadtime_shift(const dtm_scene* s, dtm_dtype dt, const void* P_base_dev,
+                             void* P_dev, int64_t ld, dtm_stream_t stream);
+
+/* Base matrix and shift fused: writes P~ = J_l P~_base directly (row i is
+ * built from reactivation bin (i + l) mod n); no extra traffic. */
+int dtm_build_transition(const dtm_scene* s, dtm_dtype dt, void* P_dev, int64_t ld,
+                         void* workspace_dev, size_t workspace_bytes, dtm_stream_t stream);
+
+/* Stationary vector of a row-stochastic n x n matrix P_dev (any such matrix,
+ * e.g. from dtm_build_transition) by power iteration x <- x P / sum(x P)
+ * from x0_dev (n elements of dt; NULL = uniform 1/n).  Writes pi_dev (n
+ * elements of dt, sums to 1) and *info_host.  The accumulation of x P is
+ * compensated in float32.  Synchronises `stream` before returning; returns
+ * DTM_OK even when info_host->status is DTM_ENOTCONV.  opt NULL = defaults
+ * (tol 1e-6, safety 0.25, max_iter 1000, check_every 4, DTM_STOP_BOUND). */
+int dtm_stationary_pdf(const void* P_dev, int32_t n, int64_t ld, dtm_dtype dt,
+                       const dtm_solve_opts* opt, const void* x0_dev, void* pi_dev,
+                       void* workspace_dev, size_t workspace_bytes,
+                       dtm_solve_info* info_host, dtm_stream_t stream);
+
+/* ---- batched: many pixels with uneven n_b and dead time ------------------ */
+
+/* Launch shape of the batched kernels.  Zero fields take the built-in or
+ * autotuned defaults. */
+typedef struct dtm_tile_config {
+  int32_t fused_threads;   /* threads per workgroup of the fused kernel: 256 or 512 */
+  int32_t fused_unroll;    /* rows in flight per thread in a sweep: 2, 4 or 8       */
+  int32_t fused_max_bins;  /* pixels with n_b above this take the banded path       */
+  int32_t band_rows;       /* rows per workgroup in the banded sweep                */
+} dtm_tile_config;
+
+typedef struct dtm_plan dtm_plan; /* opaque host object */
+
+/* Validates every scene (DTM_EINVAL names nothing: use dtm_validate_scene to
+ * find the pixel), fixes offsets, pixel order and launch shapes.  Copies the
+ * scenes; scenes_host may be freed afterwards.  opt NULL = defaults; tiles
+ * NULL = defaults. */
+int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt,
+                    const dtm_solve_opts* opt, const dtm_tile_config* tiles,
+                    dtm_plan** plan_out);
+void dtm_plan_destroy(dtm_plan* plan);
+
+/* Device workspace the plan needs (per-pixel metadata, bin tables, the dense
+ * matrices of every pixel, iterates and partial sums), in bytes. */
+size_t dtm_plan_workspace_bytes(const dtm_plan* plan);
+/* Sum over pixels of n_b (length of the packed pi) and of n_b^2 (packed
+ * matrices). */
+int64_t dtm_plan_pi_elems(const dtm_plan* plan);
+int64_t dtm_plan_matrix_elems(const dtm_plan* plan);
+/* pi_offsets[p] = sum_{q<p} n_b(q) (n_pixels + 1 entries) and
+ * mat_offsets[p] = sum_{q<p} n_b(q)^2; either may be NULL. */
+int dtm_plan_offsets(const dtm_plan* plan, int64_t* pi_offsets_host, int64_t* mat_offsets_host);
+/* The launch shape the plan uses (after defaults and autotuning). */
+int dtm_plan_tiles(const dtm_plan* plan, dtm_tile_config* tiles_out);
+
+/* Binds the plan to a workspace and uploads its metadata there.
+ * Synchronises `stream`.  Must precede the calls below; re-binding moves it. */
+int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes,
+                  dtm_stream_t stream);
+
+/* Solves every pixel: bin tables, transition matrix (shift fused), power
+ * iteration with the plan's stop rule, float64 residual check.  Writes pi
+ * packed by pi_offsets (dtype of the plan) and one dtm_solve_info per pixel
+ * to infos_dev (device memory, plan order = input order).  x0_packed_dev
+ * (packed like pi, dtype of the plan) seeds the iteration; NULL = uniform.
+ * A warm start that is not positive and finite is replaced by uniform; one
+ * that does not converge within max_iter is re-run from uniform.  Launches
+ * only: no host synchronisation, no allocation, no memset, so the call can
+ * be captured in a hipGraph and replayed. */
+int dtm_solve_batched(const dtm_plan* plan, const void* x0_packed_dev, void* pi_packed_dev,
+                      dtm_solve_info* infos_dev, dtm_stream_t stream);
+
+/* Batched a2 / a3 / fused a2+a3, writing every pixel's n_b x n_b matrix
+ * packed by mat_offsets (ld = n_b).  Launch only. */
+int dtm_build_base_batched(const dtm_plan* plan, void* P_packed_dev, dtm_stream_t stream);
+int dtm_apply_deadtime_shift_batched(const dtm_plan* plan, const void* P_base_packed_dev,
+                                     void* P_packed_dev, dtm_stream_t stream);
+int dtm_build_transition_batched(const dtm_plan* plan, void* P_packed_dev,
+                                 dtm_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DTM_H */

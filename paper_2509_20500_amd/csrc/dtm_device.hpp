@@ -1,0 +1,172 @@
+// Device building blocks for gfx950: reductions, bin tables, row sums and
+// the per-element value of the transition matrix.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dtm_internal.h"
+
+namespace dtm {
+
+constexpr int kWave = 64;
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4;
+};
+template <>
+struct Vec<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+
+// ---- reductions (fixed order: results are bitwise reproducible) ----------
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum of a and of b over the block; every thread gets both.  `red` is LDS
+// with room for 2 * BT / 64 doubles.
+template <int BT>
+__device__ inline void block_sum2(double& a, double& b, double* red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x % kWave) == 0) {
+    red[w] = a;
+    red[BT / kWave + w] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int i = 0; i < BT / kWave; ++i) {
+    sa += red[i];
+    sb += red[BT / kWave + i];
+  }
+  a = sa;
+  b = sb;
+}
+
+template <int BT>
+__device__ inline double block_sum(double a, double* red) {
+  double b = 0.0;
+  block_sum2<BT>(a, b, red);
+  return a;
+}
+
+// Exclusive prefix sum over the block in thread order; `total` gets the sum.
+template <int BT>
+__device__ inline double block_exclusive_scan(double v, double* red, double& total) {
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  double x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  double excl = __shfl_up(x, 1, kWave);
+  if (lane == 0) excl = 0.0;
+  __syncthreads();
+  if (lane == kWave - 1) red[w] = x;
+  __syncthreads();
+  double base = 0.0, tot = 0.0;
+#pragma unroll
+  for (int i = 0; i < BT / kWave; ++i) {
+    if (i < w) base += red[i];
+    tot += red[i];
+  }
+  total = tot;
+  return base + excl;
+}
+
+// Compensated (Kahan) accumulation; the sum is s - c.  float64 needs none.
+__device__ inline void comp_add(float& s, float& c, float v) {
+  const float y = v - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+__device__ inline void comp_add(double& s, double& c, double v) {
+  (void)c;
+  s += v;
+}
+
+// ---- bin tables ------------------------------------------------------------
+
+// Probability mass of the standard normal on [za, zb] (za <= zb), from the
+// tail that keeps the difference accurate.
+__device__ inline double gauss_mass(double za, double zb) {
+  const double r = 0.70710678118654752440;  // 1/sqrt(2)
+  if (za >= 0.0) return 0.5 * (erfc(za * r) - erfc(zb * r));
+  if (zb <= 0.0) return 0.5 * (erfc(-zb * r) - erfc(-za * r));
+  return 0.5 * (erf(zb * r) - erf(za * r));
+}
+
+// Flux integral of lambda over [a, b] inside one period (Eq. arrival_flux):
+// S times the normal mass plus the background share B (b - a) / t_r.
+__device__ inline double flux_integral(const PixelMeta& m, double a, double b) {
+  const double is = 1.0 / m.sigma;
+  return m.S * gauss_mass((a - m.tau) * is, (b - m.tau) * is) + m.B * (b - a) / m.t_r;
+}
+
+// lambda(t) = S N(t - tau; 0, sigma^2) + B / t_r (Eq. arrival_flux).
+__device__ inline double flux_at(const PixelMeta& m, double t) {
+  const double z = (t - m.tau) / m.sigma;
+  return m.S * exp(-0.5 * z * z) * (0.39894228040143267794 / m.sigma) + m.B / m.t_r;
+}
+
+// Bin tables of one pixel, computed by the whole block (BT threads).
+// F_j = F(s_j) (Theorem 1) is an exclusive float64 prefix sum of per-bin
+// integrals plus the half-bin integral up to the centre; Lambda = F(t_r).
+// Writes g_j = lambda_j exp(-F_j) in T for j < n and 0 for n <= j < ld
+// (g may point to LDS or global memory), and optionally lambda_j (T) and
+// F_j (float64, with F_n = Lambda).  Returns Lambda.
+template <typename T, int BT>
+__device__ double pixel_tables(const PixelMeta& m, T* g, T* lam_out, double* F_out, double* red) {
+  const int n = m.n;
+  const double delta = m.t_r / n;
+  const int chunk = (n + BT - 1) / BT;
+  const int j0 = min(static_cast<int>(threadIdx.x) * chunk, n);
+  const int j1 = min(j0 + chunk, n);
+  double part = 0.0;
+  for (int j = j0; j < j1; ++j) part += flux_integral(m, j * delta, (j + 1) * delta);
+  double total;
+  double acc = block_exclusive_scan<BT>(part, red, total);
+  for (int j = j0; j < j1; ++j) {
+    const double lo = j * delta;
+    const double F = acc + flux_integral(m, lo, lo + 0.5 * delta);
+    acc += flux_integral(m, lo, (j + 1) * delta);
+    const double lj = flux_at(m, lo + 0.5 * delta);
+    g[j] = static_cast<T>(lj * exp(-F));
+    if (lam_out) lam_out[j] = static_cast<T>(lj);
+    if (F_out) F_out[j] = F;
+  }
+  for (int j = n + threadIdx.x; j < m.ld; j += BT) g[j] = T(0);
+  if (F_out && threadIdx.x == 0) F_out[n] = total;
+  return total;
+}
+
+// Row sum S_k = sum_j g_j w_kj with w_kj = c for j < k (the wrap term
+// exp(-Lambda) of Theorem 1's indicator) and 1 otherwise, by one wavefront:
+// per-lane compensated partials, then a float64 butterfly.  The row factor
+// exp(F_k) of E is common to the whole row and cancels in the normalisation,
+// so it is never formed.  Returns the sum on every lane.
+template <typename T>
+__device__ inline double wave_row_sum(const T* g, int n, int k, T c) {
+  const int lane = threadIdx.x % kWave;
+  T s = T(0), comp = T(0);
+  for (int j = lane; j < n; j += kWave) {
+    const T v = g[j] * (j < k ? c : T(1));
+    comp_add(s, comp, v);
+  }
+  return wave_sum(static_cast<double>(s) - static_cast<double>(comp));
+}
+
+}  // namespace dtm

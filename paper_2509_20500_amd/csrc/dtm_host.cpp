@@ -1,0 +1,245 @@
+// Host-only logic of the library: argument validation, the dead-time shift
+// rule, solver options and batched plans.  No HIP calls.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "dtm_internal.h"
+
+namespace dtm {
+
+// Scene validation (Section 2.2's theta; flux model of Eq. arrival_flux).
+// float32 needs exp(-Lambda) and exp(-F) to stay normal: S + B <= 80.
+int validate_scene(const dtm_scene& s, dtm_dtype dt) {
+  const double v[6] = {s.period_ns, s.dead_time_ns, s.pulse_center_ns,
+                       s.pulse_sigma_ns, s.signal_flux, s.background_flux};
+  for (double x : v)
+    if (!std::isfinite(x)) return DTM_EINVAL;
+  if (s.period_ns <= 0.0 || s.dead_time_ns < 0.0 || s.pulse_sigma_ns <= 0.0) return DTM_EINVAL;
+  if (s.signal_flux < 0.0 || s.background_flux < 0.0) return DTM_EINVAL;
+  if (!(s.signal_flux + s.background_flux > 0.0)) return DTM_EINVAL;
+  if (s.n_bins < 2 || s.n_bins > DTM_MAX_BINS || s.reserved != 0) return DTM_EINVAL;
+  if (dt != DTM_F32 && dt != DTM_F64) return DTM_EINVAL;
+  const double lim = dt == DTM_F32 ? 80.0 : 700.0;
+  if (s.signal_flux + s.background_flux > lim) return DTM_ENOTSUP;
+  return DTM_OK;
+}
+
+// l = ceil(x_d / Delta) mod n_b (Theorem 2) with x_d = t_d mod t_r.
+// q = x_d * n_b / t_r; a q within 1e-9 (relative) of an integer is that
+// integer: the dead time is a whole number of bins and the shifted centre is
+// itself a centre, so there is nothing to round up.
+int shift_bins(const dtm_scene& s, int32_t* l) {
+  const double x_d = std::fmod(s.dead_time_ns, s.period_ns);
+  const double q = x_d * static_cast<double>(s.n_bins) / s.period_ns;
+  const double r = std::nearbyint(q);
+  double lq;
+  if (std::fabs(q - r) <= 1e-9 * std::max(1.0, q))
+    lq = r;
+  else
+    lq = std::ceil(q);
+  int64_t li = static_cast<int64_t>(lq) % s.n_bins;
+  if (li < 0) li += s.n_bins;
+  *l = static_cast<int32_t>(li);
+  return DTM_OK;
+}
+
+int fill_opts(const dtm_solve_opts* opt, KOpts* k, int32_t* check_every) {
+  dtm_solve_opts o;
+  if (opt) {
+    o = *opt;
+  } else {
+    o.tol_l1 = 1e-6;
+    o.safety = 0.25;
+    o.max_iter = 1000;
+    o.check_every = 4;
+    o.stop_rule = DTM_STOP_BOUND;
+    o.flags = 0;
+  }
+  if (!(o.tol_l1 > 0.0) || !std::isfinite(o.tol_l1)) return DTM_EINVAL;
+  if (!(o.safety > 0.0 && o.safety <= 1.0)) return DTM_EINVAL;
+  if (o.max_iter < 1 || o.check_every < 1) return DTM_EINVAL;
+  if (o.stop_rule != DTM_STOP_CHANGE && o.stop_rule != DTM_STOP_BOUND) return DTM_EINVAL;
+  if (o.flags & ~DTM_FLAG_NO_FINAL_CHECK) return DTM_EINVAL;
+  k->tol = o.tol_l1;
+  k->safety = o.safety;
+  k->max_iter = o.max_iter;
+  k->stop_rule = o.stop_rule;
+  k->final_check = (o.flags & DTM_FLAG_NO_FINAL_CHECK) ? 0 : 1;
+  k->pad = 0;
+  if (check_every) *check_every = o.check_every;
+  return DTM_OK;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace dtm
+
+using namespace dtm;
+
+extern "C" {
+
+const char* dtm_status_string(int status) {
+  switch (status) {
+    case DTM_OK: return "ok";
+    case DTM_EINVAL: return "invalid argument";
+    case DTM_ENOTCONV: return "power iteration did not converge within max_iter";
+    case DTM_EHIP: return "HIP runtime error";
+    case DTM_EALIAS: return "input and output buffers overlap";
+    case DTM_ENOSPACE: return "workspace too small";
+    case DTM_ENOTSUP: return "not supported by this build";
+    default: return "unknown status";
+  }
+}
+
+int dtm_version(void) { return 10000; }
+
+int dtm_validate_scene(const dtm_scene* s) {
+  if (!s) return DTM_EINVAL;
+  return validate_scene(*s, DTM_F64);
+}
+
+int dtm_shift_bins(const dtm_scene* s, int32_t* l_out) {
+  if (!s || !l_out) return DTM_EINVAL;
+  const int st = validate_scene(*s, DTM_F64);
+  if (st != DTM_OK) return st;
+  return shift_bins(*s, l_out);
+}
+
+size_t dtm_workspace_bytes(int32_t n, dtm_dtype dt) {
+  if (n < 2 || n > DTM_MAX_BINS || (dt != DTM_F32 && dt != DTM_F64)) return 0;
+  return single_layout(n, dt).total;
+}
+
+int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt,
+                    const dtm_solve_opts* opt, const dtm_tile_config* tiles,
+                    dtm_plan** plan_out) {
+  if (!plan_out) return DTM_EINVAL;
+  *plan_out = nullptr;
+  if (!scenes_host || n_pixels < 1) return DTM_EINVAL;
+  if (dt != DTM_F32 && dt != DTM_F64) return DTM_EINVAL;
+  KOpts ko;
+  int32_t ce = 4;
+  int st = fill_opts(opt, &ko, &ce);
+  if (st != DTM_OK) return st;
+  for (int32_t p = 0; p < n_pixels; ++p) {
+    st = validate_scene(scenes_host[p], dt);
+    if (st != DTM_OK) return st;
+  }
+  dtm_plan* plan = new (std::nothrow) dtm_plan();
+  if (!plan) return DTM_EINVAL;
+  plan->dt = dt;
+  plan->kopts = ko;
+  plan->check_every = ce;
+  dtm_tile_config tc = {0, 0, 0, 0};
+  if (tiles) tc = *tiles;
+  if (tc.fused_threads == 0) tc.fused_threads = 256;
+  if (tc.fused_unroll == 0) tc.fused_unroll = 8;
+  if (tc.fused_max_bins == 0) tc.fused_max_bins = DTM_MAX_BINS;
+  if (tc.band_rows == 0) tc.band_rows = 256;
+  if ((tc.fused_threads != 256 && tc.fused_threads != 512) ||
+      (tc.fused_unroll != 2 && tc.fused_unroll != 4 && tc.fused_unroll != 8) ||
+      tc.fused_max_bins < 2 || tc.band_rows < 16 || tc.band_rows % 16 != 0) {
+    delete plan;
+    return DTM_EINVAL;
+  }
+  plan->tiles = tc;
+  plan->n_pixels = n_pixels;
+
+  // Launch order: descending n (longest jobs first), stable on input index.
+  std::vector<int32_t> order(n_pixels);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return scenes_host[a].n_bins > scenes_host[b].n_bins;
+  });
+  // Offsets in the caller's order.
+  std::vector<int64_t> pi_off(n_pixels), out_off(n_pixels);
+  int64_t acc_pi = 0, acc_out = 0;
+  for (int32_t p = 0; p < n_pixels; ++p) {
+    pi_off[p] = acc_pi;
+    out_off[p] = acc_out;
+    acc_pi += scenes_host[p].n_bins;
+    acc_out += static_cast<int64_t>(scenes_host[p].n_bins) * scenes_host[p].n_bins;
+  }
+  plan->pi_elems = acc_pi;
+  plan->mat_elems = acc_out;
+  plan->meta.resize(n_pixels);
+  int64_t acc_vec = 0, acc_pool = 0;
+  int32_t max_n = 0, max_ld = 0;
+  for (int32_t q = 0; q < n_pixels; ++q) {
+    const int32_t p = order[q];
+    const dtm_scene& s = scenes_host[p];
+    PixelMeta& m = plan->meta[q];
+    m.t_r = s.period_ns;
+    m.tau = s.pulse_center_ns;
+    m.sigma = s.pulse_sigma_ns;
+    m.S = s.signal_flux;
+    m.B = s.background_flux;
+    m.n = s.n_bins;
+    shift_bins(s, &m.l);
+    m.ld = padded_ld(s.n_bins, dt);
+    m.index = p;
+    m.pi_off = pi_off[p];
+    m.vec_off = acc_vec;
+    m.mat_off = acc_pool;
+    m.out_off = out_off[p];
+    acc_vec += m.ld;
+    acc_pool += static_cast<int64_t>(m.n) * m.ld;
+    max_n = std::max(max_n, m.n);
+    max_ld = std::max(max_ld, m.ld);
+  }
+  plan->vec_elems = acc_vec;
+  plan->pool_elems = acc_pool;
+  plan->max_n = max_n;
+  plan->max_ld = max_ld;
+  const size_t es = dtype_size(dt);
+  size_t off = 0;
+  plan->off_meta = off;
+  off = align_up(off + sizeof(PixelMeta) * n_pixels, 256);
+  plan->off_colf = off;
+  off = align_up(off + es * acc_vec, 256);
+  plan->off_invs = off;
+  off = align_up(off + es * acc_vec, 256);
+  plan->off_scal = off;
+  off = align_up(off + 8 * static_cast<size_t>(n_pixels), 256);
+  plan->off_state = off;
+  off = align_up(off + sizeof(SolveState) * n_pixels, 256);
+  plan->off_pool = off;
+  off = align_up(off + es * static_cast<size_t>(acc_pool), 256);
+  plan->total_bytes = off;
+  plan->ws = nullptr;
+  plan->ws_bytes = 0;
+  *plan_out = plan;
+  return DTM_OK;
+}
+
+void dtm_plan_destroy(dtm_plan* plan) { delete plan; }
+
+size_t dtm_plan_workspace_bytes(const dtm_plan* plan) { return plan ? plan->total_bytes : 0; }
+int64_t dtm_plan_pi_elems(const dtm_plan* plan) { return plan ? plan->pi_elems : -1; }
+int64_t dtm_plan_matrix_elems(const dtm_plan* plan) { return plan ? plan->mat_elems : -1; }
+
+int dtm_plan_offsets(const dtm_plan* plan, int64_t* pi_offsets, int64_t* mat_offsets) {
+  if (!plan) return DTM_EINVAL;
+  const int32_t n = plan->n_pixels;
+  std::vector<int64_t> pi(n + 1), mat(n + 1);
+  for (const PixelMeta& m : plan->meta) {
+    pi[m.index] = m.pi_off;
+    mat[m.index] = m.out_off;
+  }
+  pi[n] = plan->pi_elems;
+  mat[n] = plan->mat_elems;
+  if (pi_offsets) std::memcpy(pi_offsets, pi.data(), sizeof(int64_t) * (n + 1));
+  if (mat_offsets) std::memcpy(mat_offsets, mat.data(), sizeof(int64_t) * (n + 1));
+  return DTM_OK;
+}
+
+int dtm_plan_tiles(const dtm_plan* plan, dtm_tile_config* tiles_out) {
+  if (!plan || !tiles_out) return DTM_EINVAL;
+  *tiles_out = plan->tiles;
+  return DTM_OK;
+}
+
+}  // extern "C"

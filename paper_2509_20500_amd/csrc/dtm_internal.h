@@ -1,0 +1,118 @@
+// Internal types shared by the host library and the kernels.  Plain C++,
+// no HIP dependency, so the host-only translation unit builds with g++.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "dtm.h"
+
+namespace dtm {
+
+// Per-pixel metadata resident in device memory (batched path).  Offsets are
+// in elements of the plan's dtype.
+struct PixelMeta {
+  double t_r;     // period
+  double tau;     // pulse centre
+  double sigma;   // pulse width
+  double S;       // signal photons / period
+  double B;       // background photons / period
+  int32_t n;      // bins
+  int32_t l;      // dead-time shift in bins (Theorem 2)
+  int32_t ld;     // row stride of the pixel's matrix (n rounded up to 16 bytes)
+  int32_t index;  // position of the pixel in the caller's arrays
+  int64_t pi_off;   // offset of pi / x0 in the packed vectors (sum of n)
+  int64_t vec_off;  // offset of per-pixel vectors in the workspace (sum of ld)
+  int64_t mat_off;  // offset of the pixel's matrix in the matrix pool (sum of n*ld)
+  int64_t out_off;  // offset of the pixel's matrix in a caller's packed output (sum of n*n)
+};
+static_assert(sizeof(PixelMeta) == 88, "PixelMeta layout");
+
+// Solver options as the kernels see them.
+struct KOpts {
+  double tol;
+  double safety;
+  int32_t max_iter;
+  int32_t stop_rule;
+  int32_t final_check;
+  int32_t pad;
+};
+
+// Per-pixel iteration state of the single-pixel (multi-launch) solver.
+struct SolveState {
+  double c1, c2, c3;   // last three changes (c1 newest)
+  double rho;          // |lambda_2| estimate
+  double resid;        // float64 residual of the last check sweep
+  double sum_y;        // sum of the last product (diagnostic)
+  int32_t iter;        // sweeps done
+  int32_t check_next;  // next sweep accumulates in float64 and yields the residual
+  int32_t done;        // 1 once finished (converged or out of sweeps)
+  int32_t status;      // DTM_OK / DTM_ENOTCONV
+  int32_t flags;       // DTM_INFO_*
+  int32_t warm;        // started from a caller's vector
+  int32_t iter_offset; // sweeps done before the last restart
+  int32_t pad;
+};
+static_assert(sizeof(SolveState) == 80, "SolveState layout");
+
+// Shared host logic (dtm_host.cpp).
+int validate_scene(const dtm_scene& s, dtm_dtype dt);
+int shift_bins(const dtm_scene& s, int32_t* l);
+int fill_opts(const dtm_solve_opts* opt, KOpts* k, int32_t* check_every);
+inline int32_t padded_ld(int32_t n, dtm_dtype dt) {
+  const int32_t vec = dt == DTM_F32 ? 4 : 2;  // 16 bytes
+  return (n + vec - 1) / vec * vec;
+}
+inline size_t dtype_size(dtm_dtype dt) { return dt == DTM_F32 ? 4 : 8; }
+inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Workspace layout of the single-pixel entry points (byte offsets).  The
+// band count caps the float64 partial sums at 256 rows of length ld.
+struct SingleLayout {
+  int32_t ld, bands, band_rows;
+  size_t off_colf, off_invs, off_x, off_scal, off_state, off_part, total;
+};
+inline SingleLayout single_layout(int32_t n, dtm_dtype dt) {
+  SingleLayout L;
+  L.ld = padded_ld(n, dt);
+  const int32_t want = (n + 63) / 64;
+  L.bands = want < 256 ? want : 256;
+  L.band_rows = (n + L.bands - 1) / L.bands;
+  L.bands = (n + L.band_rows - 1) / L.band_rows;
+  const size_t es = dtype_size(dt);
+  size_t off = 0;
+  L.off_colf = off; off = align256(off + es * L.ld);
+  L.off_invs = off; off = align256(off + es * L.ld);
+  L.off_x = off;    off = align256(off + es * L.ld);
+  L.off_scal = off; off = align256(off + 64);
+  L.off_state = off; off = align256(off + sizeof(SolveState));
+  L.off_part = off; off = align256(off + 8 * static_cast<size_t>(L.bands) * L.ld);
+  L.total = off;
+  return L;
+}
+
+}  // namespace dtm
+
+#include <vector>
+
+// The host side of a batched plan.  Pixels are stored in launch order
+// (descending n, so the largest pixels start first); meta[i].index maps back
+// to the caller's order.
+struct dtm_plan {
+  dtm_dtype dt;
+  dtm::KOpts kopts;
+  int32_t check_every;
+  dtm_tile_config tiles;
+  std::vector<dtm::PixelMeta> meta;
+  int32_t n_pixels;
+  int32_t max_n;
+  int32_t max_ld;
+  int64_t pi_elems;    // sum n
+  int64_t mat_elems;   // sum n*n
+  int64_t pool_elems;  // sum n*ld
+  int64_t vec_elems;   // sum ld
+  // workspace layout, byte offsets
+  size_t off_meta, off_pool, off_colf, off_invs, off_scal, off_state, total_bytes;
+  void* ws;            // bound workspace (device), or nullptr
+  size_t ws_bytes;
+};

@@ -1,0 +1,1023 @@
+// HIP kernels for gfx950 and the C-ABI entry points that launch them.
+//
+// Matrix element (Section 3.4, Eq. Eij_ours with the row permutation J_l):
+//   P~[i, j] = lambda_j exp(-Lambda [k > j] - F_j + F_k) / R_k,  k = (i + l) mod n
+//            = g_j w_kj / S_k,   g_j = lambda_j exp(-F_j),  w_kj = exp(-Lambda) if j < k else 1,
+// where S_k = sum_j g_j w_kj is the row sum of the base matrix with its common
+// row factor exp(F_k) cancelled.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "dtm_device.hpp"
+#include "dtm_internal.h"
+
+namespace dtm {
+
+// ============================================================================
+// Kernels shared by the single-pixel and the batched entry points.  A launch
+// covers `metas[0 .. gridDim.y)` (device array) or the single pixel `one`
+// when metas is null.
+// ============================================================================
+
+template <typename V>
+__device__ inline V zero_vec() {
+  V v;
+#pragma unroll
+  for (int e = 0; e < static_cast<int>(sizeof(V) / sizeof(v[0])); ++e) v[e] = 0;
+  return v;
+}
+
+__device__ inline PixelMeta load_meta(const PixelMeta* metas, const PixelMeta& one, int p) {
+  return metas ? metas[p] : one;
+}
+
+// Bin tables: one block per pixel.  g -> colf[vec_off ...], c = exp(-Lambda)
+// -> scal[p]; lambda and F to the caller's buffers when given.
+template <typename T, int BT>
+__global__ __launch_bounds__(BT) void k_tables(const PixelMeta* metas, PixelMeta one, T* colf,
+                                               double* scal, T* lam_out, double* F_out) {
+  __shared__ double red[2 * BT / kWave];
+  const PixelMeta m = load_meta(metas, one, blockIdx.x);
+  const double Lam = pixel_tables<T, BT>(m, colf + m.vec_off, lam_out, F_out, red);
+  if (threadIdx.x == 0) scal[blockIdx.x] = exp(-Lam);
+}
+
+// Row sums of the base matrix: one wavefront per row k; writes 1 / S_k.
+template <typename T, int BT>
+__global__ __launch_bounds__(BT) void k_rowsums(const PixelMeta* metas, PixelMeta one,
+                                                const T* colf, const double* scal, T* invs) {
+  const PixelMeta m = load_meta(metas, one, blockIdx.y);
+  const int k = blockIdx.x * (BT / kWave) + threadIdx.x / kWave;
+  if (k >= m.n) return;
+  const T c = static_cast<T>(scal[blockIdx.y]);
+  const double s = wave_row_sum<T>(colf + m.vec_off, m.n, k, c);
+  if ((threadIdx.x % kWave) == 0) invs[m.vec_off + k] = static_cast<T>(1.0 / s);
+}
+
+// Writes rows of the transition matrix, one wavefront per row, lanes over
+// columns in 16-byte vectors.  shifted: row i is built from base row
+// (i + l) mod n (Theorem 2); otherwise from row i.  Output element (i, j) of
+// pixel p is at out + base + i * ld + j with base/ld either the padded pool
+// layout (packed = 0) or the caller's packed layout (packed = 1, ld = n).
+template <typename T, int BT, int ROWS_PER_WAVE>
+__global__ __launch_bounds__(BT) void k_build(const PixelMeta* metas, PixelMeta one, const T* colf,
+                                              const double* scal, const T* invs, T* out,
+                                              int64_t out_ld_single, int shifted, int packed) {
+  using V = typename Vec<T>::type;
+  constexpr int VN = Vec<T>::n;
+  const PixelMeta m = load_meta(metas, one, blockIdx.y);
+  const int n = m.n;
+  const int64_t ld = metas ? (packed ? m.n : m.ld) : out_ld_single;
+  const int64_t base = metas ? (packed ? m.out_off : m.mat_off) : 0;
+  const T c = static_cast<T>(scal[blockIdx.y]);
+  const T* g = colf + m.vec_off;
+  const int lane = threadIdx.x % kWave;
+  const int wave = blockIdx.x * (BT / kWave) + threadIdx.x / kWave;
+  const bool vec_ok = (ld % VN == 0) && (base % VN == 0) &&
+                      ((reinterpret_cast<uintptr_t>(out) % 16) == 0);
+  const bool pool_layout = metas && !packed;  // rows padded to ld, padding owned by the library
+  for (int r = 0; r < ROWS_PER_WAVE; ++r) {
+    const int i = wave * ROWS_PER_WAVE + r;
+    if (i >= n) return;
+    int k = i;
+    if (shifted) {
+      k = i + m.l;
+      if (k >= n) k -= n;
+    }
+    const T s = invs[m.vec_off + k];
+    T* row = out + base + static_cast<int64_t>(i) * ld;
+    if (vec_ok) {
+      for (int j0 = lane * VN; j0 < n; j0 += kWave * VN) {
+        const V gv = *reinterpret_cast<const V*>(g + j0);  // g is zero-padded to ld
+        V v;
+#pragma unroll
+        for (int e = 0; e < VN; ++e) v[e] = gv[e] * ((j0 + e) < k ? c : T(1)) * s;
+        if (j0 + VN <= n || pool_layout) {
+          *reinterpret_cast<V*>(row + j0) = v;
+        } else {
+#pragma unroll
+          for (int e = 0; e < VN; ++e)
+            if (j0 + e < n) row[j0 + e] = v[e];
+        }
+      }
+    } else {
+      for (int j = lane; j < n; j += kWave) row[j] = g[j] * (j < k ? c : T(1)) * s;
+    }
+  }
+}
+
+// Dead time as a row permutation (Theorem 2): dst[i, :] = src[(i + l) mod n, :].
+template <typename T, int BT, int ROWS_PER_WAVE>
+__global__ __launch_bounds__(BT) void k_shift(const PixelMeta* metas, PixelMeta one, const T* src,
+                                              T* dst, int64_t ld_single) {
+  using V = typename Vec<T>::type;
+  constexpr int VN = Vec<T>::n;
+  const PixelMeta m = load_meta(metas, one, blockIdx.y);
+  const int n = m.n;
+  const int64_t ld = metas ? m.n : ld_single;
+  const int64_t base = metas ? m.out_off : 0;
+  const int lane = threadIdx.x % kWave;
+  const int wave = blockIdx.x * (BT / kWave) + threadIdx.x / kWave;
+  const bool vec_ok = (ld % VN == 0) && (base % VN == 0) &&
+                      ((reinterpret_cast<uintptr_t>(src) % 16) == 0) &&
+                      ((reinterpret_cast<uintptr_t>(dst) % 16) == 0);
+  for (int r = 0; r < ROWS_PER_WAVE; ++r) {
+    const int i = wave * ROWS_PER_WAVE + r;
+    if (i >= n) return;
+    int k = i + m.l;
+    if (k >= n) k -= n;
+    const T* a = src + base + static_cast<int64_t>(k) * ld;
+    T* b = dst + base + static_cast<int64_t>(i) * ld;
+    if (vec_ok) {
+      const int nv = n / VN;
+      for (int q = lane; q < nv; q += kWave)
+        reinterpret_cast<V*>(b)[q] = reinterpret_cast<const V*>(a)[q];
+      for (int j = nv * VN + lane; j < n; j += kWave) b[j] = a[j];
+    } else {
+      for (int j = lane; j < n; j += kWave) b[j] = a[j];
+    }
+  }
+}
+
+// ============================================================================
+// Stop rule (Section 4: the error of power iteration decays like |lambda_2|^t;
+// rho is estimated from successive L1 changes).  All threads of a block run
+// it on identical inputs and reach identical decisions.
+// ============================================================================
+
+__device__ inline double estimate_rho(double c1, double c2, double c3, int t) {
+  double rho;
+  if (t <= 1 || !(c2 > 0.0)) {
+    rho = (t <= 1) ? 0.999 : 0.0;
+  } else {
+    rho = c1 / c2;
+    if (t >= 3 && c3 > 0.0) rho = fmax(rho, sqrt(c1 / c3));
+  }
+  return fmin(fmax(rho, 0.0), 0.999);
+}
+
+struct StopState {
+  double c1, c2, c3, rho, resid;
+  int iter;        // sweeps since (re)start
+  int total_iter;  // all sweeps
+  int check_next;
+  int done;
+  int status;
+  int flags;
+  int warm;
+};
+
+// Updates the state after a sweep that produced `change` (and, for a check
+// sweep, the float64 residual `resid` of its input).  Returns true when the
+// caller should restart from the uniform vector.
+__device__ inline bool stop_update(StopState& s, const KOpts& o, double change, double resid,
+                                   bool was_check) {
+  s.iter += 1;
+  s.total_iter += 1;
+  s.c3 = s.c2;
+  s.c2 = s.c1;
+  s.c1 = change;
+  s.rho = estimate_rho(s.c1, s.c2, s.c3, s.iter);
+  const double gain = s.rho / (1.0 - s.rho);
+  if (was_check) {
+    s.resid = resid;
+    s.flags |= DTM_INFO_CHECKED;
+    const bool ok = (o.stop_rule == DTM_STOP_CHANGE) ? (change < o.tol) : (resid * gain <= o.tol);
+    if (ok) {
+      s.done = 1;
+      s.status = DTM_OK;
+      return false;
+    }
+    s.check_next = 0;
+  } else {
+    s.resid = resid;
+    const bool fire = (o.stop_rule == DTM_STOP_CHANGE)
+                          ? (change < o.tol)
+                          : (change == 0.0 || (s.iter >= 2 && change * gain <= o.safety * o.tol));
+    if (fire) {
+      if (o.final_check) {
+        s.check_next = 1;
+      } else {
+        s.done = 1;
+        s.status = DTM_OK;
+        return false;
+      }
+    }
+  }
+  if (s.iter >= o.max_iter) {
+    if (s.warm && !(s.flags & DTM_INFO_RESTARTED)) {
+      s.flags |= DTM_INFO_RESTARTED;
+      s.iter = 0;
+      s.c1 = s.c2 = s.c3 = 0.0;
+      s.check_next = 0;
+      return true;
+    }
+    s.done = 1;
+    s.status = DTM_ENOTCONV;
+  }
+  return false;
+}
+
+// ============================================================================
+// Batched fused solver: one block per pixel does the bin tables, the row
+// sums, the shifted build fused with the first power-iteration sweep, the
+// remaining sweeps, the float64 check sweep and the stop rule.  Thread t owns
+// columns (t + BT * q) * VN .. + VN - 1 for q < CPT in every row, so each
+// row is one coalesced pass of the block and no cross-thread reduction of
+// x P~ is needed.
+// ============================================================================
+
+template <typename T, int BT, int CPT, int U>
+__global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict__ metas,
+                                                    T* __restrict__ pool,
+                                                    const T* __restrict__ x0_packed,
+                                                    T* __restrict__ pi_packed,
+                                                    dtm_solve_info* __restrict__ infos,
+                                                    KOpts o, int lds_ld) {
+  using V = typename Vec<T>::type;
+  constexpr int VN = Vec<T>::n;
+  constexpr int UE = (U * CPT <= 8) ? U : (8 / CPT > 0 ? 8 / CPT : 1);
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* g = reinterpret_cast<T*>(smem);
+  T* xs = g + lds_ld;
+  T* invs = xs + lds_ld;
+  double* red = reinterpret_cast<double*>(invs + lds_ld);
+
+  const PixelMeta m = metas[blockIdx.x];
+  const int n = m.n;
+  const int64_t ld = m.ld;
+  const int tid = threadIdx.x;
+  T* mat = pool + m.mat_off;
+
+  // ---- a1: bin tables -----------------------------------------------------
+  const double Lam = pixel_tables<T, BT>(m, g, nullptr, nullptr, red);
+  const T c = static_cast<T>(exp(-Lam));
+  __syncthreads();
+
+  // ---- a2: row sums of the base matrix, one wavefront per row -----------
+  for (int k = tid / kWave; k < n; k += BT / kWave) {
+    const double s = wave_row_sum<T>(g, n, k, c);
+    if ((tid % kWave) == 0) invs[k] = static_cast<T>(1.0 / s);
+  }
+
+  // ---- start vector: caller's (validated) or uniform ---------------------
+  StopState st;
+  st.c1 = st.c2 = st.c3 = 0.0;
+  st.rho = 0.999;
+  st.resid = 0.0;
+  st.iter = st.total_iter = 0;
+  st.check_next = 0;
+  st.done = 0;
+  st.status = DTM_OK;
+  st.flags = 0;
+  st.warm = 0;
+  if (x0_packed) {
+    double sum = 0.0, bad = 0.0;
+    for (int j = tid; j < n; j += BT) {
+      const double v = static_cast<double>(x0_packed[m.pi_off + j]);
+      if (!(v >= 0.0) || !isfinite(v)) bad += 1.0;
+      else sum += v;
+    }
+    block_sum2<BT>(sum, bad, red);
+    if (bad == 0.0 && sum > 0.0 && isfinite(sum)) {
+      st.warm = 1;
+      for (int j = tid; j < n; j += BT)
+        xs[j] = static_cast<T>(static_cast<double>(x0_packed[m.pi_off + j]) / sum);
+    } else {
+      st.flags |= DTM_INFO_WARM_REJECTED;
+      for (int j = tid; j < n; j += BT) xs[j] = static_cast<T>(1.0 / n);
+    }
+  } else {
+    for (int j = tid; j < n; j += BT) xs[j] = static_cast<T>(1.0 / n);
+  }
+  __syncthreads();
+
+  // This thread's columns and their g values.
+  T gr[CPT][VN];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int j0 = (tid + BT * q) * VN;
+#pragma unroll
+    for (int e = 0; e < VN; ++e) gr[q][e] = (j0 < ld) ? g[j0 + e] : T(0);
+  }
+
+  T acc[CPT][VN], cmp[CPT][VN];
+  double accd[CPT][VN];
+
+  // ---- a2+a3 fused with the first sweep: write row i from base row
+  //      k = (i + l) mod n and accumulate x_i P~[i, :] ----------------------
+#pragma unroll
+  for (int q = 0; q < CPT; ++q)
+#pragma unroll
+    for (int e = 0; e < VN; ++e) acc[q][e] = cmp[q][e] = T(0);
+  for (int i = 0; i < n; ++i) {
+    int k = i + m.l;
+    if (k >= n) k -= n;
+    const T s = invs[k];
+    const T xi = xs[i];
+    T* row = mat + static_cast<int64_t>(i) * ld;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int j0 = (tid + BT * q) * VN;
+      if (j0 < n) {
+        V v;
+#pragma unroll
+        for (int e = 0; e < VN; ++e) {
+          v[e] = gr[q][e] * ((j0 + e) < k ? c : T(1)) * s;
+          comp_add(acc[q][e], cmp[q][e], xi * v[e]);
+        }
+        *reinterpret_cast<V*>(row + j0) = v;
+      }
+    }
+  }
+  bool have_check = false;  // the accumulators hold a float64 check sweep
+
+  for (;;) {
+    // ---- reduce: sum of y = x P~, residual ||y - x||_1, then the new
+    //      iterate y / sum(y) and its change ------------------------------
+    double y[CPT][VN];
+    double sy = 0.0, rs = 0.0;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int j0 = (tid + BT * q) * VN;
+#pragma unroll
+      for (int e = 0; e < VN; ++e) {
+        y[q][e] = have_check ? accd[q][e]
+                             : static_cast<double>(acc[q][e]) - static_cast<double>(cmp[q][e]);
+        if (j0 + e < n) {
+          sy += y[q][e];
+          rs += fabs(y[q][e] - static_cast<double>(xs[j0 + e]));
+        }
+      }
+    }
+    block_sum2<BT>(sy, rs, red);
+    const double inv = 1.0 / sy;
+    T xn[CPT][VN];
+    double ch = 0.0;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int j0 = (tid + BT * q) * VN;
+#pragma unroll
+      for (int e = 0; e < VN; ++e) {
+        xn[q][e] = static_cast<T>(y[q][e] * inv);
+        if (j0 + e < n) ch += fabs(static_cast<double>(xn[q][e]) - static_cast<double>(xs[j0 + e]));
+      }
+    }
+    ch = block_sum<BT>(ch, red);  // its barriers also end every read of xs
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int j0 = (tid + BT * q) * VN;
+#pragma unroll
+      for (int e = 0; e < VN; ++e)
+        if (j0 + e < n) xs[j0 + e] = xn[q][e];
+    }
+    const bool restart = stop_update(st, o, ch, rs, have_check);
+    if (restart) {
+      for (int j = tid; j < n; j += BT) xs[j] = static_cast<T>(1.0 / n);
+    }
+    __syncthreads();
+    if (st.done) break;
+
+    // ---- a4: next sweep, U rows in flight per thread -------------------
+    have_check = st.check_next != 0;
+    if (!have_check) {
+#pragma unroll
+      for (int q = 0; q < CPT; ++q)
+#pragma unroll
+        for (int e = 0; e < VN; ++e) acc[q][e] = cmp[q][e] = T(0);
+      for (int i0 = 0; i0 < n; i0 += UE) {
+        V v[UE][CPT];
+#pragma unroll
+        for (int u = 0; u < UE; ++u) {
+          const int i = i0 + u;
+#pragma unroll
+          for (int q = 0; q < CPT; ++q) {
+            const int j0 = (tid + BT * q) * VN;
+            if (i < n && j0 < n)
+              v[u][q] = *reinterpret_cast<const V*>(mat + static_cast<int64_t>(i) * ld + j0);
+            else
+              v[u][q] = zero_vec<V>();
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UE; ++u) {
+          const T xi = (i0 + u < n) ? xs[i0 + u] : T(0);
+#pragma unroll
+          for (int q = 0; q < CPT; ++q)
+#pragma unroll
+            for (int e = 0; e < VN; ++e) comp_add(acc[q][e], cmp[q][e], xi * v[u][q][e]);
+        }
+      }
+    } else {
+      // a5: float64 check sweep (exact products, float64 sums).
+#pragma unroll
+      for (int q = 0; q < CPT; ++q)
+#pragma unroll
+        for (int e = 0; e < VN; ++e) accd[q][e] = 0.0;
+      for (int i0 = 0; i0 < n; i0 += UE) {
+        V v[UE][CPT];
+#pragma unroll
+        for (int u = 0; u < UE; ++u) {
+          const int i = i0 + u;
+#pragma unroll
+          for (int q = 0; q < CPT; ++q) {
+            const int j0 = (tid + BT * q) * VN;
+            if (i < n && j0 < n)
+              v[u][q] = *reinterpret_cast<const V*>(mat + static_cast<int64_t>(i) * ld + j0);
+            else
+              v[u][q] = zero_vec<V>();
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UE; ++u) {
+          const double xi = (i0 + u < n) ? static_cast<double>(xs[i0 + u]) : 0.0;
+#pragma unroll
+          for (int q = 0; q < CPT; ++q)
+#pragma unroll
+            for (int e = 0; e < VN; ++e) accd[q][e] += xi * static_cast<double>(v[u][q][e]);
+        }
+      }
+    }
+  }
+
+  // ---- outputs --------------------------------------------------------------
+  for (int j = tid; j < n; j += BT) pi_packed[m.pi_off + j] = xs[j];
+  if (tid == 0) {
+    dtm_solve_info info;
+    info.iterations = st.total_iter;
+    info.status = st.status;
+    info.flags = st.flags;
+    info.reserved = 0;
+    info.change_l1 = st.c1;
+    info.residual_l1 = st.resid;
+    info.rho_hat = st.rho;
+    infos[m.index] = info;
+  }
+}
+
+// ============================================================================
+// Single-pixel power iteration on a caller's matrix (any row-stochastic P,
+// any ld): a band kernel writes float64 partial sums of x P over row bands,
+// a one-block combine kernel sums them in band order and applies the stop
+// rule.  The host re-launches the pair and polls the state.
+// ============================================================================
+
+template <typename T, int BT>
+__global__ __launch_bounds__(BT) void k_solver_init(const T* x0, T* x, SolveState* state, int n) {
+  __shared__ double red[2 * BT / kWave];
+  double sum = 0.0, bad = 0.0;
+  if (x0) {
+    for (int j = threadIdx.x; j < n; j += BT) {
+      const double v = static_cast<double>(x0[j]);
+      if (!(v >= 0.0) || !isfinite(v)) bad += 1.0;
+      else sum += v;
+    }
+  }
+  block_sum2<BT>(sum, bad, red);
+  const bool warm = x0 && bad == 0.0 && sum > 0.0 && isfinite(sum);
+  for (int j = threadIdx.x; j < n; j += BT)
+    x[j] = warm ? static_cast<T>(static_cast<double>(x0[j]) / sum) : static_cast<T>(1.0 / n);
+  if (threadIdx.x == 0) {
+    SolveState s;
+    s.c1 = s.c2 = s.c3 = 0.0;
+    s.rho = 0.999;
+    s.resid = 0.0;
+    s.sum_y = 0.0;
+    s.iter = 0;
+    s.check_next = 0;
+    s.done = 0;
+    s.status = DTM_OK;
+    s.flags = (x0 && !warm) ? DTM_INFO_WARM_REJECTED : 0;
+    s.warm = warm ? 1 : 0;
+    s.iter_offset = 0;
+    s.pad = 0;
+    *state = s;
+  }
+}
+
+// Partial sums part[b][j] = sum_{i in band b} x_i P[i, j] for the column
+// block blockIdx.x (BT * VN columns); float32 is compensated, the check
+// sweep is float64.
+template <typename T, int BT, int VN>
+__global__ __launch_bounds__(BT) void k_sweep_band(const T* __restrict__ P, int n, int64_t ld,
+                                                   const T* __restrict__ x,
+                                                   const SolveState* __restrict__ state,
+                                                   double* __restrict__ part, int64_t part_ld,
+                                                   int band_rows) {
+  if (state->done) return;
+  const bool check = state->check_next != 0;
+  const int band = blockIdx.y;
+  const int i0 = band * band_rows;
+  const int i1 = min(i0 + band_rows, n);
+  const int j0 = (blockIdx.x * BT + threadIdx.x) * VN;
+  if (j0 >= n) return;
+  const int ne = min(VN, n - j0);
+  T acc[VN], cmp[VN];
+  double accd[VN];
+#pragma unroll
+  for (int e = 0; e < VN; ++e) {
+    acc[e] = cmp[e] = T(0);
+    accd[e] = 0.0;
+  }
+  if (VN > 1 && ne == VN) {
+    using V = typename Vec<T>::type;
+    for (int i = i0; i < i1; ++i) {
+      const V v = *reinterpret_cast<const V*>(P + static_cast<int64_t>(i) * ld + j0);
+      const T xi = x[i];
+      if (check) {
+#pragma unroll
+        for (int e = 0; e < VN; ++e) accd[e] += static_cast<double>(xi) * static_cast<double>(v[e]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VN; ++e) comp_add(acc[e], cmp[e], xi * v[e]);
+      }
+    }
+  } else {
+    for (int i = i0; i < i1; ++i) {
+      const T xi = x[i];
+      for (int e = 0; e < ne; ++e) {
+        const T v = P[static_cast<int64_t>(i) * ld + j0 + e];
+        if (check)
+          accd[e] += static_cast<double>(xi) * static_cast<double>(v);
+        else
+          comp_add(acc[e], cmp[e], xi * v);
+      }
+    }
+  }
+  double* out = part + static_cast<int64_t>(band) * part_ld + j0;
+  for (int e = 0; e < ne; ++e)
+    out[e] = check ? accd[e] : static_cast<double>(acc[e]) - static_cast<double>(cmp[e]);
+}
+
+template <typename T, int BT>
+__global__ __launch_bounds__(BT) void k_combine(const double* __restrict__ part, int64_t part_ld,
+                                                int bands, int n, T* __restrict__ x,
+                                                SolveState* __restrict__ state,
+                                                T* __restrict__ pi, KOpts o) {
+  __shared__ double red[2 * BT / kWave];
+  __shared__ int s_flag[2];
+  SolveState s = *state;
+  if (s.done) return;
+  const bool was_check = s.check_next != 0;
+  double sy = 0.0, rs = 0.0;
+  for (int j = threadIdx.x; j < n; j += BT) {
+    double y = 0.0;
+    for (int b = 0; b < bands; ++b) y += part[static_cast<int64_t>(b) * part_ld + j];
+    sy += y;
+    rs += fabs(y - static_cast<double>(x[j]));
+  }
+  block_sum2<BT>(sy, rs, red);
+  const double inv = 1.0 / sy;
+  double ch = 0.0;
+  for (int j = threadIdx.x; j < n; j += BT) {
+    double y = 0.0;
+    for (int b = 0; b < bands; ++b) y += part[static_cast<int64_t>(b) * part_ld + j];
+    ch += fabs(static_cast<double>(static_cast<T>(y * inv)) - static_cast<double>(x[j]));
+  }
+  ch = block_sum<BT>(ch, red);
+  for (int j = threadIdx.x; j < n; j += BT) {
+    double y = 0.0;
+    for (int b = 0; b < bands; ++b) y += part[static_cast<int64_t>(b) * part_ld + j];
+    x[j] = static_cast<T>(y * inv);
+  }
+  StopState t;
+  t.c1 = s.c1;
+  t.c2 = s.c2;
+  t.c3 = s.c3;
+  t.rho = s.rho;
+  t.resid = s.resid;
+  t.iter = s.iter;
+  t.total_iter = s.iter + s.iter_offset;
+  t.check_next = s.check_next;
+  t.done = 0;
+  t.status = DTM_OK;
+  t.flags = s.flags;
+  t.warm = s.warm;
+  const bool restart = stop_update(t, o, ch, rs, was_check);
+  __syncthreads();
+  if (restart)
+    for (int j = threadIdx.x; j < n; j += BT) x[j] = static_cast<T>(1.0 / n);
+  if (t.done)
+    for (int j = threadIdx.x; j < n; j += BT) pi[j] = x[j];
+  if (threadIdx.x == 0) {
+    s.c1 = t.c1;
+    s.c2 = t.c2;
+    s.c3 = t.c3;
+    s.rho = t.rho;
+    s.resid = t.resid;
+    s.sum_y = sy;
+    s.iter = t.iter;
+    s.iter_offset = t.total_iter - t.iter;
+    s.check_next = t.check_next;
+    s.done = t.done;
+    s.status = t.status;
+    s.flags = t.flags;
+    *state = s;
+  }
+  (void)s_flag;
+}
+
+}  // namespace dtm
+
+// ============================================================================
+// Host side
+// ============================================================================
+
+using namespace dtm;
+
+namespace {
+
+constexpr int kBT = 256;
+constexpr int kRowsPerWave = 4;
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? DTM_OK : DTM_EHIP; }
+int last_launch() { return hip_ok(hipGetLastError()); }
+
+PixelMeta single_meta(const dtm_scene& s, dtm_dtype dt) {
+  PixelMeta m;
+  m.t_r = s.period_ns;
+  m.tau = s.pulse_center_ns;
+  m.sigma = s.pulse_sigma_ns;
+  m.S = s.signal_flux;
+  m.B = s.background_flux;
+  m.n = s.n_bins;
+  shift_bins(s, &m.l);
+  m.ld = padded_ld(s.n_bins, dt);
+  m.index = 0;
+  m.pi_off = 0;
+  m.vec_off = 0;
+  m.mat_off = 0;
+  m.out_off = 0;
+  return m;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
+}
+
+template <typename T>
+int launch_tables(const PixelMeta* metas, const PixelMeta& one, int np, T* colf, double* scal,
+                  T* lam, double* F, hipStream_t st) {
+  hipLaunchKernelGGL((k_tables<T, kBT>), dim3(np), dim3(kBT), 0, st, metas, one, colf, scal, lam, F);
+  return last_launch();
+}
+
+template <typename T>
+int launch_rowsums(const PixelMeta* metas, const PixelMeta& one, int np, int max_n, const T* colf,
+                   const double* scal, T* invs, hipStream_t st) {
+  const int rows_per_block = kBT / kWave;
+  dim3 grid((max_n + rows_per_block - 1) / rows_per_block, np);
+  hipLaunchKernelGGL((k_rowsums<T, kBT>), grid, dim3(kBT), 0, st, metas, one, colf, scal, invs);
+  return last_launch();
+}
+
+template <typename T>
+int launch_build(const PixelMeta* metas, const PixelMeta& one, int np, int max_n, const T* colf,
+                 const double* scal, const T* invs, T* out, int64_t ld, int shifted, int packed,
+                 hipStream_t st) {
+  const int rows_per_block = (kBT / kWave) * kRowsPerWave;
+  dim3 grid((max_n + rows_per_block - 1) / rows_per_block, np);
+  hipLaunchKernelGGL((k_build<T, kBT, kRowsPerWave>), grid, dim3(kBT), 0, st, metas, one, colf,
+                     scal, invs, out, ld, shifted, packed);
+  return last_launch();
+}
+
+template <typename T>
+int launch_shift(const PixelMeta* metas, const PixelMeta& one, int np, int max_n, const T* src,
+                 T* dst, int64_t ld, hipStream_t st) {
+  const int rows_per_block = (kBT / kWave) * kRowsPerWave;
+  dim3 grid((max_n + rows_per_block - 1) / rows_per_block, np);
+  hipLaunchKernelGGL((k_shift<T, kBT, kRowsPerWave>), grid, dim3(kBT), 0, st, metas, one, src, dst, ld);
+  return last_launch();
+}
+
+// Single pixel: tables + row sums into the workspace.
+template <typename T>
+int single_prepare(const dtm_scene& s, dtm_dtype dt, void* ws, size_t ws_bytes, T* lam, double* F,
+                   PixelMeta* m_out, SingleLayout* L_out, hipStream_t st) {
+  const PixelMeta m = single_meta(s, dt);
+  const SingleLayout L = single_layout(s.n_bins, dt);
+  if (!ws) return DTM_EINVAL;
+  if (ws_bytes < L.total) return DTM_ENOSPACE;
+  char* w = static_cast<char*>(ws);
+  T* colf = reinterpret_cast<T*>(w + L.off_colf);
+  T* invs = reinterpret_cast<T*>(w + L.off_invs);
+  double* scal = reinterpret_cast<double*>(w + L.off_scal);
+  int rc = launch_tables<T>(nullptr, m, 1, colf, scal, lam, F, st);
+  if (rc) return rc;
+  rc = launch_rowsums<T>(nullptr, m, 1, m.n, colf, scal, invs, st);
+  *m_out = m;
+  *L_out = L;
+  return rc;
+}
+
+template <typename T>
+int single_build(const dtm_scene* s, dtm_dtype dt, void* P, int64_t ld, void* ws, size_t ws_bytes,
+                 int shifted, hipStream_t st) {
+  PixelMeta m;
+  SingleLayout L;
+  int rc = single_prepare<T>(*s, dt, ws, ws_bytes, nullptr, nullptr, &m, &L, st);
+  if (rc) return rc;
+  char* w = static_cast<char*>(ws);
+  return launch_build<T>(nullptr, m, 1, m.n, reinterpret_cast<T*>(w + L.off_colf),
+                         reinterpret_cast<double*>(w + L.off_scal),
+                         reinterpret_cast<T*>(w + L.off_invs), static_cast<T*>(P), ld, shifted, 0, st);
+}
+
+template <typename T>
+int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_every, const T* x0,
+                 T* pi, void* ws, dtm_solve_info* info, hipStream_t st, dtm_dtype dt) {
+  const SingleLayout L = single_layout(n, dt);
+  char* w = static_cast<char*>(ws);
+  T* x = reinterpret_cast<T*>(w + L.off_x);
+  SolveState* state = reinterpret_cast<SolveState*>(w + L.off_state);
+  double* part = reinterpret_cast<double*>(w + L.off_part);
+  constexpr int VN = Vec<T>::n;
+  const bool vec = (ld % VN == 0) && (reinterpret_cast<uintptr_t>(P) % 16 == 0);
+  hipLaunchKernelGGL((k_solver_init<T, kBT>), dim3(1), dim3(kBT), 0, st, x0, x, state, n);
+  int rc = last_launch();
+  if (rc) return rc;
+  const int vn = vec ? VN : 1;
+  const int cols_per_block = kBT * vn;
+  dim3 grid((n + cols_per_block - 1) / cols_per_block, L.bands);
+  SolveState hs;
+  const int max_sweeps = 2 * ko.max_iter + 2;
+  int launched = 0;
+  for (;;) {
+    for (int r = 0; r < check_every && launched < max_sweeps; ++r, ++launched) {
+      if (vec)
+        hipLaunchKernelGGL((k_sweep_band<T, kBT, VN>), grid, dim3(kBT), 0, st, P, n, ld, x, state,
+                           part, static_cast<int64_t>(L.ld), L.band_rows);
+      else
+        hipLaunchKernelGGL((k_sweep_band<T, kBT, 1>), grid, dim3(kBT), 0, st, P, n, ld, x, state,
+                           part, static_cast<int64_t>(L.ld), L.band_rows);
+      hipLaunchKernelGGL((k_combine<T, kBT>), dim3(1), dim3(kBT), 0, st, part,
+                         static_cast<int64_t>(L.ld), L.bands, n, x, state, pi, ko);
+    }
+    rc = last_launch();
+    if (rc) return rc;
+    if (hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess) return DTM_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return DTM_EHIP;
+    if (hs.done || launched >= max_sweeps) break;
+  }
+  if (!hs.done) {  // cannot happen with the stop rule's own max_iter; be explicit anyway
+    hs.status = DTM_ENOTCONV;
+    if (hipMemcpyAsync(pi, x, sizeof(T) * n, hipMemcpyDeviceToDevice, st) != hipSuccess) return DTM_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return DTM_EHIP;
+  }
+  if (info) {
+    info->iterations = hs.iter + hs.iter_offset;
+    info->status = hs.status;
+    info->flags = hs.flags;
+    info->reserved = 0;
+    info->change_l1 = hs.c1;
+    info->residual_l1 = hs.resid;
+    info->rho_hat = hs.rho;
+  }
+  return DTM_OK;
+}
+
+// Fused batched solve: kernel instance by (dtype, block, columns per thread).
+template <typename T, int BT, int CPT>
+int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, int count, T* pool,
+                     const T* x0, T* pi, dtm_solve_info* infos, int lds_ld, hipStream_t st) {
+  const size_t lds = 3 * sizeof(T) * static_cast<size_t>(lds_ld) + 2 * BT / kWave * sizeof(double);
+  void (*kern)(const PixelMeta*, T*, const T*, T*, dtm_solve_info*, KOpts, int) = nullptr;
+  switch (unroll) {
+    case 2: kern = k_solve_fused<T, BT, CPT, 2>; break;
+    case 4: kern = k_solve_fused<T, BT, CPT, 4>; break;
+    default: kern = k_solve_fused<T, BT, CPT, 8>; break;
+  }
+  if (lds > 64 * 1024) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            static_cast<int>(lds)) != hipSuccess)
+      return DTM_EHIP;
+  }
+  hipLaunchKernelGGL(kern, dim3(count), dim3(BT), lds, st, metas, pool, x0, pi, infos, plan->kopts, lds_ld);
+  return last_launch();
+}
+
+template <typename T, int BT>
+int launch_fused_bt(const dtm_plan* plan, int cpt, const PixelMeta* metas, int count, T* pool,
+                    const T* x0, T* pi, dtm_solve_info* infos, int lds_ld, hipStream_t st) {
+  const int u = plan->tiles.fused_unroll;
+  switch (cpt) {
+    case 1: return launch_fused_cpt<T, BT, 1>(plan, u, metas, count, pool, x0, pi, infos, lds_ld, st);
+    case 2: return launch_fused_cpt<T, BT, 2>(plan, u, metas, count, pool, x0, pi, infos, lds_ld, st);
+    case 4: return launch_fused_cpt<T, BT, 4>(plan, u, metas, count, pool, x0, pi, infos, lds_ld, st);
+    default: return DTM_ENOTSUP;
+  }
+}
+
+template <typename T>
+int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info* infos,
+                  hipStream_t st) {
+  char* w = static_cast<char*>(plan->ws);
+  const PixelMeta* metas = reinterpret_cast<const PixelMeta*>(w + plan->off_meta);
+  T* pool = reinterpret_cast<T*>(w + plan->off_pool);
+  constexpr int VN = Vec<T>::n;
+  // columns per thread covering the largest pixel; at most 4 chunks of
+  // VN columns per thread (more would spill), so wide pixels take 512 threads
+  int bt = plan->tiles.fused_threads;
+  int cpt = (plan->max_ld + bt * VN - 1) / (bt * VN);
+  if (cpt > 4 && bt == 256) {
+    bt = 512;
+    cpt = (plan->max_ld + bt * VN - 1) / (bt * VN);
+  }
+  cpt = cpt <= 1 ? 1 : cpt <= 2 ? 2 : 4;
+  if (cpt * bt * VN < plan->max_ld) return DTM_ENOTSUP;
+  const int lds_ld = plan->max_ld;
+  const size_t lds = 3 * sizeof(T) * static_cast<size_t>(lds_ld) + 2 * bt / kWave * sizeof(double);
+  if (lds > 160 * 1024) return DTM_ENOTSUP;
+  const T* x0t = static_cast<const T*>(x0);
+  T* pit = static_cast<T*>(pi);
+  if (bt == 512)
+    return launch_fused_bt<T, 512>(plan, cpt, metas, plan->n_pixels, pool, x0t, pit, infos, lds_ld, st);
+  return launch_fused_bt<T, 256>(plan, cpt, metas, plan->n_pixels, pool, x0t, pit, infos, lds_ld, st);
+}
+
+template <typename T>
+int batched_tables_rowsums(const dtm_plan* plan, hipStream_t st) {
+  char* w = static_cast<char*>(plan->ws);
+  const PixelMeta* metas = reinterpret_cast<const PixelMeta*>(w + plan->off_meta);
+  T* colf = reinterpret_cast<T*>(w + plan->off_colf);
+  T* invs = reinterpret_cast<T*>(w + plan->off_invs);
+  double* scal = reinterpret_cast<double*>(w + plan->off_scal);
+  PixelMeta dummy;
+  std::memset(&dummy, 0, sizeof(dummy));
+  int rc = launch_tables<T>(metas, dummy, plan->n_pixels, colf, scal, nullptr, nullptr, st);
+  if (rc) return rc;
+  return launch_rowsums<T>(metas, dummy, plan->n_pixels, plan->max_n, colf, scal, invs, st);
+}
+
+template <typename T>
+int batched_build(const dtm_plan* plan, void* out, int shifted, hipStream_t st) {
+  int rc = batched_tables_rowsums<T>(plan, st);
+  if (rc) return rc;
+  char* w = static_cast<char*>(plan->ws);
+  const PixelMeta* metas = reinterpret_cast<const PixelMeta*>(w + plan->off_meta);
+  PixelMeta dummy;
+  std::memset(&dummy, 0, sizeof(dummy));
+  return launch_build<T>(metas, dummy, plan->n_pixels, plan->max_n,
+                         reinterpret_cast<T*>(w + plan->off_colf),
+                         reinterpret_cast<double*>(w + plan->off_scal),
+                         reinterpret_cast<T*>(w + plan->off_invs), static_cast<T*>(out), 0, shifted,
+                         1, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int dtm_bin_tables(const dtm_scene* s, dtm_dtype dt, void* lambda_dev, double* F_dev,
+                   void* workspace_dev, size_t workspace_bytes, dtm_stream_t stream) {
+  if (!s) return DTM_EINVAL;
+  const int v = validate_scene(*s, dt);
+  if (v) return v;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const PixelMeta m = single_meta(*s, dt);
+  const SingleLayout L = single_layout(s->n_bins, dt);
+  if (!workspace_dev) return DTM_EINVAL;
+  if (workspace_bytes < L.total) return DTM_ENOSPACE;
+  char* w = static_cast<char*>(workspace_dev);
+  double* scal = reinterpret_cast<double*>(w + L.off_scal);
+  if (dt == DTM_F32)
+    return launch_tables<float>(nullptr, m, 1, reinterpret_cast<float*>(w + L.off_colf), scal,
+                                static_cast<float*>(lambda_dev), F_dev, st);
+  return launch_tables<double>(nullptr, m, 1, reinterpret_cast<double*>(w + L.off_colf), scal,
+                               static_cast<double*>(lambda_dev), F_dev, st);
+}
+
+static int check_matrix_args(const dtm_scene* s, dtm_dtype dt, const void* P, int64_t ld) {
+  if (!s || !P) return DTM_EINVAL;
+  const int v = validate_scene(*s, dt);
+  if (v) return v;
+  if (ld < s->n_bins) return DTM_EINVAL;
+  return DTM_OK;
+}
+
+int dtm_build_base(const dtm_scene* s, dtm_dtype dt, void* P_base_dev, int64_t ld,
+                   void* workspace_dev, size_t workspace_bytes, dtm_stream_t stream) {
+  const int v = check_matrix_args(s, dt, P_base_dev, ld);
+  if (v) return v;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dt == DTM_F32) return single_build<float>(s, dt, P_base_dev, ld, workspace_dev, workspace_bytes, 0, st);
+  return single_build<double>(s, dt, P_base_dev, ld, workspace_dev, workspace_bytes, 0, st);
+}
+
+int dtm_build_transition(const dtm_scene* s, dtm_dtype dt, void* P_dev, int64_t ld,
+                         void* workspace_dev, size_t workspace_bytes, dtm_stream_t stream) {
+  const int v = check_matrix_args(s, dt, P_dev, ld);
+  if (v) return v;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dt == DTM_F32) return single_build<float>(s, dt, P_dev, ld, workspace_dev, workspace_bytes, 1, st);
+  return single_build<double>(s, dt, P_dev, ld, workspace_dev, workspace_bytes, 1, st);
+}
+
+int dtm_apply_deadtime_shift(const dtm_scene* s, dtm_dtype dt, const void* P_base_dev, void* P_dev,
+                             int64_t ld, dtm_stream_t stream) {
+  int v = check_matrix_args(s, dt, P_base_dev, ld);
+  if (v) return v;
+  if (!P_dev) return DTM_EINVAL;
+  const size_t bytes = dtype_size(dt) * static_cast<size_t>(ld) * (s->n_bins - 1) +
+                       dtype_size(dt) * s->n_bins;
+  if (overlaps(P_base_dev, bytes, P_dev, bytes)) return DTM_EALIAS;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const PixelMeta m = single_meta(*s, dt);
+  if (dt == DTM_F32)
+    return launch_shift<float>(nullptr, m, 1, m.n, static_cast<const float*>(P_base_dev),
+                               static_cast<float*>(P_dev), ld, st);
+  return launch_shift<double>(nullptr, m, 1, m.n, static_cast<const double*>(P_base_dev),
+                              static_cast<double*>(P_dev), ld, st);
+}
+
+int dtm_stationary_pdf(const void* P_dev, int32_t n, int64_t ld, dtm_dtype dt,
+                       const dtm_solve_opts* opt, const void* x0_dev, void* pi_dev,
+                       void* workspace_dev, size_t workspace_bytes, dtm_solve_info* info_host,
+                       dtm_stream_t stream) {
+  if (!P_dev || !pi_dev || !workspace_dev) return DTM_EINVAL;
+  if (dt != DTM_F32 && dt != DTM_F64) return DTM_EINVAL;
+  if (n < 2 || n > DTM_MAX_BINS || ld < n) return DTM_EINVAL;
+  KOpts ko;
+  int32_t ce = 4;
+  int rc = fill_opts(opt, &ko, &ce);
+  if (rc) return rc;
+  const SingleLayout L = single_layout(n, dt);
+  if (workspace_bytes < L.total) return DTM_ENOSPACE;
+  const size_t es = dtype_size(dt);
+  if (overlaps(pi_dev, es * n, workspace_dev, L.total)) return DTM_EALIAS;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dt == DTM_F32)
+    return single_solve<float>(static_cast<const float*>(P_dev), n, ld, ko, ce,
+                               static_cast<const float*>(x0_dev), static_cast<float*>(pi_dev),
+                               workspace_dev, info_host, st, dt);
+  return single_solve<double>(static_cast<const double*>(P_dev), n, ld, ko, ce,
+                              static_cast<const double*>(x0_dev), static_cast<double*>(pi_dev),
+                              workspace_dev, info_host, st, dt);
+}
+
+int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes, dtm_stream_t stream) {
+  if (!plan || !workspace_dev) return DTM_EINVAL;
+  if (workspace_bytes < plan->total_bytes) return DTM_ENOSPACE;
+  if (reinterpret_cast<uintptr_t>(workspace_dev) % 256 != 0) return DTM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(workspace_dev);
+  if (hipMemcpyAsync(w + plan->off_meta, plan->meta.data(), sizeof(PixelMeta) * plan->meta.size(),
+                     hipMemcpyHostToDevice, st) != hipSuccess)
+    return DTM_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return DTM_EHIP;
+  plan->ws = workspace_dev;
+  plan->ws_bytes = workspace_bytes;
+  return DTM_OK;
+}
+
+int dtm_solve_batched(const dtm_plan* plan, const void* x0_packed_dev, void* pi_packed_dev,
+                      dtm_solve_info* infos_dev, dtm_stream_t stream) {
+  if (!plan || !plan->ws || !pi_packed_dev || !infos_dev) return DTM_EINVAL;
+  const size_t es = dtype_size(plan->dt);
+  if (overlaps(pi_packed_dev, es * plan->pi_elems, plan->ws, plan->total_bytes)) return DTM_EALIAS;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (plan->dt == DTM_F32) return batched_solve<float>(plan, x0_packed_dev, pi_packed_dev, infos_dev, st);
+  return batched_solve<double>(plan, x0_packed_dev, pi_packed_dev, infos_dev, st);
+}
+
+int dtm_build_base_batched(const dtm_plan* plan, void* P_packed_dev, dtm_stream_t stream) {
+  if (!plan || !plan->ws || !P_packed_dev) return DTM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (plan->dt == DTM_F32) return batched_build<float>(plan, P_packed_dev, 0, st);
+  return batched_build<double>(plan, P_packed_dev, 0, st);
+}
+
+int dtm_build_transition_batched(const dtm_plan* plan, void* P_packed_dev, dtm_stream_t stream) {
+  if (!plan || !plan->ws || !P_packed_dev) return DTM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (plan->dt == DTM_F32) return batched_build<float>(plan, P_packed_dev, 1, st);
+  return batched_build<double>(plan, P_packed_dev, 1, st);
+}
+
+int dtm_apply_deadtime_shift_batched(const dtm_plan* plan, const void* P_base_packed_dev,
+                                     void* P_packed_dev, dtm_stream_t stream) {
+  if (!plan || !plan->ws || !P_base_packed_dev || !P_packed_dev) return DTM_EINVAL;
+  const size_t bytes = dtype_size(plan->dt) * static_cast<size_t>(plan->mat_elems);
+  if (overlaps(P_base_packed_dev, bytes, P_packed_dev, bytes)) return DTM_EALIAS;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(plan->ws);
+  const PixelMeta* metas = reinterpret_cast<const PixelMeta*>(w + plan->off_meta);
+  PixelMeta dummy;
+  std::memset(&dummy, 0, sizeof(dummy));
+  if (plan->dt == DTM_F32)
+    return launch_shift<float>(metas, dummy, plan->n_pixels, plan->max_n,
+                               static_cast<const float*>(P_base_packed_dev),
+                               static_cast<float*>(P_packed_dev), 0, st);
+  return launch_shift<double>(metas, dummy, plan->n_pixels, plan->max_n,
+                              static_cast<const double*>(P_base_packed_dev),
+                              static_cast<double*>(P_packed_dev), 0, st);
+}
+
+}  // extern "C"
