@@ -72,7 +72,7 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--pixels", type=int, default=4096)
     ap.add_argument("--check", type=int, default=16, help="pixels compared with the oracle after timing")
-    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--threads", type=int, default=0, help="fused block size (0 = default)")
     ap.add_argument("--unroll", type=int, default=0, help="rows in flight per thread (0 = default)")

@@ -103,6 +103,8 @@ typedef struct dtm_solve_opts {
 #define DTM_INFO_WARM_REJECTED 0x1 /* x0 was not a positive finite vector: uniform used */
 #define DTM_INFO_RESTARTED     0x2 /* warm start did not converge: re-ran from uniform   */
 #define DTM_INFO_CHECKED       0x4 /* residual_l1 comes from a float64 check sweep       */
+#define DTM_INFO_STALLED       0x8 /* changes stopped shrinking at the precision floor   */
+#define DTM_INFO_REFINED      0x10 /* float32 could not certify: re-solved in float64    */
 typedef struct dtm_solve_info {
   int32_t iterations;  /* sweeps performed (each reads the matrix once)         */
   int32_t status;

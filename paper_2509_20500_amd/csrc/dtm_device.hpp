@@ -31,34 +31,38 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Sum of a and of b over the block; every thread gets both.  `red` is LDS
-// with room for 2 * BT / 64 doubles.
+// Sums of a, b and c over the block; every thread gets all three.  `red` is
+// LDS with room for 3 * BT / 64 doubles.
 template <int BT>
-__device__ inline void block_sum2(double& a, double& b, double* red) {
+__device__ inline void block_sum3(double& a, double& b, double& c, double* red) {
   a = wave_sum(a);
   b = wave_sum(b);
+  c = wave_sum(c);
+  constexpr int NW = BT / kWave;
   const int w = threadIdx.x / kWave;
   __syncthreads();
   if ((threadIdx.x % kWave) == 0) {
     red[w] = a;
-    red[BT / kWave + w] = b;
+    red[NW + w] = b;
+    red[2 * NW + w] = c;
   }
   __syncthreads();
-  double sa = 0.0, sb = 0.0;
+  double sa = 0.0, sb = 0.0, sc = 0.0;
 #pragma unroll
-  for (int i = 0; i < BT / kWave; ++i) {
+  for (int i = 0; i < NW; ++i) {
     sa += red[i];
-    sb += red[BT / kWave + i];
+    sb += red[NW + i];
+    sc += red[2 * NW + i];
   }
   a = sa;
   b = sb;
+  c = sc;
 }
 
 template <int BT>
-__device__ inline double block_sum(double a, double* red) {
-  double b = 0.0;
-  block_sum2<BT>(a, b, red);
-  return a;
+__device__ inline void block_sum2(double& a, double& b, double* red) {
+  double c = 0.0;
+  block_sum3<BT>(a, b, c, red);
 }
 
 // Exclusive prefix sum over the block in thread order; `total` gets the sum.

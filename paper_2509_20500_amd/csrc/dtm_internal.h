@@ -38,22 +38,29 @@ struct KOpts {
   int32_t pad;
 };
 
+// Convergence bookkeeping of one pixel, shared by both solvers.
+struct StopState {
+  double c1, c2, c3;  // last three L1 changes (c1 newest)
+  double rho;         // |lambda_2| estimate
+  double gain;        // estimated error of the iterate per unit of change
+  double resid;       // float64 residual of the last check sweep
+  double dd_prev;     // ||d_{t-1}||_2^2 of the previous difference vector
+  int32_t iter;       // sweeps since the (re)start
+  int32_t total_iter; // all sweeps
+  int32_t check_next; // next sweep is the float64 check
+  int32_t done;
+  int32_t status;     // DTM_OK / DTM_ENOTCONV
+  int32_t flags;      // DTM_INFO_*
+  int32_t warm;       // started from a caller's vector
+  int32_t stalled;    // changes stopped decreasing at the precision floor
+};
+
 // Per-pixel iteration state of the single-pixel (multi-launch) solver.
 struct SolveState {
-  double c1, c2, c3;   // last three changes (c1 newest)
-  double rho;          // |lambda_2| estimate
-  double resid;        // float64 residual of the last check sweep
-  double sum_y;        // sum of the last product (diagnostic)
-  int32_t iter;        // sweeps done
-  int32_t check_next;  // next sweep accumulates in float64 and yields the residual
-  int32_t done;        // 1 once finished (converged or out of sweeps)
-  int32_t status;      // DTM_OK / DTM_ENOTCONV
-  int32_t flags;       // DTM_INFO_*
-  int32_t warm;        // started from a caller's vector
-  int32_t iter_offset; // sweeps done before the last restart
-  int32_t pad;
+  StopState s;
+  double sum_y;  // sum of the last product (diagnostic)
+  double pad;
 };
-static_assert(sizeof(SolveState) == 80, "SolveState layout");
 
 // Shared host logic (dtm_host.cpp).
 int validate_scene(const dtm_scene& s, dtm_dtype dt);
@@ -70,7 +77,7 @@ inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // band count caps the float64 partial sums at 256 rows of length ld.
 struct SingleLayout {
   int32_t ld, bands, band_rows;
-  size_t off_colf, off_invs, off_x, off_scal, off_state, off_part, total;
+  size_t off_colf, off_invs, off_x, off_scal, off_state, off_dprev, off_part, total;
 };
 inline SingleLayout single_layout(int32_t n, dtm_dtype dt) {
   SingleLayout L;
@@ -86,6 +93,7 @@ inline SingleLayout single_layout(int32_t n, dtm_dtype dt) {
   L.off_x = off;    off = align256(off + es * L.ld);
   L.off_scal = off; off = align256(off + 64);
   L.off_state = off; off = align256(off + sizeof(SolveState));
+  L.off_dprev = off; off = align256(off + 8 * static_cast<size_t>(L.ld));
   L.off_part = off; off = align256(off + 8 * static_cast<size_t>(L.bands) * L.ld);
   L.total = off;
   return L;

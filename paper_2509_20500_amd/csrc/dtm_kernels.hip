@@ -40,7 +40,7 @@ __device__ inline PixelMeta load_meta(const PixelMeta* metas, const PixelMeta& o
 template <typename T, int BT>
 __global__ __launch_bounds__(BT) void k_tables(const PixelMeta* metas, PixelMeta one, T* colf,
                                                double* scal, T* lam_out, double* F_out) {
-  __shared__ double red[2 * BT / kWave];
+  __shared__ double red[3 * BT / kWave];
   const PixelMeta m = load_meta(metas, one, blockIdx.x);
   const double Lam = pixel_tables<T, BT>(m, colf + m.vec_off, lam_out, F_out, red);
   if (threadIdx.x == 0) scal[blockIdx.x] = exp(-Lam);
@@ -144,10 +144,33 @@ __global__ __launch_bounds__(BT) void k_shift(const PixelMeta* metas, PixelMeta 
 }
 
 // ============================================================================
-// Stop rule (Section 4: the error of power iteration decays like |lambda_2|^t;
-// rho is estimated from successive L1 changes).  All threads of a block run
-// it on identical inputs and reach identical decisions.
+// Stop rule.  The error of power iteration decays like |lambda_2|^t
+// (Section 4); its phase decides whether the iterates approach pi
+// monotonically or oscillate around it.  After sweep t with difference
+// vector d_t = x_{t+1} - x_t:
+//   rho  = max(c_t / c_{t-1}, sqrt(c_t / c_{t-2}))     (|lambda_2| estimate)
+//   if d_t is parallel to d_{t-1} (a real dominant eigenvalue mu, estimated
+//   by projection), the remaining error is |mu| / (1 - mu) * ||d_t||, which
+//   is small for an alternating mu < 0; otherwise the phase-free worst case
+//   rho / (1 - rho) is used.
+// Every thread of a block runs this on identical inputs.
 // ============================================================================
+
+__device__ inline void stop_init(StopState& s, int warm, int flags) {
+  s.c1 = s.c2 = s.c3 = 0.0;
+  s.rho = 0.999;
+  s.gain = 999.0;
+  s.resid = 0.0;
+  s.dd_prev = 0.0;
+  s.iter = 0;
+  s.total_iter = 0;
+  s.check_next = 0;
+  s.done = 0;
+  s.status = DTM_OK;
+  s.flags = flags;
+  s.warm = warm;
+  s.stalled = 0;
+}
 
 __device__ inline double estimate_rho(double c1, double c2, double c3, int t) {
   double rho;
@@ -160,50 +183,66 @@ __device__ inline double estimate_rho(double c1, double c2, double c3, int t) {
   return fmin(fmax(rho, 0.0), 0.999);
 }
 
-struct StopState {
-  double c1, c2, c3, rho, resid;
-  int iter;        // sweeps since (re)start
-  int total_iter;  // all sweeps
-  int check_next;
-  int done;
-  int status;
-  int flags;
-  int warm;
-};
-
-// Updates the state after a sweep that produced `change` (and, for a check
-// sweep, the float64 residual `resid` of its input).  Returns true when the
-// caller should restart from the uniform vector.
-__device__ inline bool stop_update(StopState& s, const KOpts& o, double change, double resid,
-                                   bool was_check) {
+// Updates the state after a sweep: change = ||d_t||_1, dd = ||d_t||_2^2,
+// ddp = <d_t, d_{t-1}>, resid = ||x_t P - x_t||_1 (float64 on a check
+// sweep), eps = unit round-off of the iterate's type.  Returns true when the
+// caller must restart from the uniform vector (a warm start that failed).
+__device__ inline bool stop_update(StopState& s, const KOpts& o, double change, double dd,
+                                   double ddp, double resid, bool was_check, double eps) {
   s.iter += 1;
   s.total_iter += 1;
   s.c3 = s.c2;
   s.c2 = s.c1;
   s.c1 = change;
-  s.rho = estimate_rho(s.c1, s.c2, s.c3, s.iter);
-  const double gain = s.rho / (1.0 - s.rho);
+  // Ratios of changes near the round-off floor are noise: keep the last
+  // estimate made above 64 units of round-off.
+  if (s.iter <= 2 || change >= 64.0 * eps) {
+    s.rho = estimate_rho(s.c1, s.c2, s.c3, s.iter);
+    double g = s.rho / (1.0 - s.rho);
+    if (s.iter >= 2 && s.dd_prev > 0.0 && dd > 0.0) {
+      const double mu = ddp / s.dd_prev;
+      const double cos2 = (ddp * ddp) / (dd * s.dd_prev);
+      if (cos2 >= 0.99 && mu < 0.999) g = fmin(g, fabs(mu) / (1.0 - mu));
+    }
+    s.gain = g;
+  }
+  const double gain = s.gain;
+  s.dd_prev = dd;
+  // No progress over two sweeps at the round-off floor of the iterate.
+  const bool stalled = s.iter >= 3 && change > 0.0 && change >= s.c3 && change < 4096.0 * eps;
+  if (stalled) s.stalled = 1;
+  s.resid = resid;
   if (was_check) {
-    s.resid = resid;
     s.flags |= DTM_INFO_CHECKED;
-    const bool ok = (o.stop_rule == DTM_STOP_CHANGE) ? (change < o.tol) : (resid * gain <= o.tol);
+    const bool ok = (o.stop_rule == DTM_STOP_CHANGE) ? (change < o.tol)
+                                                     : (resid * gain <= o.safety * o.tol);
     if (ok) {
       s.done = 1;
       s.status = DTM_OK;
       return false;
     }
+    if (s.stalled) {  // cannot improve further in this precision
+      s.flags |= DTM_INFO_STALLED;
+      s.done = 1;
+      s.status = DTM_ENOTCONV;
+      return false;
+    }
     s.check_next = 0;
   } else {
-    s.resid = resid;
     const bool fire = (o.stop_rule == DTM_STOP_CHANGE)
                           ? (change < o.tol)
                           : (change == 0.0 || (s.iter >= 2 && change * gain <= o.safety * o.tol));
-    if (fire) {
+    if (fire || s.stalled) {
       if (o.final_check) {
         s.check_next = 1;
-      } else {
+      } else if (fire) {
         s.done = 1;
         s.status = DTM_OK;
+        return false;
+      } else {
+        s.flags |= DTM_INFO_STALLED;
+        s.done = 1;
+        s.status = DTM_ENOTCONV;
         return false;
       }
     }
@@ -213,13 +252,27 @@ __device__ inline bool stop_update(StopState& s, const KOpts& o, double change, 
       s.flags |= DTM_INFO_RESTARTED;
       s.iter = 0;
       s.c1 = s.c2 = s.c3 = 0.0;
+      s.dd_prev = 0.0;
       s.check_next = 0;
+      s.stalled = 0;
       return true;
     }
     s.done = 1;
     s.status = DTM_ENOTCONV;
   }
   return false;
+}
+
+__device__ inline dtm_solve_info make_info(const StopState& s) {
+  dtm_solve_info info;
+  info.iterations = s.total_iter;
+  info.status = s.status;
+  info.flags = s.flags;
+  info.reserved = 0;
+  info.change_l1 = s.c1;
+  info.residual_l1 = s.resid;
+  info.rho_hat = s.rho;
+  return info;
 }
 
 // ============================================================================
@@ -266,15 +319,7 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
 
   // ---- start vector: caller's (validated) or uniform ---------------------
   StopState st;
-  st.c1 = st.c2 = st.c3 = 0.0;
-  st.rho = 0.999;
-  st.resid = 0.0;
-  st.iter = st.total_iter = 0;
-  st.check_next = 0;
-  st.done = 0;
-  st.status = DTM_OK;
-  st.flags = 0;
-  st.warm = 0;
+  stop_init(st, 0, 0);
   if (x0_packed) {
     double sum = 0.0, bad = 0.0;
     for (int j = tid; j < n; j += BT) {
@@ -307,6 +352,11 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
 
   T acc[CPT][VN], cmp[CPT][VN];
   double accd[CPT][VN];
+  double dprev[CPT][VN];  // previous difference vector on this thread's columns
+#pragma unroll
+  for (int q = 0; q < CPT; ++q)
+#pragma unroll
+    for (int e = 0; e < VN; ++e) dprev[q][e] = 0.0;
 
   // ---- a2+a3 fused with the first sweep: write row i from base row
   //      k = (i + l) mod n and accumulate x_i P~[i, :] ----------------------
@@ -357,27 +407,33 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
     block_sum2<BT>(sy, rs, red);
     const double inv = 1.0 / sy;
     T xn[CPT][VN];
-    double ch = 0.0;
+    double ch = 0.0, dd = 0.0, ddp = 0.0;
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const int j0 = (tid + BT * q) * VN;
 #pragma unroll
       for (int e = 0; e < VN; ++e) {
         xn[q][e] = static_cast<T>(y[q][e] * inv);
-        if (j0 + e < n) ch += fabs(static_cast<double>(xn[q][e]) - static_cast<double>(xs[j0 + e]));
+        const double dj = (j0 + e < n)
+                              ? static_cast<double>(xn[q][e]) - static_cast<double>(xs[j0 + e])
+                              : 0.0;
+        ch += fabs(dj);
+        dd += dj * dj;
+        ddp += dj * dprev[q][e];
+        dprev[q][e] = dj;
       }
     }
-    ch = block_sum<BT>(ch, red);  // its barriers also end every read of xs
+    block_sum3<BT>(ch, dd, ddp, red);  // its barriers also end every read of xs
+    const bool restart = stop_update(st, o, ch, dd, ddp, rs, have_check,
+                                     sizeof(T) == 4 ? 5.9604644775390625e-8 : 1.1102230246251565e-16);
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const int j0 = (tid + BT * q) * VN;
 #pragma unroll
-      for (int e = 0; e < VN; ++e)
-        if (j0 + e < n) xs[j0 + e] = xn[q][e];
-    }
-    const bool restart = stop_update(st, o, ch, rs, have_check);
-    if (restart) {
-      for (int j = tid; j < n; j += BT) xs[j] = static_cast<T>(1.0 / n);
+      for (int e = 0; e < VN; ++e) {
+        if (j0 + e < n) xs[j0 + e] = restart ? static_cast<T>(1.0 / n) : xn[q][e];
+        if (restart) dprev[q][e] = 0.0;
+      }
     }
     __syncthreads();
     if (st.done) break;
@@ -447,14 +503,118 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
   // ---- outputs --------------------------------------------------------------
   for (int j = tid; j < n; j += BT) pi_packed[m.pi_off + j] = xs[j];
   if (tid == 0) {
-    dtm_solve_info info;
-    info.iterations = st.total_iter;
-    info.status = st.status;
-    info.flags = st.flags;
-    info.reserved = 0;
-    info.change_l1 = st.c1;
-    info.residual_l1 = st.resid;
-    info.rho_hat = st.rho;
+    const dtm_solve_info info = make_info(st);
+    infos[m.index] = info;
+  }
+}
+
+// ============================================================================
+// Float64 refinement of the pixels a float32 solve could not certify (they
+// stalled at the float32 round-off floor above the tolerance).  A
+// slowly mixing chain (|lambda_2| near 1) amplifies the float32 round-off of
+// the matrix and of the iterate by about 1 / (1 - |lambda_2|); when the
+// float64 residual bound cannot reach the tolerance the pixel is re-solved
+// here in float64, starting from its float32 result.  The matrix entries
+// g_j w_kj / S_k are regenerated in every sweep from float64 tables held in
+// LDS, so no float64 matrix is stored.  Thread t owns columns t + BT q.
+// ============================================================================
+
+template <int BT, int QMAX, typename TO>
+__global__ __launch_bounds__(BT) void k_refine_f64(const PixelMeta* __restrict__ metas,
+                                                   TO* __restrict__ pi_packed,
+                                                   dtm_solve_info* __restrict__ infos, KOpts o,
+                                                   int lds_ld) {
+  const PixelMeta m = metas[blockIdx.x];
+  const dtm_solve_info prev = infos[m.index];
+  if (prev.status == DTM_OK || !(prev.flags & DTM_INFO_STALLED)) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* g = reinterpret_cast<double*>(smem);  // tables, then u_i = x_i / S_{k(i)}
+  double* invs = g + lds_ld;
+  double* red = invs + lds_ld;
+  const int n = m.n;
+  const int tid = threadIdx.x;
+  const double Lam = pixel_tables<double, BT>(m, g, nullptr, nullptr, red);
+  const double c = exp(-Lam);
+  __syncthreads();
+  for (int k = tid / kWave; k < n; k += BT / kWave) {
+    const double sk = wave_row_sum<double>(g, n, k, c);
+    if ((tid % kWave) == 0) invs[k] = 1.0 / sk;
+  }
+  double gr[QMAX], xr[QMAX], dp[QMAX];
+  double sum0 = 0.0, bad = 0.0;
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    const int j = tid + BT * q;
+    gr[q] = (j < n) ? g[j] : 0.0;
+    xr[q] = (j < n) ? static_cast<double>(pi_packed[m.pi_off + j]) : 0.0;
+    dp[q] = 0.0;
+    if (j < n) {
+      if (!(xr[q] >= 0.0) || !isfinite(xr[q])) bad += 1.0;
+      else sum0 += xr[q];
+    }
+  }
+  block_sum2<BT>(sum0, bad, red);  // also orders the g reads before g is reused
+  const bool start_ok = bad == 0.0 && sum0 > 0.0 && isfinite(sum0);
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) xr[q] = start_ok ? xr[q] / sum0 : 1.0 / n;
+  StopState st;
+  stop_init(st, 0, 0);
+  double* u = g;
+  for (;;) {
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int i = tid + BT * q;
+      if (i < n) {
+        int k = i + m.l;
+        if (k >= n) k -= n;
+        u[i] = xr[q] * invs[k];
+      }
+    }
+    __syncthreads();
+    double acc[QMAX];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) acc[q] = 0.0;
+    for (int i = 0; i < n; ++i) {
+      int k = i + m.l;
+      if (k >= n) k -= n;
+      const double ui = u[i];
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) acc[q] += ui * ((tid + BT * q) < k ? c : 1.0);
+    }
+    double sy = 0.0, rs = 0.0;
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      acc[q] *= gr[q];  // y_j
+      if (tid + BT * q < n) {
+        sy += acc[q];
+        rs += fabs(acc[q] - xr[q]);
+      }
+    }
+    block_sum2<BT>(sy, rs, red);
+    double ch = 0.0, dd = 0.0, ddp = 0.0;
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const double xn = acc[q] / sy;
+      const double dj = (tid + BT * q < n) ? xn - xr[q] : 0.0;
+      ch += fabs(dj);
+      dd += dj * dj;
+      ddp += dj * dp[q];
+      dp[q] = dj;
+      xr[q] = xn;
+    }
+    block_sum3<BT>(ch, dd, ddp, red);  // its barriers end the reads of u
+    stop_update(st, o, ch, dd, ddp, rs, true, 1.1102230246251565e-16);
+    if (st.done) break;
+  }
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    const int j = tid + BT * q;
+    if (j < n) pi_packed[m.pi_off + j] = static_cast<TO>(xr[q]);
+  }
+  if (tid == 0) {
+    dtm_solve_info info = make_info(st);
+    info.iterations += prev.iterations;
+    info.flags |= (prev.flags & ~(DTM_INFO_STALLED)) | DTM_INFO_REFINED;
     infos[m.index] = info;
   }
 }
@@ -467,8 +627,9 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
 // ============================================================================
 
 template <typename T, int BT>
-__global__ __launch_bounds__(BT) void k_solver_init(const T* x0, T* x, SolveState* state, int n) {
-  __shared__ double red[2 * BT / kWave];
+__global__ __launch_bounds__(BT) void k_solver_init(const T* x0, T* x, double* dprev,
+                                                    SolveState* state, int n) {
+  __shared__ double red[3 * BT / kWave];
   double sum = 0.0, bad = 0.0;
   if (x0) {
     for (int j = threadIdx.x; j < n; j += BT) {
@@ -479,22 +640,15 @@ __global__ __launch_bounds__(BT) void k_solver_init(const T* x0, T* x, SolveStat
   }
   block_sum2<BT>(sum, bad, red);
   const bool warm = x0 && bad == 0.0 && sum > 0.0 && isfinite(sum);
-  for (int j = threadIdx.x; j < n; j += BT)
+  for (int j = threadIdx.x; j < n; j += BT) {
     x[j] = warm ? static_cast<T>(static_cast<double>(x0[j]) / sum) : static_cast<T>(1.0 / n);
+    dprev[j] = 0.0;
+  }
   if (threadIdx.x == 0) {
     SolveState s;
-    s.c1 = s.c2 = s.c3 = 0.0;
-    s.rho = 0.999;
-    s.resid = 0.0;
+    stop_init(s.s, warm ? 1 : 0, (x0 && !warm) ? DTM_INFO_WARM_REJECTED : 0);
     s.sum_y = 0.0;
-    s.iter = 0;
-    s.check_next = 0;
-    s.done = 0;
-    s.status = DTM_OK;
-    s.flags = (x0 && !warm) ? DTM_INFO_WARM_REJECTED : 0;
-    s.warm = warm ? 1 : 0;
-    s.iter_offset = 0;
-    s.pad = 0;
+    s.pad = 0.0;
     *state = s;
   }
 }
@@ -508,8 +662,8 @@ __global__ __launch_bounds__(BT) void k_sweep_band(const T* __restrict__ P, int 
                                                    const SolveState* __restrict__ state,
                                                    double* __restrict__ part, int64_t part_ld,
                                                    int band_rows) {
-  if (state->done) return;
-  const bool check = state->check_next != 0;
+  if (state->s.done) return;
+  const bool check = state->s.check_next != 0;
   const int band = blockIdx.y;
   const int i0 = band * band_rows;
   const int i1 = min(i0 + band_rows, n);
@@ -556,11 +710,11 @@ __global__ __launch_bounds__(BT) void k_sweep_band(const T* __restrict__ P, int 
 template <typename T, int BT>
 __global__ __launch_bounds__(BT) void k_combine(const double* __restrict__ part, int64_t part_ld,
                                                 int bands, int n, T* __restrict__ x,
+                                                double* __restrict__ dprev,
                                                 SolveState* __restrict__ state,
                                                 T* __restrict__ pi, KOpts o) {
-  __shared__ double red[2 * BT / kWave];
-  __shared__ int s_flag[2];
-  SolveState s = *state;
+  __shared__ double red[3 * BT / kWave];
+  StopState s = state->s;
   if (s.done) return;
   const bool was_check = s.check_next != 0;
   double sy = 0.0, rs = 0.0;
@@ -572,53 +726,36 @@ __global__ __launch_bounds__(BT) void k_combine(const double* __restrict__ part,
   }
   block_sum2<BT>(sy, rs, red);
   const double inv = 1.0 / sy;
-  double ch = 0.0;
+  double ch = 0.0, dd = 0.0, ddp = 0.0;
   for (int j = threadIdx.x; j < n; j += BT) {
     double y = 0.0;
     for (int b = 0; b < bands; ++b) y += part[static_cast<int64_t>(b) * part_ld + j];
-    ch += fabs(static_cast<double>(static_cast<T>(y * inv)) - static_cast<double>(x[j]));
+    const T xn = static_cast<T>(y * inv);
+    const double dj = static_cast<double>(xn) - static_cast<double>(x[j]);
+    ch += fabs(dj);
+    dd += dj * dj;
+    ddp += dj * dprev[j];
+    dprev[j] = dj;
+    x[j] = xn;  // each thread owns its j: no other thread reads it in this launch
   }
-  ch = block_sum<BT>(ch, red);
-  for (int j = threadIdx.x; j < n; j += BT) {
-    double y = 0.0;
-    for (int b = 0; b < bands; ++b) y += part[static_cast<int64_t>(b) * part_ld + j];
-    x[j] = static_cast<T>(y * inv);
+  block_sum3<BT>(ch, dd, ddp, red);
+  const bool restart = stop_update(s, o, ch, dd, ddp, rs, was_check,
+                                   sizeof(T) == 4 ? 5.9604644775390625e-8 : 1.1102230246251565e-16);
+  if (restart) {
+    for (int j = threadIdx.x; j < n; j += BT) {
+      x[j] = static_cast<T>(1.0 / n);
+      dprev[j] = 0.0;
+    }
   }
-  StopState t;
-  t.c1 = s.c1;
-  t.c2 = s.c2;
-  t.c3 = s.c3;
-  t.rho = s.rho;
-  t.resid = s.resid;
-  t.iter = s.iter;
-  t.total_iter = s.iter + s.iter_offset;
-  t.check_next = s.check_next;
-  t.done = 0;
-  t.status = DTM_OK;
-  t.flags = s.flags;
-  t.warm = s.warm;
-  const bool restart = stop_update(t, o, ch, rs, was_check);
-  __syncthreads();
-  if (restart)
-    for (int j = threadIdx.x; j < n; j += BT) x[j] = static_cast<T>(1.0 / n);
-  if (t.done)
+  if (s.done)
     for (int j = threadIdx.x; j < n; j += BT) pi[j] = x[j];
   if (threadIdx.x == 0) {
-    s.c1 = t.c1;
-    s.c2 = t.c2;
-    s.c3 = t.c3;
-    s.rho = t.rho;
-    s.resid = t.resid;
-    s.sum_y = sy;
-    s.iter = t.iter;
-    s.iter_offset = t.total_iter - t.iter;
-    s.check_next = t.check_next;
-    s.done = t.done;
-    s.status = t.status;
-    s.flags = t.flags;
-    *state = s;
+    SolveState out;
+    out.s = s;
+    out.sum_y = sy;
+    out.pad = 0.0;
+    *state = out;
   }
-  (void)s_flag;
 }
 
 }  // namespace dtm
@@ -736,16 +873,19 @@ int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_e
   char* w = static_cast<char*>(ws);
   T* x = reinterpret_cast<T*>(w + L.off_x);
   SolveState* state = reinterpret_cast<SolveState*>(w + L.off_state);
+  double* dprev = reinterpret_cast<double*>(w + L.off_dprev);
   double* part = reinterpret_cast<double*>(w + L.off_part);
   constexpr int VN = Vec<T>::n;
   const bool vec = (ld % VN == 0) && (reinterpret_cast<uintptr_t>(P) % 16 == 0);
-  hipLaunchKernelGGL((k_solver_init<T, kBT>), dim3(1), dim3(kBT), 0, st, x0, x, state, n);
+  hipLaunchKernelGGL((k_solver_init<T, kBT>), dim3(1), dim3(kBT), 0, st, x0, x, dprev, state, n);
   int rc = last_launch();
   if (rc) return rc;
   const int vn = vec ? VN : 1;
   const int cols_per_block = kBT * vn;
   dim3 grid((n + cols_per_block - 1) / cols_per_block, L.bands);
   SolveState hs;
+  // Each pair of launches is one sweep; after `done` they return at once.
+  // The stop rule ends every solve within 2 * max_iter sweeps (one restart).
   const int max_sweeps = 2 * ko.max_iter + 2;
   int launched = 0;
   for (;;) {
@@ -757,27 +897,27 @@ int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_e
         hipLaunchKernelGGL((k_sweep_band<T, kBT, 1>), grid, dim3(kBT), 0, st, P, n, ld, x, state,
                            part, static_cast<int64_t>(L.ld), L.band_rows);
       hipLaunchKernelGGL((k_combine<T, kBT>), dim3(1), dim3(kBT), 0, st, part,
-                         static_cast<int64_t>(L.ld), L.bands, n, x, state, pi, ko);
+                         static_cast<int64_t>(L.ld), L.bands, n, x, dprev, state, pi, ko);
     }
     rc = last_launch();
     if (rc) return rc;
     if (hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess) return DTM_EHIP;
     if (hipStreamSynchronize(st) != hipSuccess) return DTM_EHIP;
-    if (hs.done || launched >= max_sweeps) break;
+    if (hs.s.done || launched >= max_sweeps) break;
   }
-  if (!hs.done) {  // cannot happen with the stop rule's own max_iter; be explicit anyway
-    hs.status = DTM_ENOTCONV;
+  if (!hs.s.done) {
+    hs.s.status = DTM_ENOTCONV;
     if (hipMemcpyAsync(pi, x, sizeof(T) * n, hipMemcpyDeviceToDevice, st) != hipSuccess) return DTM_EHIP;
     if (hipStreamSynchronize(st) != hipSuccess) return DTM_EHIP;
   }
   if (info) {
-    info->iterations = hs.iter + hs.iter_offset;
-    info->status = hs.status;
-    info->flags = hs.flags;
+    info->iterations = hs.s.total_iter;
+    info->status = hs.s.status;
+    info->flags = hs.s.flags;
     info->reserved = 0;
-    info->change_l1 = hs.c1;
-    info->residual_l1 = hs.resid;
-    info->rho_hat = hs.rho;
+    info->change_l1 = hs.s.c1;
+    info->residual_l1 = hs.s.resid;
+    info->rho_hat = hs.s.rho;
   }
   return DTM_OK;
 }
@@ -786,7 +926,7 @@ int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_e
 template <typename T, int BT, int CPT>
 int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, int count, T* pool,
                      const T* x0, T* pi, dtm_solve_info* infos, int lds_ld, hipStream_t st) {
-  const size_t lds = 3 * sizeof(T) * static_cast<size_t>(lds_ld) + 2 * BT / kWave * sizeof(double);
+  const size_t lds = 3 * sizeof(T) * static_cast<size_t>(lds_ld) + 3 * BT / kWave * sizeof(double);
   void (*kern)(const PixelMeta*, T*, const T*, T*, dtm_solve_info*, KOpts, int) = nullptr;
   switch (unroll) {
     case 2: kern = k_solve_fused<T, BT, CPT, 2>; break;
@@ -815,6 +955,26 @@ int launch_fused_bt(const dtm_plan* plan, int cpt, const PixelMeta* metas, int c
   }
 }
 
+// Float64 refinement pass over the pixels of a float32 solve that failed
+// their certificate (blocks of certified pixels return at once).
+template <typename T>
+int launch_refine(const dtm_plan* plan, const PixelMeta* metas, T* pi, dtm_solve_info* infos,
+                  hipStream_t st) {
+  constexpr int BT = 512, QMAX = 16;
+  if (plan->max_n > BT * QMAX) return DTM_ENOTSUP;
+  const size_t lds = 2 * sizeof(double) * static_cast<size_t>(plan->max_ld) + 3 * BT / kWave * sizeof(double);
+  auto kern = k_refine_f64<BT, QMAX, T>;
+  if (lds > 64 * 1024) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            static_cast<int>(lds)) != hipSuccess)
+      return DTM_EHIP;
+  }
+  hipLaunchKernelGGL(kern, dim3(plan->n_pixels), dim3(BT), lds, st, metas, pi, infos, plan->kopts,
+                     plan->max_ld);
+  return last_launch();
+}
+
 template <typename T>
 int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info* infos,
                   hipStream_t st) {
@@ -833,13 +993,17 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
   cpt = cpt <= 1 ? 1 : cpt <= 2 ? 2 : 4;
   if (cpt * bt * VN < plan->max_ld) return DTM_ENOTSUP;
   const int lds_ld = plan->max_ld;
-  const size_t lds = 3 * sizeof(T) * static_cast<size_t>(lds_ld) + 2 * bt / kWave * sizeof(double);
+  const size_t lds = 3 * sizeof(T) * static_cast<size_t>(lds_ld) + 3 * bt / kWave * sizeof(double);
   if (lds > 160 * 1024) return DTM_ENOTSUP;
   const T* x0t = static_cast<const T*>(x0);
   T* pit = static_cast<T*>(pi);
+  int rc;
   if (bt == 512)
-    return launch_fused_bt<T, 512>(plan, cpt, metas, plan->n_pixels, pool, x0t, pit, infos, lds_ld, st);
-  return launch_fused_bt<T, 256>(plan, cpt, metas, plan->n_pixels, pool, x0t, pit, infos, lds_ld, st);
+    rc = launch_fused_bt<T, 512>(plan, cpt, metas, plan->n_pixels, pool, x0t, pit, infos, lds_ld, st);
+  else
+    rc = launch_fused_bt<T, 256>(plan, cpt, metas, plan->n_pixels, pool, x0t, pit, infos, lds_ld, st);
+  if (rc || sizeof(T) == 8) return rc;
+  return launch_refine<T>(plan, metas, pit, infos, st);
 }
 
 template <typename T>

@@ -36,6 +36,8 @@ DTM_FLAG_NO_FINAL_CHECK = 0x1
 DTM_INFO_WARM_REJECTED = 0x1
 DTM_INFO_RESTARTED = 0x2
 DTM_INFO_CHECKED = 0x4
+DTM_INFO_STALLED = 0x8
+DTM_INFO_REFINED = 0x10
 
 DTM_MAX_BINS = 65536
 

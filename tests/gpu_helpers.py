@@ -23,8 +23,17 @@ def oracle_pi(scene):
     return odtm.stationary_solve(odtm.transition_matrix(scene))
 
 
+def default_opts(dt):
+    """Stop rule targets: 1e-6 for float32, 1e-10 for float64 (so that the
+    float64 path lands well inside its 1e-9 parity bar)."""
+    d = lib()
+    return d.opts(tol=1e-6) if dt == "f32" else d.opts(tol=1e-10)
+
+
 def run_batched(scenes, dt, x0=None, solve_opts=None, tiles=None, return_plan=False):
     d = lib()
+    if solve_opts is None:
+        solve_opts = default_opts(dt)
     plan = d.Plan(scenes, dt, solve_opts, tiles)
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     plan.bind(ws)
