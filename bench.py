@@ -64,6 +64,26 @@ def cpu_baseline(scenes, sample):
     }
 
 
+def copy_calibration(nbytes=1 << 30, reps=10):
+    """A plain device-to-device copy of known size (torch's elementwise copy
+    kernel): its achieved GB/s, and the reference whose FETCH_SIZE and
+    WRITE_SIZE counters (nbytes each per launch) scale the solver's."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": ms,
+            "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +96,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--threads", type=int, default=0, help="fused block size (0 = default)")
     ap.add_argument("--unroll", type=int, default=0, help="rows in flight per thread (0 = default)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also time a plain 1 GiB device copy (the reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); pixels shard across GPUs "
@@ -172,6 +194,8 @@ def main():
     }
     plan.close()
     del ws
+    if args.calibrate:
+        out["copy_calibration"] = copy_calibration()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scenes, args.cpu_sample)
     print(json.dumps(out), flush=True)

@@ -148,12 +148,20 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   plan->tiles = tc;
   plan->n_pixels = n_pixels;
 
-  // Launch order: descending n (longest jobs first), stable on input index.
+  // Launch order: longest expected job first, so that the last blocks to
+  // start are short ones.  A pixel's cost is n^2 bytes per sweep times its
+  // sweep count; the sweep count grows as the spectral gap 1 - |lambda_2|
+  // shrinks, which happens as the background flux B grows (Section 4), so
+  // the expected cost is taken as n^2 (1 + 2 B).  Stable on input index.
   std::vector<int32_t> order(n_pixels);
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    return scenes_host[a].n_bins > scenes_host[b].n_bins;
-  });
+  std::vector<double> cost(n_pixels);
+  for (int32_t p = 0; p < n_pixels; ++p) {
+    const double nn = static_cast<double>(scenes_host[p].n_bins);
+    cost[p] = nn * nn * (1.0 + 2.0 * scenes_host[p].background_flux);
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
   // Offsets in the caller's order.
   std::vector<int64_t> pi_off(n_pixels), out_off(n_pixels);
   int64_t acc_pi = 0, acc_out = 0;
@@ -168,6 +176,7 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   plan->meta.resize(n_pixels);
   int64_t acc_vec = 0, acc_pool = 0;
   int32_t max_n = 0, max_ld = 0;
+  static_assert(DTM_POOL_PAD % 16 == 0, "pool stagger must keep 16-byte alignment");
   for (int32_t q = 0; q < n_pixels; ++q) {
     const int32_t p = order[q];
     const dtm_scene& s = scenes_host[p];
@@ -186,7 +195,11 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
     m.mat_off = acc_pool;
     m.out_off = out_off[p];
     acc_vec += m.ld;
-    acc_pool += static_cast<int64_t>(m.n) * m.ld;
+    // Consecutive matrices are staggered by DTM_POOL_PAD bytes so that the
+    // many blocks streaming their own matrix in step do not start on the
+    // same HBM channel.
+    acc_pool += static_cast<int64_t>(m.n) * m.ld +
+                static_cast<int64_t>(DTM_POOL_PAD) / static_cast<int64_t>(dtype_size(dt));
     max_n = std::max(max_n, m.n);
     max_ld = std::max(max_ld, m.ld);
   }

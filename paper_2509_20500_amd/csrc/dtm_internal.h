@@ -7,6 +7,14 @@
 
 #include "dtm.h"
 
+// Tuning constants (compile time).
+#ifndef DTM_POOL_PAD
+#define DTM_POOL_PAD 0  // bytes added between consecutive matrices in the pool
+#endif
+#ifndef DTM_NT_LOADS
+#define DTM_NT_LOADS 1  // stream matrix reads with non-temporal loads
+#endif
+
 namespace dtm {
 
 // Per-pixel metadata resident in device memory (batched path).  Offsets are

@@ -276,16 +276,95 @@ __device__ inline dtm_solve_info make_info(const StopState& s) {
 }
 
 // ============================================================================
-// Batched fused solver: one block per pixel does the bin tables, the row
-// sums, the shifted build fused with the first power-iteration sweep, the
-// remaining sweeps, the float64 check sweep and the stop rule.  Thread t owns
-// columns (t + BT * q) * VN .. + VN - 1 for q < CPT in every row, so each
-// row is one coalesced pass of the block and no cross-thread reduction of
-// x P~ is needed.
+// Batched fused solver: one block per pixel does the row sums, the shifted
+// build fused with the first power-iteration sweep, the remaining sweeps,
+// the float64 check sweep and the stop rule.  The bin tables g_j and
+// c = exp(-Lambda) come from k_tables (run just before, so that its erf code
+// does not set this kernel's register budget).  Thread t owns columns
+// (t + BT q) * VN .. + VN - 1 for q < CPT in every row: each row is one
+// coalesced pass of the block and x P~ needs no cross-thread reduction.
 // ============================================================================
+
+template <typename V>
+__device__ inline V stream_load(const V* p) {
+#if DTM_NT_LOADS
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
+// y += x_i P[i, :] over rows [i0, i1) for this thread's columns, UE rows in
+// flight plus the next UE rows prefetched.  Addresses of columns past n are
+// clamped to column 0 (those lanes' sums are never used), so the loads carry
+// no per-lane guards.
+template <typename T, int BT, int CPT, int UE, bool CHECK, typename A>
+__device__ inline void sweep_rows(const T* __restrict__ mat, int64_t ld, int n, const int* jc,
+                                  const T* __restrict__ xs, A (&acc)[CPT][Vec<T>::n],
+                                  A (&cmp)[CPT][Vec<T>::n]) {
+  using V = typename Vec<T>::type;
+  constexpr int VN = Vec<T>::n;
+  int i0 = 0;
+  if (n >= UE) {
+    V cur[UE][CPT];
+#pragma unroll
+    for (int u = 0; u < UE; ++u)
+#pragma unroll
+      for (int q = 0; q < CPT; ++q)
+        cur[u][q] = stream_load(
+            reinterpret_cast<const V*>(mat + static_cast<int64_t>(u) * ld + jc[q]));
+    for (; i0 + UE <= n; i0 += UE) {
+      V nxt[UE][CPT];
+      const bool more = i0 + 2 * UE <= n;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < UE; ++u)
+#pragma unroll
+          for (int q = 0; q < CPT; ++q)
+            nxt[u][q] = stream_load(reinterpret_cast<const V*>(
+                mat + static_cast<int64_t>(i0 + UE + u) * ld + jc[q]));
+      }
+#pragma unroll
+      for (int u = 0; u < UE; ++u) {
+        const T xi = xs[i0 + u];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+#pragma unroll
+          for (int e = 0; e < VN; ++e) {
+            if constexpr (CHECK)
+              acc[q][e] += static_cast<double>(xi) * static_cast<double>(cur[u][q][e]);
+            else
+              comp_add(acc[q][e], cmp[q][e], xi * cur[u][q][e]);
+          }
+      }
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < UE; ++u)
+#pragma unroll
+          for (int q = 0; q < CPT; ++q) cur[u][q] = nxt[u][q];
+      }
+    }
+  }
+  for (; i0 < n; ++i0) {
+    const T xi = xs[i0];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const V v = *reinterpret_cast<const V*>(mat + static_cast<int64_t>(i0) * ld + jc[q]);
+#pragma unroll
+      for (int e = 0; e < VN; ++e) {
+        if constexpr (CHECK)
+          acc[q][e] += static_cast<double>(xi) * static_cast<double>(v[e]);
+        else
+          comp_add(acc[q][e], cmp[q][e], xi * v[e]);
+      }
+    }
+  }
+}
 
 template <typename T, int BT, int CPT, int U>
 __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict__ metas,
+                                                    const T* __restrict__ colf,
+                                                    const double* __restrict__ scal,
                                                     T* __restrict__ pool,
                                                     const T* __restrict__ x0_packed,
                                                     T* __restrict__ pi_packed,
@@ -305,10 +384,10 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
   const int64_t ld = m.ld;
   const int tid = threadIdx.x;
   T* mat = pool + m.mat_off;
+  const T c = static_cast<T>(scal[blockIdx.x]);
 
-  // ---- a1: bin tables -----------------------------------------------------
-  const double Lam = pixel_tables<T, BT>(m, g, nullptr, nullptr, red);
-  const T c = static_cast<T>(exp(-Lam));
+  // ---- a1 tables into LDS (g is zero-padded to ld) -------------------------
+  for (int j = tid; j < m.ld; j += BT) g[j] = colf[m.vec_off + j];
   __syncthreads();
 
   // ---- a2: row sums of the base matrix, one wavefront per row -----------
@@ -341,29 +420,30 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
   }
   __syncthreads();
 
-  // This thread's columns and their g values.
+  // This thread's columns (clamped to 0 past n) and their g values.
+  int jc[CPT];
   T gr[CPT][VN];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int j0 = (tid + BT * q) * VN;
+    jc[q] = j0 < n ? j0 : 0;
 #pragma unroll
-    for (int e = 0; e < VN; ++e) gr[q][e] = (j0 < ld) ? g[j0 + e] : T(0);
+    for (int e = 0; e < VN; ++e) gr[q][e] = (j0 < n) ? g[j0 + e] : T(0);
   }
 
   T acc[CPT][VN], cmp[CPT][VN];
-  double accd[CPT][VN];
+  double accd[CPT][VN], dd0[CPT][VN];
   double dprev[CPT][VN];  // previous difference vector on this thread's columns
 #pragma unroll
   for (int q = 0; q < CPT; ++q)
 #pragma unroll
-    for (int e = 0; e < VN; ++e) dprev[q][e] = 0.0;
+    for (int e = 0; e < VN; ++e) {
+      dprev[q][e] = 0.0;
+      acc[q][e] = cmp[q][e] = T(0);
+    }
 
   // ---- a2+a3 fused with the first sweep: write row i from base row
   //      k = (i + l) mod n and accumulate x_i P~[i, :] ----------------------
-#pragma unroll
-  for (int q = 0; q < CPT; ++q)
-#pragma unroll
-    for (int e = 0; e < VN; ++e) acc[q][e] = cmp[q][e] = T(0);
   for (int i = 0; i < n; ++i) {
     int k = i + m.l;
     if (k >= n) k -= n;
@@ -373,15 +453,13 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const int j0 = (tid + BT * q) * VN;
-      if (j0 < n) {
-        V v;
+      V v;
 #pragma unroll
-        for (int e = 0; e < VN; ++e) {
-          v[e] = gr[q][e] * ((j0 + e) < k ? c : T(1)) * s;
-          comp_add(acc[q][e], cmp[q][e], xi * v[e]);
-        }
-        *reinterpret_cast<V*>(row + j0) = v;
+      for (int e = 0; e < VN; ++e) {
+        v[e] = gr[q][e] * ((j0 + e) < k ? c : T(1)) * s;
+        comp_add(acc[q][e], cmp[q][e], xi * v[e]);
       }
+      if (j0 < n) __builtin_nontemporal_store(v, reinterpret_cast<V*>(row + j0));
     }
   }
   bool have_check = false;  // the accumulators hold a float64 check sweep
@@ -438,74 +516,26 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
     __syncthreads();
     if (st.done) break;
 
-    // ---- a4: next sweep, U rows in flight per thread -------------------
+    // ---- a4: next sweep (a5: float64 check sweep when due) --------------
     have_check = st.check_next != 0;
     if (!have_check) {
 #pragma unroll
       for (int q = 0; q < CPT; ++q)
 #pragma unroll
         for (int e = 0; e < VN; ++e) acc[q][e] = cmp[q][e] = T(0);
-      for (int i0 = 0; i0 < n; i0 += UE) {
-        V v[UE][CPT];
-#pragma unroll
-        for (int u = 0; u < UE; ++u) {
-          const int i = i0 + u;
-#pragma unroll
-          for (int q = 0; q < CPT; ++q) {
-            const int j0 = (tid + BT * q) * VN;
-            if (i < n && j0 < n)
-              v[u][q] = *reinterpret_cast<const V*>(mat + static_cast<int64_t>(i) * ld + j0);
-            else
-              v[u][q] = zero_vec<V>();
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < UE; ++u) {
-          const T xi = (i0 + u < n) ? xs[i0 + u] : T(0);
-#pragma unroll
-          for (int q = 0; q < CPT; ++q)
-#pragma unroll
-            for (int e = 0; e < VN; ++e) comp_add(acc[q][e], cmp[q][e], xi * v[u][q][e]);
-        }
-      }
+      sweep_rows<T, BT, CPT, UE, false>(mat, ld, n, jc, xs, acc, cmp);
     } else {
-      // a5: float64 check sweep (exact products, float64 sums).
 #pragma unroll
       for (int q = 0; q < CPT; ++q)
 #pragma unroll
-        for (int e = 0; e < VN; ++e) accd[q][e] = 0.0;
-      for (int i0 = 0; i0 < n; i0 += UE) {
-        V v[UE][CPT];
-#pragma unroll
-        for (int u = 0; u < UE; ++u) {
-          const int i = i0 + u;
-#pragma unroll
-          for (int q = 0; q < CPT; ++q) {
-            const int j0 = (tid + BT * q) * VN;
-            if (i < n && j0 < n)
-              v[u][q] = *reinterpret_cast<const V*>(mat + static_cast<int64_t>(i) * ld + j0);
-            else
-              v[u][q] = zero_vec<V>();
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < UE; ++u) {
-          const double xi = (i0 + u < n) ? static_cast<double>(xs[i0 + u]) : 0.0;
-#pragma unroll
-          for (int q = 0; q < CPT; ++q)
-#pragma unroll
-            for (int e = 0; e < VN; ++e) accd[q][e] += xi * static_cast<double>(v[u][q][e]);
-        }
-      }
+        for (int e = 0; e < VN; ++e) accd[q][e] = dd0[q][e] = 0.0;
+      sweep_rows<T, BT, CPT, UE, true>(mat, ld, n, jc, xs, accd, dd0);
     }
   }
 
   // ---- outputs --------------------------------------------------------------
   for (int j = tid; j < n; j += BT) pi_packed[m.pi_off + j] = xs[j];
-  if (tid == 0) {
-    const dtm_solve_info info = make_info(st);
-    infos[m.index] = info;
-  }
+  if (tid == 0) infos[m.index] = make_info(st);
 }
 
 // ============================================================================
@@ -924,10 +954,12 @@ int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_e
 
 // Fused batched solve: kernel instance by (dtype, block, columns per thread).
 template <typename T, int BT, int CPT>
-int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, int count, T* pool,
-                     const T* x0, T* pi, dtm_solve_info* infos, int lds_ld, hipStream_t st) {
+int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, int count,
+                     const T* colf, const double* scal, T* pool, const T* x0, T* pi,
+                     dtm_solve_info* infos, int lds_ld, hipStream_t st) {
   const size_t lds = 3 * sizeof(T) * static_cast<size_t>(lds_ld) + 3 * BT / kWave * sizeof(double);
-  void (*kern)(const PixelMeta*, T*, const T*, T*, dtm_solve_info*, KOpts, int) = nullptr;
+  void (*kern)(const PixelMeta*, const T*, const double*, T*, const T*, T*, dtm_solve_info*, KOpts,
+               int) = nullptr;
   switch (unroll) {
     case 2: kern = k_solve_fused<T, BT, CPT, 2>; break;
     case 4: kern = k_solve_fused<T, BT, CPT, 4>; break;
@@ -939,19 +971,25 @@ int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, i
                             static_cast<int>(lds)) != hipSuccess)
       return DTM_EHIP;
   }
-  hipLaunchKernelGGL(kern, dim3(count), dim3(BT), lds, st, metas, pool, x0, pi, infos, plan->kopts, lds_ld);
+  hipLaunchKernelGGL(kern, dim3(count), dim3(BT), lds, st, metas, colf, scal, pool, x0, pi, infos,
+                     plan->kopts, lds_ld);
   return last_launch();
 }
 
 template <typename T, int BT>
-int launch_fused_bt(const dtm_plan* plan, int cpt, const PixelMeta* metas, int count, T* pool,
-                    const T* x0, T* pi, dtm_solve_info* infos, int lds_ld, hipStream_t st) {
+int launch_fused_bt(const dtm_plan* plan, int cpt, const PixelMeta* metas, int count,
+                    const T* colf, const double* scal, T* pool, const T* x0, T* pi,
+                    dtm_solve_info* infos, int lds_ld, hipStream_t st) {
   const int u = plan->tiles.fused_unroll;
   switch (cpt) {
-    case 1: return launch_fused_cpt<T, BT, 1>(plan, u, metas, count, pool, x0, pi, infos, lds_ld, st);
-    case 2: return launch_fused_cpt<T, BT, 2>(plan, u, metas, count, pool, x0, pi, infos, lds_ld, st);
-    case 4: return launch_fused_cpt<T, BT, 4>(plan, u, metas, count, pool, x0, pi, infos, lds_ld, st);
-    default: return DTM_ENOTSUP;
+    case 1:
+      return launch_fused_cpt<T, BT, 1>(plan, u, metas, count, colf, scal, pool, x0, pi, infos, lds_ld, st);
+    case 2:
+      return launch_fused_cpt<T, BT, 2>(plan, u, metas, count, colf, scal, pool, x0, pi, infos, lds_ld, st);
+    case 4:
+      return launch_fused_cpt<T, BT, 4>(plan, u, metas, count, colf, scal, pool, x0, pi, infos, lds_ld, st);
+    default:
+      return DTM_ENOTSUP;
   }
 }
 
@@ -997,11 +1035,18 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
   if (lds > 160 * 1024) return DTM_ENOTSUP;
   const T* x0t = static_cast<const T*>(x0);
   T* pit = static_cast<T*>(pi);
-  int rc;
+  T* colf = reinterpret_cast<T*>(w + plan->off_colf);
+  double* scal = reinterpret_cast<double*>(w + plan->off_scal);
+  PixelMeta dummy;
+  std::memset(&dummy, 0, sizeof(dummy));
+  int rc = launch_tables<T>(metas, dummy, plan->n_pixels, colf, scal, nullptr, nullptr, st);
+  if (rc) return rc;
   if (bt == 512)
-    rc = launch_fused_bt<T, 512>(plan, cpt, metas, plan->n_pixels, pool, x0t, pit, infos, lds_ld, st);
+    rc = launch_fused_bt<T, 512>(plan, cpt, metas, plan->n_pixels, colf, scal, pool, x0t, pit, infos,
+                                 lds_ld, st);
   else
-    rc = launch_fused_bt<T, 256>(plan, cpt, metas, plan->n_pixels, pool, x0t, pit, infos, lds_ld, st);
+    rc = launch_fused_bt<T, 256>(plan, cpt, metas, plan->n_pixels, colf, scal, pool, x0t, pit, infos,
+                                 lds_ld, st);
   if (rc || sizeof(T) == 8) return rc;
   return launch_refine<T>(plan, metas, pit, infos, st);
 }
