@@ -114,7 +114,7 @@ def main():
     dtm.lib()
     torch.cuda.set_device(0)
     scenes = sc.batched_uniform(n_pixels=args.pixels)
-    tiles = dtm.TileConfig(args.threads, args.unroll, 0, 0) if (args.threads or args.unroll) else None
+    tiles = dtm.tiles(args.threads, args.unroll) if (args.threads or args.unroll) else None
     plan = dtm.Plan(scenes, args.dtype, dtm.opts(tol=1e-6), tiles)
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     plan.bind(ws)

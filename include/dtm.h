@@ -175,10 +175,13 @@ int dtm_stationary_pdf(const void* P_dev, int32_t n, int64_t ld, dtm_dtype dt,
 /* Launch shape of the batched kernels.  Zero fields take the built-in or
  * autotuned defaults. */
 typedef struct dtm_tile_config {
-  int32_t fused_threads;   /* threads per workgroup of the fused kernel: 256 or 512 */
-  int32_t fused_unroll;    /* rows in flight per thread in a sweep: 2, 4 or 8       */
-  int32_t fused_max_bins;  /* pixels with n_b above this take the banded path       */
-  int32_t band_rows;       /* rows per workgroup in the banded sweep                */
+  int32_t fused_threads;   /* threads per workgroup of the fused kernel: 256 or 512     */
+  int32_t fused_unroll;    /* rows in flight per thread in a sweep: 2, 4 or 8           */
+  int32_t fused_max_bins;  /* pixels with n_b above this take the banded path (>= 2)    */
+  int32_t band_rows;       /* rows per workgroup in the banded sweep, multiple of 16   */
+  int32_t band_sweeps;     /* sweeps launched for banded pixels (<= max_iter); a banded
+                              pixel not converged by then ends with DTM_ENOTCONV       */
+  int32_t reserved[3];     /* must be 0                                                 */
 } dtm_tile_config;
 
 typedef struct dtm_plan dtm_plan; /* opaque host object */

@@ -133,17 +133,29 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   plan->dt = dt;
   plan->kopts = ko;
   plan->check_every = ce;
-  dtm_tile_config tc = {0, 0, 0, 0};
+  dtm_tile_config tc;
+  std::memset(&tc, 0, sizeof(tc));
   if (tiles) tc = *tiles;
   if (tc.fused_threads == 0) tc.fused_threads = 256;
   if (tc.fused_unroll == 0) tc.fused_unroll = 8;
-  if (tc.fused_max_bins == 0) tc.fused_max_bins = DTM_MAX_BINS;
+  if (tc.fused_max_bins == 0) tc.fused_max_bins = 2048;
   if (tc.band_rows == 0) tc.band_rows = 256;
+  if (tc.band_sweeps == 0) tc.band_sweeps = std::min(ko.max_iter, 64);
   if ((tc.fused_threads != 256 && tc.fused_threads != 512) ||
       (tc.fused_unroll != 2 && tc.fused_unroll != 4 && tc.fused_unroll != 8) ||
-      tc.fused_max_bins < 2 || tc.band_rows < 16 || tc.band_rows % 16 != 0) {
+      tc.fused_max_bins < 2 || tc.band_rows < 16 || tc.band_rows % 16 != 0 ||
+      tc.band_sweeps < 1 || tc.band_sweeps > ko.max_iter || tc.reserved[0] || tc.reserved[1] ||
+      tc.reserved[2]) {
     delete plan;
     return DTM_EINVAL;
+  }
+  // The fused kernel holds g, x and 1/S in LDS (3 ld elements) and at most 4
+  // vectors of columns per thread of a 512-thread block.
+  {
+    const int32_t vn = dt == DTM_F32 ? 4 : 2;
+    const int32_t cap_regs = 512 * vn * 4;
+    const int32_t cap_lds = static_cast<int32_t>((150 * 1024) / (3 * dtype_size(dt)));
+    tc.fused_max_bins = std::min(tc.fused_max_bins, std::min(cap_regs, cap_lds));
   }
   plan->tiles = tc;
   plan->n_pixels = n_pixels;
@@ -207,6 +219,38 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   plan->pool_elems = acc_pool;
   plan->max_n = max_n;
   plan->max_ld = max_ld;
+
+  // Split: pixels up to fused_max_bins take the one-block fused kernel, the
+  // others the banded path (row bands x column blocks, one block each).
+  const int32_t vn = dt == DTM_F32 ? 4 : 2;
+  plan->band_threads = 256;
+  plan->band_cpt = 4;
+  const int32_t colw = plan->band_threads * vn * plan->band_cpt;
+  plan->max_n_small = plan->max_ld_small = plan->max_n_big = plan->max_ld_big = 0;
+  int64_t acc_part = 0;
+  for (int32_t q = 0; q < n_pixels; ++q) {
+    PixelMeta& m = plan->meta[q];
+    if (m.n <= tc.fused_max_bins) {
+      m.bands = 0;
+      m.big = -1;
+      m.part_off = 0;
+      plan->small_sel.push_back(q);
+      plan->max_n_small = std::max(plan->max_n_small, m.n);
+      plan->max_ld_small = std::max(plan->max_ld_small, m.ld);
+    } else {
+      m.bands = (m.n + tc.band_rows - 1) / tc.band_rows;
+      m.big = static_cast<int32_t>(plan->big_sel.size());
+      m.part_off = acc_part;
+      acc_part += static_cast<int64_t>(m.bands) * m.ld;
+      plan->big_sel.push_back(q);
+      plan->max_n_big = std::max(plan->max_n_big, m.n);
+      plan->max_ld_big = std::max(plan->max_ld_big, m.ld);
+      const int32_t cblocks = (m.n + colw - 1) / colw;
+      for (int32_t b = 0; b < m.bands; ++b)
+        for (int32_t cb = 0; cb < cblocks; ++cb) plan->items.push_back(BandItem{q, b, cb, 0});
+    }
+  }
+  plan->part_elems = acc_part;
   const size_t es = dtype_size(dt);
   size_t off = 0;
   plan->off_meta = off;
@@ -219,6 +263,18 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   off = align_up(off + 8 * static_cast<size_t>(n_pixels), 256);
   plan->off_state = off;
   off = align_up(off + sizeof(SolveState) * n_pixels, 256);
+  plan->off_small = off;
+  off = align_up(off + sizeof(int32_t) * (plan->small_sel.size() + 1), 256);
+  plan->off_big = off;
+  off = align_up(off + sizeof(int32_t) * (plan->big_sel.size() + 1), 256);
+  plan->off_items = off;
+  off = align_up(off + sizeof(BandItem) * (plan->items.size() + 1), 256);
+  plan->off_xbuf = off;
+  off = align_up(off + es * acc_vec, 256);
+  plan->off_dprev = off;
+  off = align_up(off + 8 * acc_vec, 256);
+  plan->off_part = off;
+  off = align_up(off + 8 * static_cast<size_t>(acc_part), 256);
   plan->off_pool = off;
   off = align_up(off + es * static_cast<size_t>(acc_pool), 256);
   plan->total_bytes = off;

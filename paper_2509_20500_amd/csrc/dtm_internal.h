@@ -33,8 +33,20 @@ struct PixelMeta {
   int64_t vec_off;  // offset of per-pixel vectors in the workspace (sum of ld)
   int64_t mat_off;  // offset of the pixel's matrix in the matrix pool (sum of n*ld)
   int64_t out_off;  // offset of the pixel's matrix in a caller's packed output (sum of n*n)
+  int64_t part_off; // banded pixels: offset (in doubles) of the band partial sums
+  int32_t bands;    // banded pixels: row bands (0 for pixels of the fused kernel)
+  int32_t big;      // position in the banded-pixel list, or -1
 };
-static_assert(sizeof(PixelMeta) == 88, "PixelMeta layout");
+static_assert(sizeof(PixelMeta) == 104, "PixelMeta layout");
+
+// One work item of the banded sweep: a band of rows times a block of columns
+// of one pixel.
+struct BandItem {
+  int32_t meta;      // index into the plan's PixelMeta array
+  int32_t band;      // row band
+  int32_t colblock;  // column block
+  int32_t pad;
+};
 
 // Solver options as the kernels see them.
 struct KOpts {
@@ -127,8 +139,15 @@ struct dtm_plan {
   int64_t mat_elems;   // sum n*n
   int64_t pool_elems;  // sum n*ld
   int64_t vec_elems;   // sum ld
+  // pixels of the fused one-block kernel and of the banded multi-block path
+  std::vector<int32_t> small_sel, big_sel;
+  std::vector<dtm::BandItem> items;
+  int32_t max_n_small, max_ld_small, max_n_big, max_ld_big;
+  int32_t band_threads, band_cpt;  // banded sweep block size and column chunks per thread
+  int64_t part_elems;              // doubles of band partial sums
   // workspace layout, byte offsets
   size_t off_meta, off_pool, off_colf, off_invs, off_scal, off_state, total_bytes;
+  size_t off_small, off_big, off_items, off_xbuf, off_dprev, off_part;
   void* ws;            // bound workspace (device), or nullptr
   size_t ws_bytes;
 };

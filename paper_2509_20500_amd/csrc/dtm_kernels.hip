@@ -49,11 +49,13 @@ __global__ __launch_bounds__(BT) void k_tables(const PixelMeta* metas, PixelMeta
 // Row sums of the base matrix: one wavefront per row k; writes 1 / S_k.
 template <typename T, int BT>
 __global__ __launch_bounds__(BT) void k_rowsums(const PixelMeta* metas, PixelMeta one,
-                                                const T* colf, const double* scal, T* invs) {
-  const PixelMeta m = load_meta(metas, one, blockIdx.y);
+                                                const int32_t* sel, const T* colf,
+                                                const double* scal, T* invs) {
+  const int q = sel ? sel[blockIdx.y] : blockIdx.y;
+  const PixelMeta m = load_meta(metas, one, q);
   const int k = blockIdx.x * (BT / kWave) + threadIdx.x / kWave;
   if (k >= m.n) return;
-  const T c = static_cast<T>(scal[blockIdx.y]);
+  const T c = static_cast<T>(scal[q]);
   const double s = wave_row_sum<T>(colf + m.vec_off, m.n, k, c);
   if ((threadIdx.x % kWave) == 0) invs[m.vec_off + k] = static_cast<T>(1.0 / s);
 }
@@ -369,6 +371,7 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
                                                     const T* __restrict__ x0_packed,
                                                     T* __restrict__ pi_packed,
                                                     dtm_solve_info* __restrict__ infos,
+                                                    const int32_t* __restrict__ sel,
                                                     KOpts o, int lds_ld) {
   using V = typename Vec<T>::type;
   constexpr int VN = Vec<T>::n;
@@ -379,12 +382,13 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
   T* invs = xs + lds_ld;
   double* red = reinterpret_cast<double*>(invs + lds_ld);
 
-  const PixelMeta m = metas[blockIdx.x];
+  const int pq = sel[blockIdx.x];
+  const PixelMeta m = metas[pq];
   const int n = m.n;
   const int64_t ld = m.ld;
   const int tid = threadIdx.x;
   T* mat = pool + m.mat_off;
-  const T c = static_cast<T>(scal[blockIdx.x]);
+  const T c = static_cast<T>(scal[pq]);
 
   // ---- a1 tables into LDS (g is zero-padded to ld) -------------------------
   for (int j = tid; j < m.ld; j += BT) g[j] = colf[m.vec_off + j];
@@ -536,6 +540,204 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
   // ---- outputs --------------------------------------------------------------
   for (int j = tid; j < n; j += BT) pi_packed[m.pi_off + j] = xs[j];
   if (tid == 0) infos[m.index] = make_info(st);
+}
+
+// ============================================================================
+// Banded path for pixels too large for one block: a sweep is one launch over
+// (pixel, row band, column block) items, each writing float64 partial sums of
+// x P~ over its band; a combine launch (one block per pixel) adds the bands
+// in order, normalises and applies the stop rule.  The first sweep builds the
+// band's rows (shift fused) while it accumulates.  Launch boundaries order
+// the steps, so no block ever waits for another.
+// ============================================================================
+
+template <typename T, int BT>
+__global__ __launch_bounds__(BT) void k_band_init(const PixelMeta* __restrict__ metas,
+                                                  const int32_t* __restrict__ big,
+                                                  const T* __restrict__ x0_packed,
+                                                  T* __restrict__ xbuf, double* __restrict__ dprev,
+                                                  SolveState* __restrict__ states) {
+  __shared__ double red[3 * BT / kWave];
+  const int q = big[blockIdx.x];
+  const PixelMeta m = metas[q];
+  const int n = m.n;
+  double sum = 0.0, bad = 0.0;
+  if (x0_packed) {
+    for (int j = threadIdx.x; j < n; j += BT) {
+      const double v = static_cast<double>(x0_packed[m.pi_off + j]);
+      if (!(v >= 0.0) || !isfinite(v)) bad += 1.0;
+      else sum += v;
+    }
+  }
+  block_sum2<BT>(sum, bad, red);
+  const bool warm = x0_packed && bad == 0.0 && sum > 0.0 && isfinite(sum);
+  for (int j = threadIdx.x; j < n; j += BT) {
+    xbuf[m.vec_off + j] =
+        warm ? static_cast<T>(static_cast<double>(x0_packed[m.pi_off + j]) / sum) : static_cast<T>(1.0 / n);
+    dprev[m.vec_off + j] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    SolveState st;
+    stop_init(st.s, warm ? 1 : 0, (x0_packed && !warm) ? DTM_INFO_WARM_REJECTED : 0);
+    st.sum_y = 0.0;
+    st.pad = 0.0;
+    states[q] = st;
+  }
+}
+
+template <typename T, int BT, int CPT, int U>
+__global__ __launch_bounds__(BT) void k_band_sweep(const PixelMeta* __restrict__ metas,
+                                                   const BandItem* __restrict__ items,
+                                                   const T* __restrict__ colf,
+                                                   const double* __restrict__ scal,
+                                                   const T* __restrict__ invs,
+                                                   T* __restrict__ pool,
+                                                   const T* __restrict__ xbuf,
+                                                   const SolveState* __restrict__ states,
+                                                   double* __restrict__ part, int band_rows,
+                                                   int first) {
+  using V = typename Vec<T>::type;
+  constexpr int VN = Vec<T>::n;
+  constexpr int UE = (U * CPT <= 8) ? U : (8 / CPT > 0 ? 8 / CPT : 1);
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* xs = reinterpret_cast<T*>(smem);
+  const BandItem it = items[blockIdx.x];
+  const PixelMeta m = metas[it.meta];
+  const StopState& st = states[it.meta].s;
+  if (st.done) return;
+  const bool check = st.check_next != 0;
+  const int n = m.n;
+  const int64_t ld = m.ld;
+  const int i0 = it.band * band_rows;
+  const int nr = min(band_rows, n - i0);
+  const int tid = threadIdx.x;
+  for (int r = tid; r < nr; r += BT) xs[r] = xbuf[m.vec_off + i0 + r];
+  __syncthreads();
+  const int cbase = it.colblock * (BT * VN * CPT);
+  int jc[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int j0 = cbase + (tid + BT * q) * VN;
+    jc[q] = j0 < n ? j0 : 0;
+  }
+  T* mat = pool + m.mat_off + static_cast<int64_t>(i0) * ld;
+  T acc[CPT][VN], cmp[CPT][VN];
+  double accd[CPT][VN], dd0[CPT][VN];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q)
+#pragma unroll
+    for (int e = 0; e < VN; ++e) {
+      acc[q][e] = cmp[q][e] = T(0);
+      accd[q][e] = dd0[q][e] = 0.0;
+    }
+  if (first) {
+    const T c = static_cast<T>(scal[it.meta]);
+    T gr[CPT][VN];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int j0 = cbase + (tid + BT * q) * VN;
+#pragma unroll
+      for (int e = 0; e < VN; ++e) gr[q][e] = (j0 < n) ? colf[m.vec_off + j0 + e] : T(0);
+    }
+    for (int r = 0; r < nr; ++r) {
+      const int i = i0 + r;
+      int k = i + m.l;
+      if (k >= n) k -= n;
+      const T s = invs[m.vec_off + k];
+      const T xi = xs[r];
+      T* row = mat + static_cast<int64_t>(r) * ld;
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int j0 = cbase + (tid + BT * q) * VN;
+        V v;
+#pragma unroll
+        for (int e = 0; e < VN; ++e) {
+          v[e] = gr[q][e] * ((j0 + e) < k ? c : T(1)) * s;
+          comp_add(acc[q][e], cmp[q][e], xi * v[e]);
+        }
+        if (j0 < n) __builtin_nontemporal_store(v, reinterpret_cast<V*>(row + j0));
+      }
+    }
+  } else if (!check) {
+    sweep_rows<T, BT, CPT, UE, false>(mat, ld, nr, jc, xs, acc, cmp);
+  } else {
+    sweep_rows<T, BT, CPT, UE, true>(mat, ld, nr, jc, xs, accd, dd0);
+  }
+  double* out = part + m.part_off + static_cast<int64_t>(it.band) * ld;
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int j0 = cbase + (tid + BT * q) * VN;
+#pragma unroll
+    for (int e = 0; e < VN; ++e)
+      if (j0 + e < n)
+        out[j0 + e] = check ? accd[q][e] : static_cast<double>(acc[q][e]) - static_cast<double>(cmp[q][e]);
+  }
+}
+
+template <typename T, int BT>
+__global__ __launch_bounds__(BT) void k_band_combine(const PixelMeta* __restrict__ metas,
+                                                     const int32_t* __restrict__ big,
+                                                     const double* __restrict__ part,
+                                                     T* __restrict__ xbuf, double* __restrict__ dprev,
+                                                     SolveState* __restrict__ states,
+                                                     T* __restrict__ pi_packed,
+                                                     dtm_solve_info* __restrict__ infos, KOpts o,
+                                                     int last) {
+  __shared__ double red[3 * BT / kWave];
+  const int q = big[blockIdx.x];
+  const PixelMeta m = metas[q];
+  StopState s = states[q].s;
+  if (s.done) return;
+  const bool was_check = s.check_next != 0;
+  const int n = m.n;
+  const double* pp = part + m.part_off;
+  T* x = xbuf + m.vec_off;
+  double* dp = dprev + m.vec_off;
+  double sy = 0.0, rs = 0.0;
+  for (int j = threadIdx.x; j < n; j += BT) {
+    double y = 0.0;
+    for (int b = 0; b < m.bands; ++b) y += pp[static_cast<int64_t>(b) * m.ld + j];
+    sy += y;
+    rs += fabs(y - static_cast<double>(x[j]));
+  }
+  block_sum2<BT>(sy, rs, red);
+  const double inv = 1.0 / sy;
+  double ch = 0.0, dd = 0.0, ddp = 0.0;
+  for (int j = threadIdx.x; j < n; j += BT) {
+    double y = 0.0;
+    for (int b = 0; b < m.bands; ++b) y += pp[static_cast<int64_t>(b) * m.ld + j];
+    const T xn = static_cast<T>(y * inv);
+    const double dj = static_cast<double>(xn) - static_cast<double>(x[j]);
+    ch += fabs(dj);
+    dd += dj * dj;
+    ddp += dj * dp[j];
+    dp[j] = dj;
+    x[j] = xn;  // thread-private index: read above by this thread only
+  }
+  block_sum3<BT>(ch, dd, ddp, red);
+  const bool restart = stop_update(s, o, ch, dd, ddp, rs, was_check,
+                                   sizeof(T) == 4 ? 5.9604644775390625e-8 : 1.1102230246251565e-16);
+  if (restart) {
+    for (int j = threadIdx.x; j < n; j += BT) {
+      x[j] = static_cast<T>(1.0 / n);
+      dp[j] = 0.0;
+    }
+  }
+  if (!s.done && last) {  // out of launched sweeps
+    s.done = 1;
+    s.status = DTM_ENOTCONV;
+  }
+  if (s.done) {
+    for (int j = threadIdx.x; j < n; j += BT) pi_packed[m.pi_off + j] = x[j];
+    if (threadIdx.x == 0) infos[m.index] = make_info(s);
+  }
+  if (threadIdx.x == 0) {
+    SolveState out;
+    out.s = s;
+    out.sum_y = sy;
+    out.pad = 0.0;
+    states[q] = out;
+  }
 }
 
 // ============================================================================
@@ -835,11 +1037,11 @@ int launch_tables(const PixelMeta* metas, const PixelMeta& one, int np, T* colf,
 }
 
 template <typename T>
-int launch_rowsums(const PixelMeta* metas, const PixelMeta& one, int np, int max_n, const T* colf,
-                   const double* scal, T* invs, hipStream_t st) {
+int launch_rowsums(const PixelMeta* metas, const PixelMeta& one, const int32_t* sel, int np,
+                   int max_n, const T* colf, const double* scal, T* invs, hipStream_t st) {
   const int rows_per_block = kBT / kWave;
   dim3 grid((max_n + rows_per_block - 1) / rows_per_block, np);
-  hipLaunchKernelGGL((k_rowsums<T, kBT>), grid, dim3(kBT), 0, st, metas, one, colf, scal, invs);
+  hipLaunchKernelGGL((k_rowsums<T, kBT>), grid, dim3(kBT), 0, st, metas, one, sel, colf, scal, invs);
   return last_launch();
 }
 
@@ -877,7 +1079,7 @@ int single_prepare(const dtm_scene& s, dtm_dtype dt, void* ws, size_t ws_bytes, 
   double* scal = reinterpret_cast<double*>(w + L.off_scal);
   int rc = launch_tables<T>(nullptr, m, 1, colf, scal, lam, F, st);
   if (rc) return rc;
-  rc = launch_rowsums<T>(nullptr, m, 1, m.n, colf, scal, invs, st);
+  rc = launch_rowsums<T>(nullptr, m, nullptr, 1, m.n, colf, scal, invs, st);
   *m_out = m;
   *L_out = L;
   return rc;
@@ -954,12 +1156,12 @@ int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_e
 
 // Fused batched solve: kernel instance by (dtype, block, columns per thread).
 template <typename T, int BT, int CPT>
-int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, int count,
-                     const T* colf, const double* scal, T* pool, const T* x0, T* pi,
+int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, const int32_t* sel,
+                     int count, const T* colf, const double* scal, T* pool, const T* x0, T* pi,
                      dtm_solve_info* infos, int lds_ld, hipStream_t st) {
   const size_t lds = 3 * sizeof(T) * static_cast<size_t>(lds_ld) + 3 * BT / kWave * sizeof(double);
-  void (*kern)(const PixelMeta*, const T*, const double*, T*, const T*, T*, dtm_solve_info*, KOpts,
-               int) = nullptr;
+  void (*kern)(const PixelMeta*, const T*, const double*, T*, const T*, T*, dtm_solve_info*,
+               const int32_t*, KOpts, int) = nullptr;
   switch (unroll) {
     case 2: kern = k_solve_fused<T, BT, CPT, 2>; break;
     case 4: kern = k_solve_fused<T, BT, CPT, 4>; break;
@@ -972,22 +1174,25 @@ int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, i
       return DTM_EHIP;
   }
   hipLaunchKernelGGL(kern, dim3(count), dim3(BT), lds, st, metas, colf, scal, pool, x0, pi, infos,
-                     plan->kopts, lds_ld);
+                     sel, plan->kopts, lds_ld);
   return last_launch();
 }
 
 template <typename T, int BT>
-int launch_fused_bt(const dtm_plan* plan, int cpt, const PixelMeta* metas, int count,
-                    const T* colf, const double* scal, T* pool, const T* x0, T* pi,
+int launch_fused_bt(const dtm_plan* plan, int cpt, const PixelMeta* metas, const int32_t* sel,
+                    int count, const T* colf, const double* scal, T* pool, const T* x0, T* pi,
                     dtm_solve_info* infos, int lds_ld, hipStream_t st) {
   const int u = plan->tiles.fused_unroll;
   switch (cpt) {
     case 1:
-      return launch_fused_cpt<T, BT, 1>(plan, u, metas, count, colf, scal, pool, x0, pi, infos, lds_ld, st);
+      return launch_fused_cpt<T, BT, 1>(plan, u, metas, sel, count, colf, scal, pool, x0, pi, infos,
+                                        lds_ld, st);
     case 2:
-      return launch_fused_cpt<T, BT, 2>(plan, u, metas, count, colf, scal, pool, x0, pi, infos, lds_ld, st);
+      return launch_fused_cpt<T, BT, 2>(plan, u, metas, sel, count, colf, scal, pool, x0, pi, infos,
+                                        lds_ld, st);
     case 4:
-      return launch_fused_cpt<T, BT, 4>(plan, u, metas, count, colf, scal, pool, x0, pi, infos, lds_ld, st);
+      return launch_fused_cpt<T, BT, 4>(plan, u, metas, sel, count, colf, scal, pool, x0, pi, infos,
+                                        lds_ld, st);
     default:
       return DTM_ENOTSUP;
   }
@@ -999,7 +1204,7 @@ template <typename T>
 int launch_refine(const dtm_plan* plan, const PixelMeta* metas, T* pi, dtm_solve_info* infos,
                   hipStream_t st) {
   constexpr int BT = 512, QMAX = 16;
-  if (plan->max_n > BT * QMAX) return DTM_ENOTSUP;
+  if (plan->max_n > BT * QMAX) return DTM_OK;  // wider pixels keep their STALLED status
   const size_t lds = 2 * sizeof(double) * static_cast<size_t>(plan->max_ld) + 3 * BT / kWave * sizeof(double);
   auto kern = k_refine_f64<BT, QMAX, T>;
   if (lds > 64 * 1024) {
@@ -1013,41 +1218,90 @@ int launch_refine(const dtm_plan* plan, const PixelMeta* metas, T* pi, dtm_solve
   return last_launch();
 }
 
+// Banded path: init, then band_sweeps x (sweep over all items, combine).
+template <typename T>
+int launch_banded(const dtm_plan* plan, const PixelMeta* metas, const T* colf, const double* scal,
+                  const T* invs, T* pool, const T* x0, T* pi, dtm_solve_info* infos, hipStream_t st) {
+  constexpr int BT = 256, CPT = 4;
+  char* w = static_cast<char*>(plan->ws);
+  const int32_t* big = reinterpret_cast<const int32_t*>(w + plan->off_big);
+  const BandItem* items = reinterpret_cast<const BandItem*>(w + plan->off_items);
+  T* xbuf = reinterpret_cast<T*>(w + plan->off_xbuf);
+  double* dprev = reinterpret_cast<double*>(w + plan->off_dprev);
+  double* part = reinterpret_cast<double*>(w + plan->off_part);
+  SolveState* states = reinterpret_cast<SolveState*>(w + plan->off_state);
+  const int nbig = static_cast<int>(plan->big_sel.size());
+  const int nitems = static_cast<int>(plan->items.size());
+  const size_t lds = sizeof(T) * static_cast<size_t>(plan->tiles.band_rows);
+  hipLaunchKernelGGL((k_band_init<T, BT>), dim3(nbig), dim3(BT), 0, st, metas, big, x0, xbuf, dprev,
+                     states);
+  int rc = last_launch();
+  if (rc) return rc;
+  void (*sweep)(const PixelMeta*, const BandItem*, const T*, const double*, const T*, T*, const T*,
+                const SolveState*, double*, int, int) = nullptr;
+  switch (plan->tiles.fused_unroll) {
+    case 2: sweep = k_band_sweep<T, BT, CPT, 2>; break;
+    case 4: sweep = k_band_sweep<T, BT, CPT, 4>; break;
+    default: sweep = k_band_sweep<T, BT, CPT, 8>; break;
+  }
+  for (int t = 0; t < plan->tiles.band_sweeps; ++t) {
+    hipLaunchKernelGGL(sweep, dim3(nitems), dim3(BT), lds, st, metas, items, colf, scal, invs, pool,
+                       xbuf, states, part, plan->tiles.band_rows, t == 0 ? 1 : 0);
+    hipLaunchKernelGGL((k_band_combine<T, BT>), dim3(nbig), dim3(BT), 0, st, metas, big, part, xbuf,
+                       dprev, states, pi, infos, plan->kopts, t == plan->tiles.band_sweeps - 1 ? 1 : 0);
+    rc = last_launch();
+    if (rc) return rc;
+  }
+  return DTM_OK;
+}
+
 template <typename T>
 int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info* infos,
                   hipStream_t st) {
   char* w = static_cast<char*>(plan->ws);
   const PixelMeta* metas = reinterpret_cast<const PixelMeta*>(w + plan->off_meta);
+  const int32_t* small = reinterpret_cast<const int32_t*>(w + plan->off_small);
+  const int32_t* big = reinterpret_cast<const int32_t*>(w + plan->off_big);
   T* pool = reinterpret_cast<T*>(w + plan->off_pool);
-  constexpr int VN = Vec<T>::n;
-  // columns per thread covering the largest pixel; at most 4 chunks of
-  // VN columns per thread (more would spill), so wide pixels take 512 threads
-  int bt = plan->tiles.fused_threads;
-  int cpt = (plan->max_ld + bt * VN - 1) / (bt * VN);
-  if (cpt > 4 && bt == 256) {
-    bt = 512;
-    cpt = (plan->max_ld + bt * VN - 1) / (bt * VN);
-  }
-  cpt = cpt <= 1 ? 1 : cpt <= 2 ? 2 : 4;
-  if (cpt * bt * VN < plan->max_ld) return DTM_ENOTSUP;
-  const int lds_ld = plan->max_ld;
-  const size_t lds = 3 * sizeof(T) * static_cast<size_t>(lds_ld) + 3 * bt / kWave * sizeof(double);
-  if (lds > 160 * 1024) return DTM_ENOTSUP;
+  T* colf = reinterpret_cast<T*>(w + plan->off_colf);
+  T* invs = reinterpret_cast<T*>(w + plan->off_invs);
+  double* scal = reinterpret_cast<double*>(w + plan->off_scal);
   const T* x0t = static_cast<const T*>(x0);
   T* pit = static_cast<T*>(pi);
-  T* colf = reinterpret_cast<T*>(w + plan->off_colf);
-  double* scal = reinterpret_cast<double*>(w + plan->off_scal);
+  constexpr int VN = Vec<T>::n;
   PixelMeta dummy;
   std::memset(&dummy, 0, sizeof(dummy));
   int rc = launch_tables<T>(metas, dummy, plan->n_pixels, colf, scal, nullptr, nullptr, st);
   if (rc) return rc;
-  if (bt == 512)
-    rc = launch_fused_bt<T, 512>(plan, cpt, metas, plan->n_pixels, colf, scal, pool, x0t, pit, infos,
-                                 lds_ld, st);
-  else
-    rc = launch_fused_bt<T, 256>(plan, cpt, metas, plan->n_pixels, colf, scal, pool, x0t, pit, infos,
-                                 lds_ld, st);
-  if (rc || sizeof(T) == 8) return rc;
+  const int nsmall = static_cast<int>(plan->small_sel.size());
+  const int nbig = static_cast<int>(plan->big_sel.size());
+  if (nsmall > 0) {
+    // columns per thread covering the largest fused pixel; at most 4 vectors
+    // of columns per thread (more would spill), so wide pixels take 512 threads
+    int bt = plan->tiles.fused_threads;
+    int cpt = (plan->max_ld_small + bt * VN - 1) / (bt * VN);
+    if (cpt > 4 && bt == 256) {
+      bt = 512;
+      cpt = (plan->max_ld_small + bt * VN - 1) / (bt * VN);
+    }
+    cpt = cpt <= 1 ? 1 : cpt <= 2 ? 2 : 4;
+    if (cpt * bt * VN < plan->max_ld_small) return DTM_ENOTSUP;
+    const int lds_ld = plan->max_ld_small;
+    if (bt == 512)
+      rc = launch_fused_bt<T, 512>(plan, cpt, metas, small, nsmall, colf, scal, pool, x0t, pit, infos,
+                                   lds_ld, st);
+    else
+      rc = launch_fused_bt<T, 256>(plan, cpt, metas, small, nsmall, colf, scal, pool, x0t, pit, infos,
+                                   lds_ld, st);
+    if (rc) return rc;
+  }
+  if (nbig > 0) {
+    rc = launch_rowsums<T>(metas, dummy, big, nbig, plan->max_n_big, colf, scal, invs, st);
+    if (rc) return rc;
+    rc = launch_banded<T>(plan, metas, colf, scal, invs, pool, x0t, pit, infos, st);
+    if (rc) return rc;
+  }
+  if (sizeof(T) == 8) return DTM_OK;
   return launch_refine<T>(plan, metas, pit, infos, st);
 }
 
@@ -1062,7 +1316,7 @@ int batched_tables_rowsums(const dtm_plan* plan, hipStream_t st) {
   std::memset(&dummy, 0, sizeof(dummy));
   int rc = launch_tables<T>(metas, dummy, plan->n_pixels, colf, scal, nullptr, nullptr, st);
   if (rc) return rc;
-  return launch_rowsums<T>(metas, dummy, plan->n_pixels, plan->max_n, colf, scal, invs, st);
+  return launch_rowsums<T>(metas, dummy, nullptr, plan->n_pixels, plan->max_n, colf, scal, invs, st);
 }
 
 template <typename T>
@@ -1178,6 +1432,18 @@ int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes, d
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(workspace_dev);
   if (hipMemcpyAsync(w + plan->off_meta, plan->meta.data(), sizeof(PixelMeta) * plan->meta.size(),
+                     hipMemcpyHostToDevice, st) != hipSuccess)
+    return DTM_EHIP;
+  if (!plan->small_sel.empty() &&
+      hipMemcpyAsync(w + plan->off_small, plan->small_sel.data(),
+                     sizeof(int32_t) * plan->small_sel.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+    return DTM_EHIP;
+  if (!plan->big_sel.empty() &&
+      hipMemcpyAsync(w + plan->off_big, plan->big_sel.data(), sizeof(int32_t) * plan->big_sel.size(),
+                     hipMemcpyHostToDevice, st) != hipSuccess)
+    return DTM_EHIP;
+  if (!plan->items.empty() &&
+      hipMemcpyAsync(w + plan->off_items, plan->items.data(), sizeof(BandItem) * plan->items.size(),
                      hipMemcpyHostToDevice, st) != hipSuccess)
     return DTM_EHIP;
   if (hipStreamSynchronize(st) != hipSuccess) return DTM_EHIP;

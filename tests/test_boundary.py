@@ -42,7 +42,7 @@ def test_struct_layouts(d):
     assert ctypes.sizeof(d.Scene) == sc.SCENE_DTYPE.itemsize == 56
     assert ctypes.sizeof(d.SolveOpts) == 32
     assert ctypes.sizeof(d.SolveInfo) == 40
-    assert ctypes.sizeof(d.TileConfig) == 16
+    assert ctypes.sizeof(d.TileConfig) == 32
     assert d.dtm_version() >= 10000
 
 
@@ -132,7 +132,7 @@ def test_plan_rejects_bad_inputs(d):
     with pytest.raises(d.DtmError):
         d.Plan(scenes, "f32")
     with pytest.raises(d.DtmError):
-        d.Plan(sc.batched_uniform(4), "f32", tiles=d.TileConfig(300, 0, 0, 0))
+        d.Plan(sc.batched_uniform(4), "f32", tiles=d.tiles(fused_threads=300))
     # binding needs a big enough, 256-byte aligned workspace (checked on the host)
     plan = d.Plan(sc.batched_uniform(4), "f32")
     assert d.lib().dtm_plan_bind(plan.handle, 1 << 20, plan.workspace_bytes - 1, None) == d.DTM_ENOSPACE

@@ -301,3 +301,48 @@ def test_float32_paper_grid_with_refinement():
         assert err <= TOL_F32, (p, s, err, info[p])
     refined = (info["flags"] & d.DTM_INFO_REFINED) != 0
     print("refined pixels:", int(refined.sum()), "of", len(scenes))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_banded_path_ragged(dt):
+    """Pixels above fused_max_bins take the banded multi-block path: ragged
+    row bands (64 rows) and, past 4096 (float32) or 2048 (float64) columns,
+    several column blocks; mixed with fused pixels in one plan."""
+    d = lib()
+    rng = np.random.default_rng(81)
+    ns = [300, 1000, 2500, 257, 64, 5000 if dt == "f32" else 3000, 777]
+    scenes = np.concatenate([
+        sc.scene(period=float(rng.uniform(50, 200)), dead_time=float(rng.uniform(5, 300)),
+                 center=float(rng.uniform(10, 40)), sigma=float(rng.uniform(0.2, 2.0)),
+                 signal=float(rng.uniform(0.1, 4)), background=float(rng.uniform(0.05, 1.5)), n_bins=n)
+        for n in ns])
+    tiles = d.tiles(fused_max_bins=256, band_rows=64)
+    pi, info, off = run_batched(scenes, dt, tiles=tiles)
+    tol = TOL_F64 if dt == "f64" else TOL_F32
+    assert np.all(info["status"] == 0), info
+    for p, (s, v) in enumerate(zip(scenes, split(pi, off))):
+        err = np.abs(v - oracle_pi(s)).sum()
+        assert err <= tol, (p, int(s["n_bins"]), err, info[p])
+
+
+def test_banded_sweep_cap_is_soft():
+    """A banded pixel that needs more sweeps than were launched ends with
+    DTM_ENOTCONV and its last iterate."""
+    d = lib()
+    scenes = sc.paper_grid(levels=(9.0,), dead_time=75.0, n_bins=512)
+    pi, info, off = run_batched(scenes, "f32", tiles=d.tiles(fused_max_bins=256, band_sweeps=3))
+    assert np.all(info["status"] == d.DTM_ENOTCONV)
+    assert np.all(info["iterations"] == 3)
+    assert np.all(np.isfinite(pi)) and abs(pi.sum() - 1) < 1e-5
+
+
+def test_banded_matches_fused_bitwise_pattern():
+    """The banded and fused paths solve the same pixels to the same
+    tolerance (they differ only in summation order)."""
+    d = lib()
+    scenes = sc.batched_uniform(24, seed=91)
+    a, ia, off = run_batched(scenes, "f32")
+    b, ib, _ = run_batched(scenes, "f32", tiles=d.tiles(fused_max_bins=512, band_rows=128))
+    assert np.all(ia["status"] == 0) and np.all(ib["status"] == 0)
+    for p in range(len(scenes)):
+        assert np.abs(a[off[p]:off[p + 1]] - b[off[p]:off[p + 1]]).sum() < 1e-6
