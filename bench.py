@@ -90,7 +90,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--pixels", type=int, default=4096)
+    ap.add_argument("--workload", default="batched_uniform", choices=["batched_uniform", "batched_uneven"])
+    ap.add_argument("--pixels", type=int, default=0, help="0 = the workload's own count")
+    ap.add_argument("--graph", action="store_true", help="replay the solve as a captured HIP graph")
+    ap.add_argument("--autotune", action="store_true", help="pick tile shapes by timing candidates")
     ap.add_argument("--check", type=int, default=16, help="pixels compared with the oracle after timing")
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,24 +116,38 @@ def main():
 
     dtm.lib()
     torch.cuda.set_device(0)
-    scenes = sc.batched_uniform(n_pixels=args.pixels)
-    tiles = dtm.tiles(args.threads, args.unroll) if (args.threads or args.unroll) else None
-    plan = dtm.Plan(scenes, args.dtype, dtm.opts(tol=1e-6), tiles)
+    uneven = args.workload == "batched_uneven"
+    if uneven:
+        scenes = sc.batched_uneven(n_pixels=args.pixels or 2048)
+    else:
+        scenes = sc.batched_uniform(n_pixels=args.pixels or 4096)
+    sopts = dtm.opts(tol=1e-6)
+    tune_report = None
+    if args.threads or args.unroll:
+        tiles = dtm.tiles(args.threads, args.unroll)
+    elif args.autotune:
+        from paper_2509_20500_amd.autotune import autotune
+        tiles, tune_report = autotune(scenes, args.dtype, sopts)
+    else:
+        tiles = None
+    plan = dtm.Plan(scenes, args.dtype, sopts, tiles)
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     plan.bind(ws)
     tdt = torch.float32 if args.dtype == "f32" else torch.float64
     pi = torch.empty(plan.pi_elems, dtype=tdt, device="cuda")
     infos = torch.zeros(plan.n_pixels * 40, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
+    graph = plan.graph(pi, infos) if args.graph else None
+    step = graph.launch if graph else (lambda: plan.solve(pi, infos))
 
     for _ in range(args.warmup):
-        plan.solve(pi, infos)
+        step()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record(stream)
     for _ in range(args.steps):
-        plan.solve(pi, infos)
+        step()
     end.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
@@ -145,16 +162,25 @@ def main():
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     value = plan.n_pixels / (ms_step * 1e-3)
 
-    # correctness gate on sampled pixels
+    # correctness gate on sampled pixels (those the dense oracle solves fast)
     from oracle import dtm as odtm
     got = pi.cpu().numpy().astype(np.float64)
     off = plan.pi_offsets
     rng = np.random.default_rng(0)
+    small = np.flatnonzero(scenes["n_bins"] <= 2048)
     l1 = 0.0
-    for p in rng.choice(plan.n_pixels, min(args.check, plan.n_pixels), replace=False):
+    for p in rng.choice(small, min(args.check, small.size), replace=False):
         ref = odtm.stationary_solve(odtm.transition_matrix(scenes[p]))
         l1 = max(l1, float(np.abs(got[off[p]:off[p + 1]] - ref).sum()))
 
+    if uneven:
+        desc = ("2048 pixels, N from {512,1024,2048,4096,8192} weighted 16:8:4:2:1, period U[50,200] ns, "
+                "dead time period*U[0.2,1.5], sigma U[0.1,1] ns, depth U[5,period-5], "
+                "S log-U[0.05,5], B log-U[0.01,1], seed 4; ")
+    else:
+        desc = ("64x64 pixels, N=1024 bins over 100 ns, dead time 50 ns, sigma 0.4 ns, "
+                "depth U[5,95] ns, S log-U[0.05,5], B log-U[0.01,1], seed 3; ")
+    desc += f"{args.dtype} build+sweeps, float64 check, L1<=1e-6" + ("; HIP graph" if graph else "")
     out = {
         "metric": "stationary-PDF pixels/s at N=1024, L1<=1e-6 vs FP64 oracle; % HBM roofline",
         "value": value,
@@ -169,12 +195,11 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {
-            "workload": "64x64 pixels, N=1024 bins over 100 ns, dead time 50 ns, sigma 0.4 ns, "
-                        "depth U[5,95] ns, S log-U[0.05,5], B log-U[0.01,1], seed 3; "
-                        f"{args.dtype} build+sweeps, float64 check, L1<=1e-6",
+            "workload": desc,
             "pixels": plan.n_pixels,
-            "n_bins": 1024,
-            "tiles": {"threads": plan.tiles.fused_threads, "unroll": plan.tiles.fused_unroll},
+            "n_bins": 1024 if not uneven else "512..8192",
+            "tiles": plan.tiles.as_dict(),
+            "graph": bool(graph),
         },
         "roofline": {
             "bound": "hbm",
@@ -183,20 +208,25 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "k_solve_fused",
+            "kernel": "k_solve_fused" if not uneven else "k_solve_fused + k_band_sweep",
             "alg_bytes_per_launch": alg_bytes,
         },
         "iterations": {"mean": float(info["iterations"].mean()), "max": int(info["iterations"].max()),
                        "min": int(info["iterations"].min())},
         "all_converged": bool(np.all(info["status"] == 0)),
+        "refined_pixels": int(np.sum((info["flags"] & dtm.DTM_INFO_REFINED) != 0)),
         "max_residual_l1": float(info["residual_l1"].max()),
         "l1_vs_oracle_sampled_max": l1,
     }
+    if tune_report is not None:
+        out["autotune"] = {"cached": tune_report["cached"], "ms": tune_report["ms"]}
+    if graph:
+        graph.close()
     plan.close()
     del ws
     if args.calibrate:
         out["copy_calibration"] = copy_calibration()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not uneven:
         out["cpu_baseline"] = cpu_baseline(scenes, args.cpu_sample)
     print(json.dumps(out), flush=True)
 

@@ -225,6 +225,17 @@ int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes,
 int dtm_solve_batched(const dtm_plan* plan, const void* x0_packed_dev, void* pi_packed_dev,
                       dtm_solve_info* infos_dev, dtm_stream_t stream);
 
+/* HIP graph of one dtm_solve_batched call: every launch of the solve is
+ * captured once and replayed by dtm_graph_launch, which saves the per-launch
+ * host cost of the banded path's sweep loop.  The plan, its workspace and the
+ * three buffers must stay valid while the graph exists; the replay reads and
+ * writes exactly what the captured call does.  Synchronises `stream`. */
+typedef struct dtm_graph dtm_graph; /* opaque host object */
+int dtm_graph_create(const dtm_plan* plan, const void* x0_packed_dev, void* pi_packed_dev,
+                     dtm_solve_info* infos_dev, dtm_stream_t stream, dtm_graph** graph_out);
+int dtm_graph_launch(dtm_graph* graph, dtm_stream_t stream);
+void dtm_graph_destroy(dtm_graph* graph);
+
 /* Batched a2 / a3 / fused a2+a3, writing every pixel's n_b x n_b matrix
  * packed by mat_offsets (ld = n_b).  Launch only. */
 int dtm_build_base_batched(const dtm_plan* plan, void* P_packed_dev, dtm_stream_t stream);

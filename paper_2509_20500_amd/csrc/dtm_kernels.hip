@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
 
 #include "dtm_device.hpp"
 #include "dtm_internal.h"
@@ -1460,6 +1461,63 @@ int dtm_solve_batched(const dtm_plan* plan, const void* x0_packed_dev, void* pi_
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (plan->dt == DTM_F32) return batched_solve<float>(plan, x0_packed_dev, pi_packed_dev, infos_dev, st);
   return batched_solve<double>(plan, x0_packed_dev, pi_packed_dev, infos_dev, st);
+}
+
+struct dtm_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+int dtm_graph_create(const dtm_plan* plan, const void* x0_packed_dev, void* pi_packed_dev,
+                     dtm_solve_info* infos_dev, dtm_stream_t stream, dtm_graph** graph_out) {
+  if (!graph_out) return DTM_EINVAL;
+  *graph_out = nullptr;
+  if (!plan || !plan->ws || !pi_packed_dev || !infos_dev) return DTM_EINVAL;
+  const size_t es = dtype_size(plan->dt);
+  if (overlaps(pi_packed_dev, es * plan->pi_elems, plan->ws, plan->total_bytes)) return DTM_EALIAS;
+  hipStream_t user = static_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(user) != hipSuccess) return DTM_EHIP;
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return DTM_EHIP;
+  int rc = DTM_OK;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    hipStreamDestroy(cs);
+    return DTM_EHIP;
+  }
+  rc = plan->dt == DTM_F32 ? batched_solve<float>(plan, x0_packed_dev, pi_packed_dev, infos_dev, cs)
+                           : batched_solve<double>(plan, x0_packed_dev, pi_packed_dev, infos_dev, cs);
+  const hipError_t ec = hipStreamEndCapture(cs, &g);
+  hipStreamDestroy(cs);
+  if (rc != DTM_OK || ec != hipSuccess || !g) {
+    if (g) hipGraphDestroy(g);
+    return rc != DTM_OK ? rc : DTM_EHIP;
+  }
+  hipGraphExec_t ex = nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(g);
+    return DTM_EHIP;
+  }
+  dtm_graph* out = new (std::nothrow) dtm_graph{g, ex};
+  if (!out) {
+    hipGraphExecDestroy(ex);
+    hipGraphDestroy(g);
+    return DTM_EINVAL;
+  }
+  *graph_out = out;
+  return DTM_OK;
+}
+
+int dtm_graph_launch(dtm_graph* graph, dtm_stream_t stream) {
+  if (!graph) return DTM_EINVAL;
+  return hip_ok(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)));
+}
+
+void dtm_graph_destroy(dtm_graph* graph) {
+  if (!graph) return;
+  hipGraphExecDestroy(graph->exec);
+  hipGraphDestroy(graph->graph);
+  delete graph;
 }
 
 int dtm_build_base_batched(const dtm_plan* plan, void* P_packed_dev, dtm_stream_t stream) {

@@ -48,6 +48,7 @@ SYMBOLS = [
     "dtm_plan_workspace_bytes", "dtm_plan_pi_elems", "dtm_plan_matrix_elems", "dtm_plan_offsets",
     "dtm_plan_tiles", "dtm_plan_bind", "dtm_solve_batched", "dtm_build_base_batched",
     "dtm_apply_deadtime_shift_batched", "dtm_build_transition_batched",
+    "dtm_graph_create", "dtm_graph_launch", "dtm_graph_destroy",
 ]
 
 
@@ -144,6 +145,9 @@ def lib() -> ctypes.CDLL:
         "dtm_build_base_batched": (ctypes.c_int, [_P, _P, _P]),
         "dtm_apply_deadtime_shift_batched": (ctypes.c_int, [_P, _P, _P, _P]),
         "dtm_build_transition_batched": (ctypes.c_int, [_P, _P, _P]),
+        "dtm_graph_create": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
+        "dtm_graph_launch": (ctypes.c_int, [_P, _P]),
+        "dtm_graph_destroy": (None, [_P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -344,9 +348,38 @@ class Plan:
         check(lib().dtm_apply_deadtime_shift_batched(self.handle, _ptr(P_base), _ptr(P), _stream(stream)),
               "dtm_apply_deadtime_shift_batched")
 
+    def graph(self, pi, infos, x0=None, stream=None):
+        """Capture one solve into a HIP graph (see Graph)."""
+        return Graph(self, pi, infos, x0, stream)
+
     def close(self):
         if getattr(self, "handle", None):
             lib().dtm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """dtm_graph_*: a captured dtm_solve_batched call, replayed by launch()."""
+
+    def __init__(self, plan, pi, infos, x0=None, stream=None):
+        h = _P()
+        check(lib().dtm_graph_create(plan.handle, _ptr(x0), _ptr(pi), _ptr(infos), _stream(stream),
+                                     ctypes.byref(h)), "dtm_graph_create")
+        self.handle = h
+        self._keep = (plan, pi, infos, x0)
+
+    def launch(self, stream=None):
+        check(lib().dtm_graph_launch(self.handle, _stream(stream)), "dtm_graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().dtm_graph_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
