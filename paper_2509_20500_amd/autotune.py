@@ -33,7 +33,7 @@ def candidates(scenes):
     """The search space, pruned to shapes that differ for these scenes."""
     n_max = int(np.max(scenes["n_bins"]))
     out, seen = [], set()
-    for unroll, fmax, band in itertools.product((4, 8), (1024, 2048, 4096), (128, 256, 512)):
+    for unroll, fmax, band in itertools.product((2, 4, 8), (1024, 2048, 4096), (128, 256, 512)):
         eff_fmax = min(fmax, n_max)
         eff_band = band if n_max > fmax else 0
         sig = (unroll, eff_fmax, eff_band)

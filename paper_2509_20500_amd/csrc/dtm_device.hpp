@@ -90,6 +90,29 @@ __device__ inline double block_exclusive_scan(double v, double* red, double& tot
   return base + excl;
 }
 
+// Exclusive prefix sum in reversed thread order: thread t gets the sum of v
+// over threads t+1 .. BT-1.
+template <int BT>
+__device__ inline double block_exclusive_scan_rev(double v, double* red) {
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  double x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double y = __shfl_down(x, off, kWave);
+    if (lane + off < kWave) x += y;
+  }
+  double excl = __shfl_down(x, 1, kWave);
+  if (lane == kWave - 1) excl = 0.0;
+  __syncthreads();
+  if (lane == 0) red[w] = x;
+  __syncthreads();
+  double base = 0.0;
+#pragma unroll
+  for (int i = BT / kWave - 1; i >= 0; --i)
+    if (i > w) base += red[i];
+  return base + excl;
+}
+
 // Compensated (Kahan) accumulation; the sum is s - c.  float64 needs none.
 __device__ inline void comp_add(float& s, float& c, float v) {
   const float y = v - c;
@@ -155,6 +178,39 @@ __device__ double pixel_tables(const PixelMeta& m, T* g, T* lam_out, double* F_o
   for (int j = n + threadIdx.x; j < m.ld; j += BT) g[j] = T(0);
   if (F_out && threadIdx.x == 0) F_out[n] = total;
   return total;
+}
+
+// Row normalisers of the base matrix (Section 3.4).  Row k of E_base times
+// lambda is exp(F_k) * g_j * w_kj with w_kj = c = exp(-Lambda) for j < k (the
+// wrap term of Theorem 1's indicator) and 1 otherwise; the common factor
+// exp(F_k) cancels in the normalisation, leaving
+//   S_k = sum_j g_j w_kj = sum_{j >= k} g_j + c * sum_{j < k} g_j.
+// Every row holds the same g and differs only in where the wrap factor
+// starts, so one prefix and one suffix float64 block scan give all n row sums
+// with no subtraction.  The block owns chunks of bins exactly as in
+// pixel_tables (so each thread reads only g values it wrote itself); pk is
+// float64 scratch of n entries.  Writes invs[k] = 1 / S_k.
+template <typename T, int BT>
+__device__ void row_normalisers(int n, const T* g, T c, double* pk, T* invs, double* red) {
+  const int chunk = (n + BT - 1) / BT;
+  const int j0 = min(static_cast<int>(threadIdx.x) * chunk, n);
+  const int j1 = min(j0 + chunk, n);
+  const double cd = static_cast<double>(c);
+  double cs = 0.0;
+  for (int j = j0; j < j1; ++j) cs += static_cast<double>(g[j]);
+  double tot;
+  const double pre = block_exclusive_scan<BT>(cs, red, tot);
+  const double suf = block_exclusive_scan_rev<BT>(cs, red);
+  double P = pre;
+  for (int j = j0; j < j1; ++j) {
+    pk[j] = P;
+    P += static_cast<double>(g[j]);
+  }
+  double Tk = suf;
+  for (int j = j1 - 1; j >= j0; --j) {
+    Tk += static_cast<double>(g[j]);
+    invs[j] = static_cast<T>(1.0 / (Tk + cd * pk[j]));
+  }
 }
 
 // Row sum S_k = sum_j g_j w_kj with w_kj = c for j < k (the wrap term

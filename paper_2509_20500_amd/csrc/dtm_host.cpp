@@ -280,11 +280,10 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   plan->total_bytes = off;
   plan->ws = nullptr;
   plan->ws_bytes = 0;
+  plan->aux_stream = plan->ev_fork = plan->ev_join = nullptr;
   *plan_out = plan;
   return DTM_OK;
 }
-
-void dtm_plan_destroy(dtm_plan* plan) { delete plan; }
 
 size_t dtm_plan_workspace_bytes(const dtm_plan* plan) { return plan ? plan->total_bytes : 0; }
 int64_t dtm_plan_pi_elems(const dtm_plan* plan) { return plan ? plan->pi_elems : -1; }

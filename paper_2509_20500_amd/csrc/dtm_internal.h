@@ -150,4 +150,9 @@ struct dtm_plan {
   size_t off_small, off_big, off_items, off_xbuf, off_dprev, off_part;
   void* ws;            // bound workspace (device), or nullptr
   size_t ws_bytes;
+  // created at bind: a second stream (default priority) and two events that
+  // fork the fused kernel off the caller's stream and join it back
+  void* aux_stream;
+  void* ev_fork;
+  void* ev_join;
 };

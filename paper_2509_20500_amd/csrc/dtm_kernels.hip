@@ -38,27 +38,20 @@ __device__ inline PixelMeta load_meta(const PixelMeta* metas, const PixelMeta& o
 
 // Bin tables: one block per pixel.  g -> colf[vec_off ...], c = exp(-Lambda)
 // -> scal[p]; lambda and F to the caller's buffers when given.
+// Bin tables and row normalisers: one block per pixel.  g -> colf[vec_off],
+// 1/S_k -> invs[vec_off], c = exp(-Lambda) -> scal[p] (pk: float64 scratch
+// with the layout of colf); lambda and F to the caller's buffers when given.
 template <typename T, int BT>
 __global__ __launch_bounds__(BT) void k_tables(const PixelMeta* metas, PixelMeta one, T* colf,
-                                               double* scal, T* lam_out, double* F_out) {
+                                               T* invs, double* pk, double* scal, T* lam_out,
+                                               double* F_out) {
   __shared__ double red[3 * BT / kWave];
   const PixelMeta m = load_meta(metas, one, blockIdx.x);
   const double Lam = pixel_tables<T, BT>(m, colf + m.vec_off, lam_out, F_out, red);
-  if (threadIdx.x == 0) scal[blockIdx.x] = exp(-Lam);
-}
-
-// Row sums of the base matrix: one wavefront per row k; writes 1 / S_k.
-template <typename T, int BT>
-__global__ __launch_bounds__(BT) void k_rowsums(const PixelMeta* metas, PixelMeta one,
-                                                const int32_t* sel, const T* colf,
-                                                const double* scal, T* invs) {
-  const int q = sel ? sel[blockIdx.y] : blockIdx.y;
-  const PixelMeta m = load_meta(metas, one, q);
-  const int k = blockIdx.x * (BT / kWave) + threadIdx.x / kWave;
-  if (k >= m.n) return;
-  const T c = static_cast<T>(scal[q]);
-  const double s = wave_row_sum<T>(colf + m.vec_off, m.n, k, c);
-  if ((threadIdx.x % kWave) == 0) invs[m.vec_off + k] = static_cast<T>(1.0 / s);
+  const double c = exp(-Lam);
+  row_normalisers<T, BT>(m.n, colf + m.vec_off, static_cast<T>(c), pk + m.vec_off,
+                         invs + m.vec_off, red);
+  if (threadIdx.x == 0) scal[blockIdx.x] = c;
 }
 
 // Writes rows of the transition matrix, one wavefront per row, lanes over
@@ -367,6 +360,7 @@ __device__ inline void sweep_rows(const T* __restrict__ mat, int64_t ld, int n, 
 template <typename T, int BT, int CPT, int U>
 __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict__ metas,
                                                     const T* __restrict__ colf,
+                                                    const T* __restrict__ invs_g,
                                                     const double* __restrict__ scal,
                                                     T* __restrict__ pool,
                                                     const T* __restrict__ x0_packed,
@@ -391,15 +385,10 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
   T* mat = pool + m.mat_off;
   const T c = static_cast<T>(scal[pq]);
 
-  // ---- a1 tables into LDS (g is zero-padded to ld) -------------------------
+  // ---- a1/a2 tables into LDS: g (zero-padded to ld) and 1/S_k -------------
   for (int j = tid; j < m.ld; j += BT) g[j] = colf[m.vec_off + j];
+  for (int j = tid; j < n; j += BT) invs[j] = invs_g[m.vec_off + j];
   __syncthreads();
-
-  // ---- a2: row sums of the base matrix, one wavefront per row -----------
-  for (int k = tid / kWave; k < n; k += BT / kWave) {
-    const double s = wave_row_sum<T>(g, n, k, c);
-    if ((tid % kWave) == 0) invs[k] = static_cast<T>(1.0 / s);
-  }
 
   // ---- start vector: caller's (validated) or uniform ---------------------
   StopState st;
@@ -1031,18 +1020,10 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 }
 
 template <typename T>
-int launch_tables(const PixelMeta* metas, const PixelMeta& one, int np, T* colf, double* scal,
-                  T* lam, double* F, hipStream_t st) {
-  hipLaunchKernelGGL((k_tables<T, kBT>), dim3(np), dim3(kBT), 0, st, metas, one, colf, scal, lam, F);
-  return last_launch();
-}
-
-template <typename T>
-int launch_rowsums(const PixelMeta* metas, const PixelMeta& one, const int32_t* sel, int np,
-                   int max_n, const T* colf, const double* scal, T* invs, hipStream_t st) {
-  const int rows_per_block = kBT / kWave;
-  dim3 grid((max_n + rows_per_block - 1) / rows_per_block, np);
-  hipLaunchKernelGGL((k_rowsums<T, kBT>), grid, dim3(kBT), 0, st, metas, one, sel, colf, scal, invs);
+int launch_tables(const PixelMeta* metas, const PixelMeta& one, int np, T* colf, T* invs, double* pk,
+                  double* scal, T* lam, double* F, hipStream_t st) {
+  hipLaunchKernelGGL((k_tables<T, kBT>), dim3(np), dim3(kBT), 0, st, metas, one, colf, invs, pk, scal,
+                     lam, F);
   return last_launch();
 }
 
@@ -1078,9 +1059,8 @@ int single_prepare(const dtm_scene& s, dtm_dtype dt, void* ws, size_t ws_bytes, 
   T* colf = reinterpret_cast<T*>(w + L.off_colf);
   T* invs = reinterpret_cast<T*>(w + L.off_invs);
   double* scal = reinterpret_cast<double*>(w + L.off_scal);
-  int rc = launch_tables<T>(nullptr, m, 1, colf, scal, lam, F, st);
-  if (rc) return rc;
-  rc = launch_rowsums<T>(nullptr, m, nullptr, 1, m.n, colf, scal, invs, st);
+  double* pk = reinterpret_cast<double*>(w + L.off_dprev);
+  const int rc = launch_tables<T>(nullptr, m, 1, colf, invs, pk, scal, lam, F, st);
   *m_out = m;
   *L_out = L;
   return rc;
@@ -1161,8 +1141,8 @@ int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, c
                      int count, const T* colf, const double* scal, T* pool, const T* x0, T* pi,
                      dtm_solve_info* infos, int lds_ld, hipStream_t st) {
   const size_t lds = 3 * sizeof(T) * static_cast<size_t>(lds_ld) + 3 * BT / kWave * sizeof(double);
-  void (*kern)(const PixelMeta*, const T*, const double*, T*, const T*, T*, dtm_solve_info*,
-               const int32_t*, KOpts, int) = nullptr;
+  void (*kern)(const PixelMeta*, const T*, const T*, const double*, T*, const T*, T*,
+               dtm_solve_info*, const int32_t*, KOpts, int) = nullptr;
   switch (unroll) {
     case 2: kern = k_solve_fused<T, BT, CPT, 2>; break;
     case 4: kern = k_solve_fused<T, BT, CPT, 4>; break;
@@ -1174,8 +1154,9 @@ int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, c
                             static_cast<int>(lds)) != hipSuccess)
       return DTM_EHIP;
   }
-  hipLaunchKernelGGL(kern, dim3(count), dim3(BT), lds, st, metas, colf, scal, pool, x0, pi, infos,
-                     sel, plan->kopts, lds_ld);
+  const T* invs = reinterpret_cast<const T*>(static_cast<char*>(plan->ws) + plan->off_invs);
+  hipLaunchKernelGGL(kern, dim3(count), dim3(BT), lds, st, metas, colf, invs, scal, pool, x0, pi,
+                     infos, sel, plan->kopts, lds_ld);
   return last_launch();
 }
 
@@ -1272,10 +1253,21 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
   constexpr int VN = Vec<T>::n;
   PixelMeta dummy;
   std::memset(&dummy, 0, sizeof(dummy));
-  int rc = launch_tables<T>(metas, dummy, plan->n_pixels, colf, scal, nullptr, nullptr, st);
+  double* pk = reinterpret_cast<double*>(w + plan->off_dprev);
+  int rc = launch_tables<T>(metas, dummy, plan->n_pixels, colf, invs, pk, scal, nullptr, nullptr, st);
   if (rc) return rc;
   const int nsmall = static_cast<int>(plan->small_sel.size());
   const int nbig = static_cast<int>(plan->big_sel.size());
+  // With both kinds of pixels, the fused kernel runs on the plan's second
+  // stream alongside the banded launches, which leave most of the GPU idle
+  // while a sweep's last bands and the combines finish.
+  const bool fork = nsmall > 0 && nbig > 0;
+  hipStream_t fst = st;
+  if (fork) {
+    fst = static_cast<hipStream_t>(plan->aux_stream);
+    if (hipEventRecord(static_cast<hipEvent_t>(plan->ev_fork), st) != hipSuccess) return DTM_EHIP;
+    if (hipStreamWaitEvent(fst, static_cast<hipEvent_t>(plan->ev_fork), 0) != hipSuccess) return DTM_EHIP;
+  }
   if (nsmall > 0) {
     // columns per thread covering the largest fused pixel; at most 4 vectors
     // of columns per thread (more would spill), so wide pixels take 512 threads
@@ -1290,17 +1282,19 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
     const int lds_ld = plan->max_ld_small;
     if (bt == 512)
       rc = launch_fused_bt<T, 512>(plan, cpt, metas, small, nsmall, colf, scal, pool, x0t, pit, infos,
-                                   lds_ld, st);
+                                   lds_ld, fst);
     else
       rc = launch_fused_bt<T, 256>(plan, cpt, metas, small, nsmall, colf, scal, pool, x0t, pit, infos,
-                                   lds_ld, st);
+                                   lds_ld, fst);
     if (rc) return rc;
   }
   if (nbig > 0) {
-    rc = launch_rowsums<T>(metas, dummy, big, nbig, plan->max_n_big, colf, scal, invs, st);
-    if (rc) return rc;
     rc = launch_banded<T>(plan, metas, colf, scal, invs, pool, x0t, pit, infos, st);
     if (rc) return rc;
+  }
+  if (fork) {
+    if (hipEventRecord(static_cast<hipEvent_t>(plan->ev_join), fst) != hipSuccess) return DTM_EHIP;
+    if (hipStreamWaitEvent(st, static_cast<hipEvent_t>(plan->ev_join), 0) != hipSuccess) return DTM_EHIP;
   }
   if (sizeof(T) == 8) return DTM_OK;
   return launch_refine<T>(plan, metas, pit, infos, st);
@@ -1313,11 +1307,10 @@ int batched_tables_rowsums(const dtm_plan* plan, hipStream_t st) {
   T* colf = reinterpret_cast<T*>(w + plan->off_colf);
   T* invs = reinterpret_cast<T*>(w + plan->off_invs);
   double* scal = reinterpret_cast<double*>(w + plan->off_scal);
+  double* pk = reinterpret_cast<double*>(w + plan->off_dprev);
   PixelMeta dummy;
   std::memset(&dummy, 0, sizeof(dummy));
-  int rc = launch_tables<T>(metas, dummy, plan->n_pixels, colf, scal, nullptr, nullptr, st);
-  if (rc) return rc;
-  return launch_rowsums<T>(metas, dummy, nullptr, plan->n_pixels, plan->max_n, colf, scal, invs, st);
+  return launch_tables<T>(metas, dummy, plan->n_pixels, colf, invs, pk, scal, nullptr, nullptr, st);
 }
 
 template <typename T>
@@ -1351,10 +1344,13 @@ int dtm_bin_tables(const dtm_scene* s, dtm_dtype dt, void* lambda_dev, double* F
   if (workspace_bytes < L.total) return DTM_ENOSPACE;
   char* w = static_cast<char*>(workspace_dev);
   double* scal = reinterpret_cast<double*>(w + L.off_scal);
+  double* pk = reinterpret_cast<double*>(w + L.off_dprev);
   if (dt == DTM_F32)
-    return launch_tables<float>(nullptr, m, 1, reinterpret_cast<float*>(w + L.off_colf), scal,
+    return launch_tables<float>(nullptr, m, 1, reinterpret_cast<float*>(w + L.off_colf),
+                                reinterpret_cast<float*>(w + L.off_invs), pk, scal,
                                 static_cast<float*>(lambda_dev), F_dev, st);
-  return launch_tables<double>(nullptr, m, 1, reinterpret_cast<double*>(w + L.off_colf), scal,
+  return launch_tables<double>(nullptr, m, 1, reinterpret_cast<double*>(w + L.off_colf),
+                               reinterpret_cast<double*>(w + L.off_invs), pk, scal,
                                static_cast<double*>(lambda_dev), F_dev, st);
 }
 
@@ -1448,9 +1444,37 @@ int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes, d
                      hipMemcpyHostToDevice, st) != hipSuccess)
     return DTM_EHIP;
   if (hipStreamSynchronize(st) != hipSuccess) return DTM_EHIP;
+  if (!plan->aux_stream) {
+    hipStream_t aux;
+    hipEvent_t a, b;
+    if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) return DTM_EHIP;
+    if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess) {
+      hipStreamDestroy(aux);
+      return DTM_EHIP;
+    }
+    if (hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+      hipEventDestroy(a);
+      hipStreamDestroy(aux);
+      return DTM_EHIP;
+    }
+    plan->aux_stream = aux;
+    plan->ev_fork = a;
+    plan->ev_join = b;
+  }
   plan->ws = workspace_dev;
   plan->ws_bytes = workspace_bytes;
   return DTM_OK;
+}
+
+void dtm_plan_destroy(dtm_plan* plan) {
+  if (!plan) return;
+  if (plan->aux_stream) {
+    hipStreamSynchronize(static_cast<hipStream_t>(plan->aux_stream));
+    hipStreamDestroy(static_cast<hipStream_t>(plan->aux_stream));
+    hipEventDestroy(static_cast<hipEvent_t>(plan->ev_fork));
+    hipEventDestroy(static_cast<hipEvent_t>(plan->ev_join));
+  }
+  delete plan;
 }
 
 int dtm_solve_batched(const dtm_plan* plan, const void* x0_packed_dev, void* pi_packed_dev,
