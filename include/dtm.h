@@ -244,6 +244,56 @@ int dtm_apply_deadtime_shift_batched(const dtm_plan* plan, const void* P_base_pa
 int dtm_build_transition_batched(const dtm_plan* plan, void* P_packed_dev,
                                  dtm_stream_t stream);
 
+/* ---- learned warm start ------------------------------------------------------
+ * A small network predicts pi from the scene parameters to seed the power
+ * iteration (dtm_solve_batched's x0; the solver's float64 residual decides,
+ * uniform is the fallback):
+ *   features phi (5, see dtm_mlp_features) -> Linear(5, 256) -> GELU
+ *   -> Linear(256, 256) -> GELU -> Linear(256, 1024) -> softmax.
+ * GELU is the erf form.  GEMMs use bfloat16 operands with float32
+ * accumulation on the matrix cores; everything else is float32.  All state
+ * lives in a caller-owned workspace described by dtm_mlp_layout: float32
+ * master parameters (W1 is stored as 16 x 256 with input rows 5..15 zero),
+ * their bfloat16 copies, gradients, Adam moments and the activations of one
+ * batch of up to max_batch rows.  Weights are row-major (in x out). */
+#define DTM_MLP_IN 5
+#define DTM_MLP_IN_PAD 16
+#define DTM_MLP_HIDDEN 256
+#define DTM_MLP_OUT 1024
+#define DTM_MLP_MAX_BATCH 65536
+
+typedef struct dtm_mlp_layout {
+  size_t params, params_bf16, grads, adam_m, adam_v, act, total; /* byte offsets, total size */
+  int64_t off_w1, off_b1, off_w2, off_b2, off_w3, off_b3;         /* element offsets of each tensor
+                                                                     in params / grads / moments */
+  int64_t n_params;
+  int32_t max_batch;
+  int32_t reserved;
+} dtm_mlp_layout;
+
+int dtm_mlp_workspace_layout(int32_t max_batch, dtm_mlp_layout* layout_out);
+/* Features of n device scenes into feat_dev (n x 5 float32):
+ * 2 tau/t_r - 1, sigma [ns], 2 (ln S - ln 0.05)/ln 100 - 1,
+ * 2 (ln B - ln 0.01)/ln 100 - 1, (t_d mod t_r)/t_r. */
+int dtm_mlp_features(const dtm_scene* scenes_dev, int32_t n, float* feat_dev, dtm_stream_t stream);
+/* Refresh the bfloat16 copies after writing the float32 parameters. */
+int dtm_mlp_sync_bf16(void* workspace_dev, int32_t max_batch, dtm_stream_t stream);
+/* probs_dev (batch x 1024 float32) = softmax(network(feat_dev)). */
+int dtm_mlp_forward(void* workspace_dev, int32_t max_batch, const float* feat_dev, int32_t batch,
+                    float* probs_dev, dtm_stream_t stream);
+/* Forward, cross-entropy -sum_j target_j log q_j per row (loss_dev, may be
+ * NULL), and the gradients of the mean loss into the workspace's grads. */
+int dtm_mlp_backward(void* workspace_dev, int32_t max_batch, const float* feat_dev,
+                     const float* target_dev, int32_t batch, float* loss_dev, dtm_stream_t stream);
+/* One Adam step (bias-corrected, step >= 1) on every parameter. */
+int dtm_mlp_adam(void* workspace_dev, int32_t max_batch, float lr, float beta1, float beta2,
+                 float eps, int32_t step, dtm_stream_t stream);
+/* The network's GEMM: C (M x N float32, ldc) = op(A) op(B), A and B bfloat16
+ * row-major, op = transpose when trans_* != 0. */
+int dtm_mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const void* A_dev, int32_t lda,
+                      int32_t trans_a, const void* B_dev, int32_t ldb, int32_t trans_b,
+                      float* C_dev, int32_t ldc, dtm_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,459 @@
+// Learned warm start for power iteration: a 5 -> 256 -> 256 -> 1024 MLP with
+// GELU activations and a softmax output, trained on stationary PDFs produced
+// by the solver itself.  GEMMs run on the MFMA units in bfloat16 with float32
+// accumulation; activations, softmax, loss, gradients of biases and the Adam
+// update are float32.  Float32 master weights, bfloat16 copies for the GEMMs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "dtm.h"
+#include "dtm_internal.h"
+
+namespace dtm {
+namespace mlp {
+
+constexpr int IN = DTM_MLP_IN;
+constexpr int INP = DTM_MLP_IN_PAD;
+constexpr int H = DTM_MLP_HIDDEN;
+constexpr int OUT = DTM_MLP_OUT;
+
+typedef uint16_t bf16;
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline float bf2f(bf16 h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+// float -> bfloat16, round to nearest even (finite inputs).
+__device__ inline bf16 f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<bf16>(u >> 16);
+}
+
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
+         x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+enum Epi { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2 };
+
+// C[M x N] = op(A)[M x K] op(B)[K x N] with op(A)[i][k] = TA ? A[k*lda+i] :
+// A[i*lda+k] and op(B)[k][j] = TB ? B[j*ldb+k] : B[k*ldb+j].  A 64 x 64 tile
+// per block of 4 wavefronts, each wavefront a 32 x 32 quarter computed as
+// 2 x 2 v_mfma_f32_16x16x16_bf16 tiles; K advances by 16 through LDS.
+// Lane layout of the 16x16x16 instruction: lane l supplies A[l%16][4(l/16)+r]
+// and B[4(l/16)+r][l%16] (r = 0..3) and receives D[4(l/16)+r][l%16].
+// Out-of-range elements load as zero and are not stored.
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* __restrict__ A,
+                                              int lda, const bf16* __restrict__ B, int ldb,
+                                              float* __restrict__ C, int ldc,
+                                              const float* __restrict__ bias,
+                                              bf16* __restrict__ Hout, int ldh) {
+  __shared__ bf16 As[64][16 + 4];
+  __shared__ bf16 Bs[64][16 + 4];  // transposed: Bs[j][k]
+  const int tid = threadIdx.x;
+  const int lane = tid % 64, wave = tid / 64;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int wi = (wave / 2) * 32, wj = (wave % 2) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    // 64 x 16 tiles: thread t loads 4 elements of each
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid * 4 + e;  // 0..1023
+      const int r = idx / 16, kk = idx % 16;
+      const int gi = i0 + r, gk = k0 + kk;
+      bf16 va = 0;
+      if (gi < M && gk < K) va = TA ? A[static_cast<int64_t>(gk) * lda + gi] : A[static_cast<int64_t>(gi) * lda + gk];
+      As[r][kk] = va;
+      const int gj = j0 + r;
+      bf16 vb = 0;
+      if (gj < N && gk < K) vb = TB ? B[static_cast<int64_t>(gj) * ldb + gk] : B[static_cast<int64_t>(gk) * ldb + gj];
+      Bs[r][kk] = vb;
+    }
+    __syncthreads();
+    const int kq = 4 * (lane / 16);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      bf16x4 fa;
+      const int ra = wi + a * 16 + lane % 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) fa[r] = static_cast<short>(As[ra][kq + r]);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        bf16x4 fb;
+        const int cb = wj + b * 16 + lane % 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fb[r] = static_cast<short>(Bs[cb][kq + r]);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa, fb, acc[a][b], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + wi + a * 16 + 4 * (lane / 16) + r;
+        const int gj = j0 + wj + b * 16 + lane % 16;
+        if (gi >= M || gj >= N) continue;
+        float v = acc[a][b][r];
+        if (EPI != EPI_STORE) v += bias[gj];
+        C[static_cast<int64_t>(gi) * ldc + gj] = v;
+        if (EPI == EPI_BIAS_GELU) Hout[static_cast<int64_t>(gi) * ldh + gj] = f2bf(gelu(v));
+      }
+}
+
+// Features of a scene, fixed affine maps onto about [-1, 1]:
+//   2 tau / t_r - 1, sigma / 1 ns, 2 (ln S - ln 0.05) / ln 100 - 1,
+//   2 (ln B - ln 0.01) / ln 100 - 1, (t_d mod t_r) / t_r.
+__global__ void k_features(const dtm_scene* __restrict__ scenes, int n, float* __restrict__ feat) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const dtm_scene s = scenes[p];
+  const double l100 = log(100.0);
+  feat[p * IN + 0] = static_cast<float>(2.0 * s.pulse_center_ns / s.period_ns - 1.0);
+  feat[p * IN + 1] = static_cast<float>(s.pulse_sigma_ns);
+  feat[p * IN + 2] = static_cast<float>(2.0 * (log(fmax(s.signal_flux, 1e-30)) - log(0.05)) / l100 - 1.0);
+  feat[p * IN + 3] = static_cast<float>(2.0 * (log(fmax(s.background_flux, 1e-30)) - log(0.01)) / l100 - 1.0);
+  feat[p * IN + 4] = static_cast<float>(fmod(s.dead_time_ns, s.period_ns) / s.period_ns);
+}
+
+// X0 (bfloat16, rows padded to INP columns with zeros).
+__global__ void k_pack_input(const float* __restrict__ feat, int batch, bf16* __restrict__ x0) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= batch * INP) return;
+  const int i = idx / INP, k = idx % INP;
+  x0[idx] = k < IN ? f2bf(feat[i * IN + k]) : static_cast<bf16>(0);
+}
+
+// Row-wise softmax of the logits; optionally cross-entropy against a target
+// distribution with its gradient dZ = (q - target) / batch (float32 and
+// bfloat16).  One block of 256 threads per row of OUT = 1024 logits.
+__global__ __launch_bounds__(256) void k_softmax_xent(const float* __restrict__ z, int batch,
+                                                      const float* __restrict__ target,
+                                                      float* __restrict__ q_out,
+                                                      float* __restrict__ dz, bf16* __restrict__ dzb,
+                                                      float* __restrict__ loss) {
+  __shared__ float red[4];
+  const int i = blockIdx.x;
+  const float* zr = z + static_cast<int64_t>(i) * OUT;
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  float v[4];
+  float mx = -INFINITY;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    v[r] = zr[tid + 256 * r];
+    mx = fmaxf(mx, v[r]);
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) red[w] = mx;
+  __syncthreads();
+  mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  __syncthreads();
+  float s = 0.f;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    v[r] = expf(v[r] - mx);
+    s += v[r];
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) red[w] = s;
+  __syncthreads();
+  s = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  const float lse = mx + logf(s);
+  float l = 0.f;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int j = tid + 256 * r;
+    const float q = v[r] / s;
+    if (q_out) q_out[static_cast<int64_t>(i) * OUT + j] = q;
+    if (target) {
+      const float t = target[static_cast<int64_t>(i) * OUT + j];
+      l -= t * (zr[j] - lse);
+      const float g = (q - t) / batch;
+      dz[static_cast<int64_t>(i) * OUT + j] = g;
+      dzb[static_cast<int64_t>(i) * OUT + j] = f2bf(g);
+    }
+  }
+  if (target) {
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
+    if (lane == 0) red[w] = l;
+    __syncthreads();
+    if (tid == 0) loss[i] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+// dA = dH * gelu'(A) (float32 and bfloat16).
+__global__ void k_gelu_back(const float* __restrict__ dh, const float* __restrict__ a, int n,
+                            float* __restrict__ da, bf16* __restrict__ dab) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const float g = dh[idx] * gelu_grad(a[idx]);
+  da[idx] = g;
+  dab[idx] = f2bf(g);
+}
+
+// db[j] = sum_i d[i][j] (fixed order over rows).
+__global__ void k_bias_grad(const float* __restrict__ d, int rows, int cols, float* __restrict__ db) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  float s = 0.f;
+  for (int i = 0; i < rows; ++i) s += d[static_cast<int64_t>(i) * cols + j];
+  db[j] = s;
+}
+
+// Adam on the flat float32 parameters; refreshes their bfloat16 copies.
+__global__ void k_adam(float* __restrict__ w, bf16* __restrict__ wb, const float* __restrict__ g,
+                       float* __restrict__ m, float* __restrict__ v, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= n) return;
+  const float gi = g[idx];
+  const float mi = b1 * m[idx] + (1.f - b1) * gi;
+  const float vi = b2 * v[idx] + (1.f - b2) * gi * gi;
+  m[idx] = mi;
+  v[idx] = vi;
+  const float wi = w[idx] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[idx] = wi;
+  wb[idx] = f2bf(wi);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ w, bf16* __restrict__ wb, int64_t n) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx < n) wb[idx] = f2bf(w[idx]);
+}
+
+// ---- layout -----------------------------------------------------------------
+
+struct Ptrs {
+  float *p, *g, *m, *v;
+  bf16* pb;
+  float *w1, *b1, *w2, *b2, *w3, *b3;
+  float *gw1, *gb1, *gw2, *gb2, *gw3, *gb3;
+  bf16 *w1b, *w2b, *w3b;
+  bf16* x0;
+  float *a1, *a2, *z, *q, *dz, *dh2, *da2, *dh1, *da1, *loss;
+  bf16 *h1, *h2, *dzb, *da2b, *da1b;
+};
+
+void layout(int32_t max_batch, dtm_mlp_layout* L) {
+  const int64_t B = max_batch;
+  L->off_w1 = 0;
+  L->off_b1 = L->off_w1 + static_cast<int64_t>(INP) * H;
+  L->off_w2 = L->off_b1 + H;
+  L->off_b2 = L->off_w2 + static_cast<int64_t>(H) * H;
+  L->off_w3 = L->off_b2 + H;
+  L->off_b3 = L->off_w3 + static_cast<int64_t>(H) * OUT;
+  L->n_params = L->off_b3 + OUT;
+  L->max_batch = max_batch;
+  L->reserved = 0;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t np = static_cast<size_t>(L->n_params);
+  L->params = take(4 * np);
+  L->params_bf16 = take(2 * np);
+  L->grads = take(4 * np);
+  L->adam_m = take(4 * np);
+  L->adam_v = take(4 * np);
+  // activations
+  L->act = off;
+  take(2 * B * INP);            // x0
+  take(4 * B * H);              // a1
+  take(2 * B * H);              // h1
+  take(4 * B * H);              // a2
+  take(2 * B * H);              // h2
+  take(4 * B * OUT);            // z
+  take(4 * B * OUT);            // q
+  take(4 * B * OUT);            // dz
+  take(2 * B * OUT);            // dzb
+  take(4 * B * H);              // dh2
+  take(4 * B * H);              // da2
+  take(2 * B * H);              // da2b
+  take(4 * B * H);              // dh1
+  take(4 * B * H);              // da1
+  take(2 * B * H);              // da1b
+  take(4 * B);                  // loss
+  L->total = off;
+}
+
+Ptrs pointers(void* ws, int32_t max_batch) {
+  dtm_mlp_layout L;
+  layout(max_batch, &L);
+  char* w = static_cast<char*>(ws);
+  Ptrs P;
+  P.p = reinterpret_cast<float*>(w + L.params);
+  P.pb = reinterpret_cast<bf16*>(w + L.params_bf16);
+  P.g = reinterpret_cast<float*>(w + L.grads);
+  P.m = reinterpret_cast<float*>(w + L.adam_m);
+  P.v = reinterpret_cast<float*>(w + L.adam_v);
+  P.w1 = P.p + L.off_w1; P.b1 = P.p + L.off_b1; P.w2 = P.p + L.off_w2;
+  P.b2 = P.p + L.off_b2; P.w3 = P.p + L.off_w3; P.b3 = P.p + L.off_b3;
+  P.gw1 = P.g + L.off_w1; P.gb1 = P.g + L.off_b1; P.gw2 = P.g + L.off_w2;
+  P.gb2 = P.g + L.off_b2; P.gw3 = P.g + L.off_w3; P.gb3 = P.g + L.off_b3;
+  P.w1b = P.pb + L.off_w1; P.w2b = P.pb + L.off_w2; P.w3b = P.pb + L.off_w3;
+  const int64_t B = max_batch;
+  size_t off = L.act;
+  auto take = [&](size_t bytes) {
+    char* q = w + off;
+    off = align256(off + bytes);
+    return q;
+  };
+  P.x0 = reinterpret_cast<bf16*>(take(2 * B * INP));
+  P.a1 = reinterpret_cast<float*>(take(4 * B * H));
+  P.h1 = reinterpret_cast<bf16*>(take(2 * B * H));
+  P.a2 = reinterpret_cast<float*>(take(4 * B * H));
+  P.h2 = reinterpret_cast<bf16*>(take(2 * B * H));
+  P.z = reinterpret_cast<float*>(take(4 * B * OUT));
+  P.q = reinterpret_cast<float*>(take(4 * B * OUT));
+  P.dz = reinterpret_cast<float*>(take(4 * B * OUT));
+  P.dzb = reinterpret_cast<bf16*>(take(2 * B * OUT));
+  P.dh2 = reinterpret_cast<float*>(take(4 * B * H));
+  P.da2 = reinterpret_cast<float*>(take(4 * B * H));
+  P.da2b = reinterpret_cast<bf16*>(take(2 * B * H));
+  P.dh1 = reinterpret_cast<float*>(take(4 * B * H));
+  P.da1 = reinterpret_cast<float*>(take(4 * B * H));
+  P.da1b = reinterpret_cast<bf16*>(take(2 * B * H));
+  P.loss = reinterpret_cast<float*>(take(4 * B));
+  return P;
+}
+
+template <bool TA, bool TB, int EPI>
+void gemm(int M, int N, int K, const bf16* A, int lda, const bf16* B, int ldb, float* C, int ldc,
+          const float* bias, bf16* Hout, int ldh, hipStream_t st) {
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc,
+                     bias, Hout, ldh);
+}
+
+// Forward pass for `batch` rows of features; leaves every activation in the
+// workspace.
+void forward(const Ptrs& P, const float* feat, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_input, dim3((batch * INP + 255) / 256), dim3(256), 0, st, feat, batch, P.x0);
+  gemm<false, false, EPI_BIAS_GELU>(batch, H, INP, P.x0, INP, P.w1b, H, P.a1, H, P.b1, P.h1, H, st);
+  gemm<false, false, EPI_BIAS_GELU>(batch, H, H, P.h1, H, P.w2b, H, P.a2, H, P.b2, P.h2, H, st);
+  gemm<false, false, EPI_BIAS>(batch, OUT, H, P.h2, H, P.w3b, OUT, P.z, OUT, P.b3, nullptr, 0, st);
+}
+
+}  // namespace mlp
+}  // namespace dtm
+
+using namespace dtm;
+using namespace dtm::mlp;
+
+namespace {
+int ok_launch() { return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP; }
+bool batch_ok(int32_t batch, int32_t max_batch) {
+  return max_batch >= 1 && max_batch <= DTM_MLP_MAX_BATCH && batch >= 1 && batch <= max_batch;
+}
+}  // namespace
+
+extern "C" {
+
+int dtm_mlp_workspace_layout(int32_t max_batch, dtm_mlp_layout* out) {
+  if (!out || max_batch < 1 || max_batch > DTM_MLP_MAX_BATCH) return DTM_EINVAL;
+  layout(max_batch, out);
+  return DTM_OK;
+}
+
+int dtm_mlp_features(const dtm_scene* scenes_dev, int32_t n, float* feat_dev, dtm_stream_t stream) {
+  if (!scenes_dev || !feat_dev || n < 1) return DTM_EINVAL;
+  hipLaunchKernelGGL(k_features, dim3((n + 255) / 256), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), scenes_dev, n, feat_dev);
+  return ok_launch();
+}
+
+int dtm_mlp_sync_bf16(void* ws, int32_t max_batch, dtm_stream_t stream) {
+  if (!ws || max_batch < 1 || max_batch > DTM_MLP_MAX_BATCH) return DTM_EINVAL;
+  dtm_mlp_layout L;
+  layout(max_batch, &L);
+  const Ptrs P = pointers(ws, max_batch);
+  hipLaunchKernelGGL(k_to_bf16, dim3(static_cast<unsigned>((L.n_params + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), P.p, P.pb, L.n_params);
+  return ok_launch();
+}
+
+int dtm_mlp_forward(void* ws, int32_t max_batch, const float* feat_dev, int32_t batch,
+                    float* probs_dev, dtm_stream_t stream) {
+  if (!ws || !feat_dev || !probs_dev || !batch_ok(batch, max_batch)) return DTM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Ptrs P = pointers(ws, max_batch);
+  forward(P, feat_dev, batch, st);
+  hipLaunchKernelGGL(k_softmax_xent, dim3(batch), dim3(256), 0, st, P.z, batch, nullptr, probs_dev,
+                     nullptr, nullptr, nullptr);
+  return ok_launch();
+}
+
+int dtm_mlp_backward(void* ws, int32_t max_batch, const float* feat_dev, const float* target_dev,
+                     int32_t batch, float* loss_dev, dtm_stream_t stream) {
+  if (!ws || !feat_dev || !target_dev || !batch_ok(batch, max_batch)) return DTM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Ptrs P = pointers(ws, max_batch);
+  forward(P, feat_dev, batch, st);
+  hipLaunchKernelGGL(k_softmax_xent, dim3(batch), dim3(256), 0, st, P.z, batch, target_dev, P.q,
+                     P.dz, P.dzb, loss_dev ? loss_dev : P.loss);
+  // layer 3: dW3 = H2^T dZ, db3 = sum dZ, dH2 = dZ W3^T
+  gemm<true, false, EPI_STORE>(H, OUT, batch, P.h2, H, P.dzb, OUT, P.gw3, OUT, nullptr, nullptr, 0, st);
+  hipLaunchKernelGGL(k_bias_grad, dim3((OUT + 255) / 256), dim3(256), 0, st, P.dz, batch, OUT, P.gb3);
+  gemm<false, true, EPI_STORE>(batch, H, OUT, P.dzb, OUT, P.w3b, OUT, P.dh2, H, nullptr, nullptr, 0, st);
+  hipLaunchKernelGGL(k_gelu_back, dim3((batch * H + 255) / 256), dim3(256), 0, st, P.dh2, P.a2,
+                     batch * H, P.da2, P.da2b);
+  // layer 2
+  gemm<true, false, EPI_STORE>(H, H, batch, P.h1, H, P.da2b, H, P.gw2, H, nullptr, nullptr, 0, st);
+  hipLaunchKernelGGL(k_bias_grad, dim3((H + 255) / 256), dim3(256), 0, st, P.da2, batch, H, P.gb2);
+  gemm<false, true, EPI_STORE>(batch, H, H, P.da2b, H, P.w2b, H, P.dh1, H, nullptr, nullptr, 0, st);
+  hipLaunchKernelGGL(k_gelu_back, dim3((batch * H + 255) / 256), dim3(256), 0, st, P.dh1, P.a1,
+                     batch * H, P.da1, P.da1b);
+  // layer 1
+  gemm<true, false, EPI_STORE>(INP, H, batch, P.x0, INP, P.da1b, H, P.gw1, H, nullptr, nullptr, 0, st);
+  hipLaunchKernelGGL(k_bias_grad, dim3((H + 255) / 256), dim3(256), 0, st, P.da1, batch, H, P.gb1);
+  return ok_launch();
+}
+
+int dtm_mlp_adam(void* ws, int32_t max_batch, float lr, float beta1, float beta2, float eps,
+                 int32_t step, dtm_stream_t stream) {
+  if (!ws || max_batch < 1 || max_batch > DTM_MLP_MAX_BATCH || step < 1) return DTM_EINVAL;
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return DTM_EINVAL;
+  dtm_mlp_layout L;
+  layout(max_batch, &L);
+  const Ptrs P = pointers(ws, max_batch);
+  const float c1 = 1.f - std::pow(beta1, static_cast<float>(step));
+  const float c2 = 1.f - std::pow(beta2, static_cast<float>(step));
+  hipLaunchKernelGGL(k_adam, dim3(static_cast<unsigned>((L.n_params + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), P.p, P.pb, P.g, P.m, P.v, L.n_params, lr, beta1,
+                     beta2, eps, c1, c2);
+  return ok_launch();
+}
+
+int dtm_mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const void* A_dev, int32_t lda, int32_t trans_a,
+                      const void* B_dev, int32_t ldb, int32_t trans_b, float* C_dev, int32_t ldc,
+                      dtm_stream_t stream) {
+  if (M < 1 || N < 1 || K < 1 || !A_dev || !B_dev || !C_dev) return DTM_EINVAL;
+  if (ldc < N || lda < (trans_a ? M : K) || ldb < (trans_b ? K : N)) return DTM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bf16* A = static_cast<const bf16*>(A_dev);
+  const bf16* B = static_cast<const bf16*>(B_dev);
+  if (!trans_a && !trans_b) gemm<false, false, EPI_STORE>(M, N, K, A, lda, B, ldb, C_dev, ldc, nullptr, nullptr, 0, st);
+  else if (trans_a && !trans_b) gemm<true, false, EPI_STORE>(M, N, K, A, lda, B, ldb, C_dev, ldc, nullptr, nullptr, 0, st);
+  else if (!trans_a && trans_b) gemm<false, true, EPI_STORE>(M, N, K, A, lda, B, ldb, C_dev, ldc, nullptr, nullptr, 0, st);
+  else gemm<true, true, EPI_STORE>(M, N, K, A, lda, B, ldb, C_dev, ldc, nullptr, nullptr, 0, st);
+  return ok_launch();
+}
+
+}  // extern "C"

@@ -49,6 +49,8 @@ SYMBOLS = [
     "dtm_plan_tiles", "dtm_plan_bind", "dtm_solve_batched", "dtm_build_base_batched",
     "dtm_apply_deadtime_shift_batched", "dtm_build_transition_batched",
     "dtm_graph_create", "dtm_graph_launch", "dtm_graph_destroy",
+    "dtm_mlp_workspace_layout", "dtm_mlp_features", "dtm_mlp_sync_bf16", "dtm_mlp_forward",
+    "dtm_mlp_backward", "dtm_mlp_adam", "dtm_mlp_gemm_bf16",
 ]
 
 

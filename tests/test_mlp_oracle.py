@@ -1,0 +1,57 @@
+"""Pins for the float64 warm-start network: closed-form features and
+central finite differences of the cross-entropy gradients.  CPU only."""
+import numpy as np
+
+from oracle import mlp
+from synth import scenes as sc
+
+
+def _params(rng, scale=0.3):
+    return {
+        "W1": rng.normal(0, scale, (mlp.IN, mlp.HIDDEN)), "b1": rng.normal(0, 0.1, mlp.HIDDEN),
+        "W2": rng.normal(0, scale / 4, (mlp.HIDDEN, mlp.HIDDEN)), "b2": rng.normal(0, 0.1, mlp.HIDDEN),
+        "W3": rng.normal(0, scale / 4, (mlp.HIDDEN, mlp.OUT)), "b3": rng.normal(0, 0.1, mlp.OUT),
+    }
+
+
+def test_features_closed_form():
+    s = sc.scene(period=100.0, dead_time=150.0, center=30.0, sigma=0.4, signal=0.05, background=1.0)
+    assert np.allclose(mlp.features(s), [-0.4, 0.4, -1.0, 1.0, 0.5], atol=1e-15)
+    s = sc.scene(period=50.0, dead_time=10.0, center=25.0, sigma=1.0, signal=5.0, background=0.01)
+    assert np.allclose(mlp.features(s), [0.0, 1.0, 1.0, -1.0, 0.2], atol=1e-15)
+
+
+def test_gelu_matches_its_definition():
+    from scipy.stats import norm
+    x = np.linspace(-6, 6, 101)
+    assert np.allclose(mlp.gelu(x), x * norm.cdf(x), atol=1e-15)
+    h = 1e-6
+    assert np.allclose(mlp.gelu_grad(x), (mlp.gelu(x + h) - mlp.gelu(x - h)) / (2 * h), atol=1e-8)
+
+
+def test_softmax_rows_sum_to_one():
+    rng = np.random.default_rng(0)
+    Q, _ = mlp.forward(_params(rng), rng.normal(size=(4, mlp.IN)))
+    assert np.allclose(Q.sum(axis=1), 1.0, atol=1e-14) and np.all(Q > 0)
+
+
+def test_gradients_match_finite_differences():
+    rng = np.random.default_rng(1)
+    P = _params(rng)
+    X = rng.normal(size=(3, mlp.IN))
+    T = rng.uniform(size=(3, mlp.OUT))
+    T /= T.sum(axis=1, keepdims=True)
+    G = mlp.grads(P, X, T)
+    h = 1e-6
+    for name, arr in P.items():
+        flat = arr.reshape(-1)
+        for idx in rng.choice(flat.size, 12, replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = mlp.loss(P, X, T)
+            flat[idx] = old - h
+            lm = mlp.loss(P, X, T)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = G[name].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * max(1e-3, abs(an)) + 1e-9, (name, idx, fd, an)
