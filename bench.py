@@ -84,13 +84,127 @@ def copy_calibration(nbytes=1 << 30, reps=10):
             "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def timed(step, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(stream)
+    for _ in range(steps):
+        step()
+    e.record(stream)
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / steps
+
+
+def warm_start_workload(args):
+    """The learned warm start at N=1024: train the network on 200,000 PDFs the
+    solver produces from uniform-workload sampling (seed 5), then solve 4,096
+    held-out pixels (seed 6) from uniform and from predicted starts.  The
+    timed warm step includes the feature kernel and the network's forward
+    pass."""
+    import numpy as np
+    import torch
+
+    from oracle import dtm as odtm
+    from paper_2509_20500_amd import dtm
+    from paper_2509_20500_amd.warmstart import WarmStartMLP, solve_targets
+    from synth import scenes as sc
+
+    t0 = time.perf_counter()
+    train = sc.warm_start_train()
+    targets, tinfo = solve_targets(train)
+    targets = (targets / targets.sum(dim=1, keepdim=True)).contiguous()
+    t_targets = time.perf_counter() - t0
+    net = WarmStartMLP(max_batch=1024, seed=0)
+    feat = net.features(train)
+    t1 = time.perf_counter()
+    hist = net.fit(feat, targets, epochs=args.epochs, lr=3e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    del targets, feat
+
+    held = sc.warm_start_eval()
+    plan = dtm.Plan(held, "f32", dtm.opts(tol=1e-6))
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.bind(ws)
+    pi_u = torch.empty(plan.pi_elems, dtype=torch.float32, device="cuda")
+    pi_w = torch.empty_like(pi_u)
+    inf_u = torch.zeros(plan.n_pixels * 40, dtype=torch.uint8, device="cuda")
+    inf_w = torch.zeros_like(inf_u)
+    raw = torch.from_numpy(np.ascontiguousarray(held).view(np.uint8).copy()).cuda()
+    feat_h = torch.empty((plan.n_pixels, 5), dtype=torch.float32, device="cuda")
+    x0 = torch.empty((plan.n_pixels, 1024), dtype=torch.float32, device="cuda")
+
+    def warm_step():
+        dtm.check(net_lib.dtm_mlp_features(raw.data_ptr(), plan.n_pixels, feat_h.data_ptr(),
+                                           dtm._stream(None)))
+        for a in range(0, plan.n_pixels, net.max_batch):
+            b = min(plan.n_pixels, a + net.max_batch)
+            dtm.check(net_lib.dtm_mlp_forward(net.ws.data_ptr(), net.max_batch, feat_h[a:b].data_ptr(), b - a,
+                                              x0[a:b].data_ptr(), dtm._stream(None)))
+        plan.solve(pi_w, inf_w, x0.view(-1))
+
+    from paper_2509_20500_amd.warmstart import _bind
+    net_lib = _bind()
+    ms_u = timed(lambda: plan.solve(pi_u, inf_u), args.steps, args.warmup)
+    ms_w = timed(warm_step, args.steps, args.warmup)
+    iu = dtm.infos_to_numpy(inf_u)
+    iw = dtm.infos_to_numpy(inf_w)
+    pu = pi_u.cpu().numpy().astype(np.float64)
+    pw = pi_w.cpu().numpy().astype(np.float64)
+    off = plan.pi_offsets
+    rng = np.random.default_rng(0)
+    l1 = 0.0
+    for p in rng.choice(plan.n_pixels, min(args.check, plan.n_pixels), replace=False):
+        ref = odtm.stationary_solve(odtm.transition_matrix(held[p]))
+        l1 = max(l1, float(np.abs(pw[off[p]:off[p + 1]] - ref).sum()),
+                 float(np.abs(pu[off[p]:off[p + 1]] - ref).sum()))
+    x0n = x0.cpu().numpy().astype(np.float64).reshape(-1)
+    start_l1 = float(np.mean([np.abs(x0n[off[p]:off[p + 1]] - pu[off[p]:off[p + 1]]).sum()
+                              for p in range(plan.n_pixels)]))
+    n = held["n_bins"].astype(np.float64)
+    alg_w = float(np.sum(4 * n * n * iw["iterations"]))
+    plan.close()
+    return {
+        "metric": "stationary-PDF pixels/s at N=1024, L1<=1e-6 vs FP64 oracle; % HBM roofline",
+        "value": plan.n_pixels / (ms_w * 1e-3),
+        "unit": "pixels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_w,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "learned warm start at N=1024: MLP 5-256-256-1024 (GELU, softmax, bf16 "
+                               "GEMMs) trained on 200,000 solver PDFs (seed 5), 4,096 held-out pixels "
+                               "(seed 6); timed step = features + MLP forward + warm-started solve",
+                   "pixels": plan.n_pixels, "epochs": args.epochs},
+        "roofline": {"bound": "hbm", "achieved": alg_w / (ms_w * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": alg_w / (ms_w * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_solve_fused", "alg_bytes_per_launch": alg_w},
+        "uniform_start": {"pixels_per_s": plan.n_pixels / (ms_u * 1e-3), "ms_per_step": ms_u,
+                          "mean_sweeps": float(iu["iterations"].mean())},
+        "warm_start": {"pixels_per_s": plan.n_pixels / (ms_w * 1e-3), "ms_per_step": ms_w,
+                       "mean_sweeps": float(iw["iterations"].mean()),
+                       "mean_l1_start_to_pi": start_l1,
+                       "fallbacks": int(np.sum((iw["flags"] & (dtm.DTM_INFO_RESTARTED | dtm.DTM_INFO_WARM_REJECTED)) != 0))},
+        "speedup_vs_uniform": ms_u / ms_w,
+        "training": {"targets_s": t_targets, "train_s": t_train, "loss_first": hist[0], "loss_last": hist[-1],
+                     "targets_all_converged": bool(np.all(tinfo["status"] == 0))},
+        "all_converged": bool(np.all(iw["status"] == 0) and np.all(iu["status"] == 0)),
+        "l1_vs_oracle_sampled_max": l1,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--workload", default="batched_uniform", choices=["batched_uniform", "batched_uneven"])
+    ap.add_argument("--workload", default="batched_uniform",
+                    choices=["batched_uniform", "batched_uneven", "warm_start"])
+    ap.add_argument("--epochs", type=int, default=150, help="warm_start: training epochs")
     ap.add_argument("--pixels", type=int, default=0, help="0 = the workload's own count")
     ap.add_argument("--graph", action="store_true", help="replay the solve as a captured HIP graph")
     ap.add_argument("--autotune", action="store_true", help="pick tile shapes by timing candidates")
@@ -116,6 +230,10 @@ def main():
 
     dtm.lib()
     torch.cuda.set_device(0)
+    if args.workload == "warm_start":
+        out = warm_start_workload(args)
+        print(json.dumps(out), flush=True)
+        return
     uneven = args.workload == "batched_uneven"
     if uneven:
         scenes = sc.batched_uneven(n_pixels=args.pixels or 2048)

@@ -83,6 +83,41 @@ def gemm_bf16(A, B, trans_a=False, trans_b=False, stream=None):
     return C
 
 
+def solve_targets(scenes, dtype="f32", chunk=16384, solve_opts=None, x0=None):
+    """Stationary PDFs of many pixels with the batched solver, in chunks so the
+    dense matrices of one chunk at a time sit in HBM.  Returns (pi as a P x n
+    tensor for equal n, or the packed vector otherwise; SolveInfo records)."""
+    import torch
+    outs, infos = [], []
+    ws = None
+    n_all = np.asarray(scenes["n_bins"])
+    for a in range(0, len(scenes), chunk):
+        s = scenes[a:a + chunk]
+        plan = dtm.Plan(s, dtype, solve_opts or dtm.opts(tol=1e-6))
+        try:
+            if ws is None or ws.numel() < plan.workspace_bytes:
+                ws = None
+                ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+            plan.bind(ws)
+            tdt = torch.float32 if plan.dtype == dtm.DTM_F32 else torch.float64
+            pi = torch.empty(plan.pi_elems, dtype=tdt, device="cuda")
+            inf = torch.zeros(plan.n_pixels * 40, dtype=torch.uint8, device="cuda")
+            xa = None
+            if x0 is not None:
+                off = int(np.sum(n_all[:a]))
+                xa = x0[off:off + plan.pi_elems]
+            plan.solve(pi, inf, xa)
+            torch.cuda.synchronize()
+            outs.append(pi)
+            infos.append(dtm.infos_to_numpy(inf))
+        finally:
+            plan.close()
+    pi = torch.cat(outs)
+    if np.all(n_all == n_all[0]):
+        pi = pi.view(len(scenes), int(n_all[0]))
+    return pi, np.concatenate(infos)
+
+
 class WarmStartMLP:
     def __init__(self, max_batch=1024, seed=0, device="cuda"):
         import torch
