@@ -24,6 +24,33 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor peak
+KERNEL_SOURCES = ("dtm_kernels.hip", "dtm_device.hpp", "dtm_internal.h", "dtm_host.cpp")
+
+
+def kernel_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2509_20500_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (profiles/*.md, line 'traffic-record: ...'), or None when there is none
+    for this kernel and workload or the kernel sources changed since."""
+    import glob
+    sha = kernel_sources_sha1()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record:"):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("sha1") == sha:
+                    return float(kv["bytes"])
+    return None
 
 
 def _oracle_one(rec):
@@ -325,7 +352,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": (measured_traffic("k_solve_fused", f"batched_uniform_n1024_{args.dtype}")
+                        if not uneven and plan.n_pixels == 4096 and not graph and not tiles else None),
             "kernel": "k_solve_fused" if not uneven else "k_solve_fused + k_band_sweep",
             "alg_bytes_per_launch": alg_bytes,
         },
