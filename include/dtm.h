@@ -88,6 +88,8 @@ typedef struct dtm_scene {
 
 /* Option flags */
 #define DTM_FLAG_NO_FINAL_CHECK 0x1 /* skip the float64 residual sweep            */
+#define DTM_FLAG_NO_DENSE       0x2 /* plan without the dense matrix pool: only the
+                                       factored solver and the spectral analysis */
 
 typedef struct dtm_solve_opts {
   double tol_l1;       /* target L1 distance (rule 1) or change threshold (rule 0) */
@@ -224,6 +226,41 @@ int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes,
  * be captured in a hipGraph and replayed. */
 int dtm_solve_batched(const dtm_plan* plan, const void* x0_packed_dev, void* pi_packed_dev,
                       dtm_solve_info* infos_dev, dtm_stream_t stream);
+
+/* Factored solver: power iteration on the same matrix without forming it.
+ * With g_j = lambda_j exp(-F_j), c = exp(-Lambda), S_k the row normaliser of
+ * the base matrix and u_k = x_{(k - l) mod n} / S_k, the left product of the
+ * dead-time matrix of Section 3.4 is
+ *   (x P~)_j = g_j (c U_{n-1} + (1 - c) U_j),   U_j = sum_{k <= j} u_k,
+ * one float64 block scan per sweep (O(n) instead of O(n^2)).  Same stop
+ * rule as dtm_solve_batched, every sweep in float64 (eps 1.1e-16), so tol can
+ * go down to ~1e-12.  Uses only the plan's tables and a float64 scratch
+ * region of its workspace; works with DTM_FLAG_NO_DENSE plans.  Launch only. */
+int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, void* pi_packed_dev,
+                               dtm_solve_info* infos_dev, dtm_stream_t stream);
+
+/* Spectral convergence analysis (Section 4): for every pixel, the second
+ * eigenvalue lambda_2 of P~ (magnitude and phase; the spectral gap is
+ * 1 - |lambda_2|) and, when mixing_eps > 0, the empirical mixing steps
+ *   min n : max_s (1/2) || e_s P~^n - pi ||_1 <= mixing_eps   (n <= max_steps,
+ * else -1).  lambda_2 comes from power iteration on the deflated operator
+ * x -> x P~ - (x 1) pi with a two-term recurrence fit
+ * v_{t+2} = a v_{t+1} + b v_t, whose roots are the dominant eigenvalue (or
+ * complex pair); the fit is reliable when |lambda_3| is clearly below
+ * |lambda_2|.  Uses the factored operator (O(n) per step per vector).  The
+ * mixing search keeps all n start states (n^2 float64 per pixel of scratch).
+ * Launch only. */
+typedef struct dtm_spectral_info {
+  double lambda2_re, lambda2_im;  /* lambda_2 (one of a conjugate pair: im >= 0) */
+  double lambda2_abs, lambda2_arg;/* |lambda_2| and its phase in [0, pi]          */
+  double fit_residual;            /* relative residual of the recurrence fit      */
+  int32_t iterations;             /* deflated power steps                          */
+  int32_t mixing_steps;           /* -1: not reached / not requested              */
+} dtm_spectral_info;
+size_t dtm_spectral_scratch_bytes(const dtm_plan* plan, int32_t with_mixing);
+int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_steps,
+                         dtm_spectral_info* out_dev, void* scratch_dev, size_t scratch_bytes,
+                         dtm_stream_t stream);
 
 /* HIP graph of one dtm_solve_batched call: every launch of the solve is
  * captured once and replayed by dtm_graph_launch, which saves the per-launch

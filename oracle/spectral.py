@@ -1,0 +1,43 @@
+"""Spectral convergence quantities of the transition matrix (Section 4).
+
+TEST INFRASTRUCTURE ONLY.  Dense float64 definitions: the eigenvalues of
+P~ by LAPACK, the second one by magnitude (its modulus sets the spectral gap
+1 - |lambda_2|, its phase the oscillation of the convergence), and the
+empirical mixing steps from explicit matrix powers.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def second_eigenvalue(Pt):
+    """lambda_2: the eigenvalue of largest modulus after the Perron value 1
+    (for a conjugate pair, the member with nonnegative imaginary part)."""
+    w = np.linalg.eigvals(np.asarray(Pt, dtype=np.float64))
+    k = int(np.argmin(np.abs(w - 1.0)))
+    rest = np.delete(w, k)
+    order = np.argsort(-np.abs(rest), kind="stable")
+    lam = rest[order[0]]
+    if lam.imag < 0:
+        lam = np.conj(lam)
+    third = np.abs(rest[order[2]]) if rest.size > 2 and abs(rest[order[1]] - np.conj(lam)) < 1e-9 \
+        else (np.abs(rest[order[1]]) if rest.size > 1 else 0.0)
+    return complex(lam), float(third)
+
+
+def mixing_distance(Pt, pi, n):
+    """d(n) = max_s (1/2) || e_s P~^n - pi ||_1."""
+    M = np.linalg.matrix_power(np.asarray(Pt, dtype=np.float64), n)
+    return float(0.5 * np.abs(M - pi[None, :]).sum(axis=1).max())
+
+
+def mixing_steps(Pt, pi, eps=0.25, max_steps=10000):
+    """Smallest n >= 1 with d(n) <= eps (rows of P~^n advanced one step at a
+    time), or -1 if not reached within max_steps."""
+    Pt = np.asarray(Pt, dtype=np.float64)
+    M = Pt.copy()
+    for n in range(1, max_steps + 1):
+        if 0.5 * np.abs(M - pi[None, :]).sum(axis=1).max() <= eps:
+            return n
+        M = M @ Pt
+    return -1

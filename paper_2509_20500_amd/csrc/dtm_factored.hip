@@ -1,0 +1,413 @@
+// Factored transition matrix: power iteration and spectral analysis in O(n)
+// per matrix-vector product, without forming P~.
+//
+// Row i of the dead-time matrix (Section 3.4, Theorem 2) is
+//   P~[i, j] = g_j w_kj / S_k,  k = (i + l) mod n,  g_j = lambda_j e^{-F_j},
+//   w_kj = c = e^{-Lambda} for j < k and 1 otherwise,
+// so with u_k = x_{(k - l) mod n} / S_k and U_j = sum_{k <= j} u_k,
+//   (x P~)_j = g_j sum_k u_k w_kj = g_j (c U_{n-1} + (1 - c) U_j):
+// one prefix scan per product.  Everything here is float64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "dtm_device.hpp"
+#include "dtm_internal.h"
+
+namespace dtm {
+namespace fact {
+
+constexpr int BT = 256;
+constexpr int NVEC = 8;  // float64 vectors of ld per pixel in the scratch region
+
+// Chunk of bins owned by this thread (the layout of pixel_tables).
+__device__ inline void chunk_of(int n, int& j0, int& j1) {
+  const int ch = (n + BT - 1) / BT;
+  j0 = min(static_cast<int>(threadIdx.x) * ch, n);
+  j1 = min(j0 + ch, n);
+}
+
+// y = x P~ (unnormalised).  u is scratch of n doubles; y may alias u but not
+// x.  Ends with block barriers (inside the scan), so callers may reduce.
+__device__ void apply(int n, int l, const double* x, const double* g, const double* invs, double c,
+                      double* u, double* y, double* red) {
+  int j0, j1;
+  chunk_of(n, j0, j1);
+  double cs = 0.0;
+  for (int k = j0; k < j1; ++k) {
+    int i = k - l;
+    if (i < 0) i += n;
+    const double v = x[i] * invs[k];
+    u[k] = v;
+    cs += v;
+  }
+  double tot;
+  const double pre = block_exclusive_scan<BT>(cs, red, tot);
+  double U = pre;
+  for (int j = j0; j < j1; ++j) {
+    U += u[j];
+    y[j] = g[j] * (c * tot + (1.0 - c) * U);
+  }
+}
+
+struct Vecs {
+  double *g, *invs, *x, *u, *dp, *v0, *v1, *v2;
+};
+
+__device__ inline Vecs vecs(double* fact, int64_t vec_elems, const PixelMeta& m) {
+  Vecs V;
+  double* base = fact + m.vec_off;
+  V.g = base;
+  V.invs = base + vec_elems;
+  V.x = base + 2 * vec_elems;
+  V.u = base + 3 * vec_elems;
+  V.dp = base + 4 * vec_elems;
+  V.v0 = base + 5 * vec_elems;
+  V.v1 = base + 6 * vec_elems;
+  V.v2 = base + 7 * vec_elems;
+  return V;
+}
+
+// Tables in float64 for one pixel; returns c = e^{-Lambda}.
+__device__ double tables(const PixelMeta& m, const Vecs& V, double* red) {
+  const double Lam = pixel_tables<double, BT>(m, V.g, nullptr, nullptr, red);
+  const double c = exp(-Lam);
+  row_normalisers<double, BT>(m.n, V.g, c, V.u, V.invs, red);
+  __syncthreads();
+  return c;
+}
+
+// Power iteration on the factored matrix (every sweep float64, treated as a
+// check sweep by the stop rule).  x0 (may be null) seeds it.  Returns the
+// stop state; V.x holds the result.
+template <typename TI>
+__device__ StopState power(const PixelMeta& m, const Vecs& V, double c, const TI* x0, KOpts o,
+                           double* red) {
+  const int n = m.n;
+  int j0, j1;
+  chunk_of(n, j0, j1);
+  StopState st;
+  stop_init(st, 0, 0);
+  double sum = 0.0, bad = 0.0;
+  if (x0) {
+    for (int j = j0; j < j1; ++j) {
+      const double v = static_cast<double>(x0[j]);
+      if (!(v >= 0.0) || !isfinite(v)) bad += 1.0;
+      else sum += v;
+    }
+  }
+  block_sum2<BT>(sum, bad, red);
+  const bool warm = x0 && bad == 0.0 && sum > 0.0 && isfinite(sum);
+  if (x0 && !warm) st.flags |= DTM_INFO_WARM_REJECTED;
+  st.warm = warm ? 1 : 0;
+  for (int j = j0; j < j1; ++j) {
+    V.x[j] = warm ? static_cast<double>(x0[j]) / sum : 1.0 / n;
+    V.dp[j] = 0.0;
+  }
+  __syncthreads();
+  for (;;) {
+    apply(n, m.l, V.x, V.g, V.invs, c, V.u, V.u, red);
+    double sy = 0.0, rs = 0.0;
+    for (int j = j0; j < j1; ++j) {
+      sy += V.u[j];
+      rs += fabs(V.u[j] - V.x[j]);
+    }
+    block_sum2<BT>(sy, rs, red);  // every read of x by apply is done
+    double ch = 0.0, dd = 0.0, ddp = 0.0;
+    for (int j = j0; j < j1; ++j) {
+      const double xn = V.u[j] / sy;
+      const double d = xn - V.x[j];
+      ch += fabs(d);
+      dd += d * d;
+      ddp += d * V.dp[j];
+      V.dp[j] = d;
+      V.x[j] = xn;
+    }
+    block_sum3<BT>(ch, dd, ddp, red);
+    const bool restart = stop_update(st, o, ch, dd, ddp, rs, true, 1.1102230246251565e-16);
+    if (restart) {
+      for (int j = j0; j < j1; ++j) {
+        V.x[j] = 1.0 / n;
+        V.dp[j] = 0.0;
+      }
+    }
+    __syncthreads();
+    if (st.done) break;
+  }
+  return st;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BT) void k_solve_factored(const PixelMeta* __restrict__ metas,
+                                                       double* __restrict__ fact, int64_t vec_elems,
+                                                       const T* __restrict__ x0_packed,
+                                                       T* __restrict__ pi_packed,
+                                                       dtm_solve_info* __restrict__ infos, KOpts o) {
+  __shared__ double red[3 * BT / kWave];
+  const PixelMeta m = metas[blockIdx.x];
+  const Vecs V = vecs(fact, vec_elems, m);
+  const double c = tables(m, V, red);
+  const StopState st = power<T>(m, V, c, x0_packed ? x0_packed + m.pi_off : nullptr, o, red);
+  int j0, j1;
+  chunk_of(m.n, j0, j1);
+  for (int j = j0; j < j1; ++j) pi_packed[m.pi_off + j] = static_cast<T>(V.x[j]);
+  if (threadIdx.x == 0) infos[m.index] = make_info(st);
+}
+
+// Deflated operator A v = v P~ - (v . 1) pi (removes the Perron pair: left
+// eigenvectors of the other eigenvalues are orthogonal to the right Perron
+// vector 1).  out may alias V.u.
+__device__ void deflated(const PixelMeta& m, const Vecs& V, double c, const double* v, double* out,
+                         double* red) {
+  int j0, j1;
+  chunk_of(m.n, j0, j1);
+  double s = 0.0;
+  for (int j = j0; j < j1; ++j) s += v[j];
+  s = block_sum<BT>(s, red);
+  apply(m.n, m.l, v, V.g, V.invs, c, V.u, out, red);
+  for (int j = j0; j < j1; ++j) out[j] -= s * V.x[j];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ metas,
+                                                 double* __restrict__ fact, int64_t vec_elems,
+                                                 double* __restrict__ scal_out,
+                                                 dtm_spectral_info* __restrict__ out, KOpts o,
+                                                 int max_iter) {
+  __shared__ double red[3 * BT / kWave];
+  const PixelMeta m = metas[blockIdx.x];
+  const int n = m.n;
+  const Vecs V = vecs(fact, vec_elems, m);
+  const double c = tables(m, V, red);
+  if (threadIdx.x == 0) scal_out[blockIdx.x] = c;
+  power<double>(m, V, c, static_cast<const double*>(nullptr), o, red);  // pi -> V.x
+  int j0, j1;
+  chunk_of(n, j0, j1);
+  // start: a fixed non-symmetric pattern, deflated
+  for (int j = j0; j < j1; ++j) V.v2[j] = 1.0 + 0.5 * sin(0.7 * j + 0.3) + ((j * 7919) % 13) * 0.01;
+  __syncthreads();
+  deflated(m, V, c, V.v2, V.v0, red);
+  double re = 0.0, im = 0.0, fit = 1.0, prev_re = 2.0, prev_im = 2.0;
+  int it = 0;
+  for (; it < max_iter; ++it) {
+    // normalise v0
+    double nv = 0.0;
+    for (int j = j0; j < j1; ++j) nv += V.v0[j] * V.v0[j];
+    nv = block_sum<BT>(nv, red);
+    if (!(nv > 0.0)) {  // the deflated operator is nil on the start vector
+      re = im = 0.0;
+      fit = 0.0;
+      break;
+    }
+    const double sc = 1.0 / sqrt(nv);
+    for (int j = j0; j < j1; ++j) V.v0[j] *= sc;
+    __syncthreads();
+    deflated(m, V, c, V.v0, V.v1, red);
+    deflated(m, V, c, V.v1, V.v2, red);
+    // least squares v2 ~ a v1 + b v0
+    double g11 = 0.0, g10 = 0.0, g00 = 0.0;
+    double r1 = 0.0, r0 = 0.0, w22 = 0.0;
+    for (int j = j0; j < j1; ++j) {
+      g11 += V.v1[j] * V.v1[j];
+      g10 += V.v1[j] * V.v0[j];
+      g00 += V.v0[j] * V.v0[j];
+      r1 += V.v2[j] * V.v1[j];
+      r0 += V.v2[j] * V.v0[j];
+      w22 += V.v2[j] * V.v2[j];
+    }
+    block_sum3<BT>(g11, g10, g00, red);
+    block_sum3<BT>(r1, r0, w22, red);
+    const double det = g11 * g00 - g10 * g10;
+    double a, b;
+    if (det > 1e-12 * g11 * g00) {
+      a = (r1 * g00 - r0 * g10) / det;
+      b = (g11 * r0 - g10 * r1) / det;
+      const double disc = a * a + 4.0 * b;
+      if (disc < 0.0) {
+        re = 0.5 * a;
+        im = 0.5 * sqrt(-disc);
+      } else {
+        const double s = sqrt(disc);
+        const double z1 = 0.5 * (a + s), z2 = 0.5 * (a - s);
+        re = fabs(z1) >= fabs(z2) ? z1 : z2;
+        im = 0.0;
+      }
+      // residual ||v2 - a v1 - b v0||^2 / ||v2||^2 from the Gram entries
+      const double res2 = w22 - 2.0 * (a * r1 + b * r0) + a * a * g11 + 2.0 * a * b * g10 + b * b * g00;
+      fit = w22 > 0.0 ? sqrt(fmax(res2, 0.0) / w22) : 0.0;
+    } else {  // v1 parallel to v0: one real dominant eigenvalue
+      a = g00 > 0.0 ? g10 / g00 : 0.0;
+      re = a;
+      im = 0.0;
+      const double res2 = g11 - 2.0 * a * g10 + a * a * g00;
+      fit = g11 > 0.0 ? sqrt(fmax(res2, 0.0) / g11) : 0.0;
+    }
+    // next start: v2 (two steps further along)
+    for (int j = j0; j < j1; ++j) V.v0[j] = V.v2[j];
+    __syncthreads();
+    const bool settled = fabs(re - prev_re) <= 1e-12 * (1.0 + fabs(re)) &&
+                         fabs(im - prev_im) <= 1e-12 * (1.0 + fabs(im));
+    prev_re = re;
+    prev_im = im;
+    if (settled && it >= 4) break;
+  }
+  if (threadIdx.x == 0) {
+    dtm_spectral_info s;
+    s.lambda2_re = re;
+    s.lambda2_im = im;
+    s.lambda2_abs = sqrt(re * re + im * im);
+    s.lambda2_arg = atan2(im, re);
+    s.fit_residual = fit;
+    s.iterations = it + 1;
+    s.mixing_steps = -1;
+    out[m.index] = s;
+  }
+}
+
+// Empirical mixing steps: all n start states e_s advanced together, one
+// thread per start state (each thread runs its own prefix scan over the n
+// bins).  X and Y are n x n, stored state-minor (X[k * n + s]) so that a
+// warp reads consecutive states.  Requires the tables and pi in V (from
+// k_spectral).
+__global__ __launch_bounds__(BT) void k_mixing(const PixelMeta* __restrict__ metas,
+                                               double* __restrict__ fact, int64_t vec_elems,
+                                               double* __restrict__ mix, const int64_t* __restrict__ mix_off,
+                                               const double* __restrict__ scal,
+                                               dtm_spectral_info* __restrict__ out, double eps,
+                                               int max_steps) {
+  __shared__ double red[3 * BT / kWave];
+  const PixelMeta m = metas[blockIdx.x];
+  const int n = m.n;
+  const Vecs V = vecs(fact, vec_elems, m);
+  const double c = scal[blockIdx.x];
+  double* X = mix + mix_off[blockIdx.x];
+  double* Y = X + static_cast<int64_t>(n) * n;
+  for (int s = threadIdx.x; s < n; s += BT)
+    for (int k = 0; k < n; ++k) X[static_cast<int64_t>(k) * n + s] = (k == s) ? 1.0 : 0.0;
+  __syncthreads();
+  int steps = -1;
+  for (int t = 1; t <= max_steps; ++t) {
+    double worst = 0.0;
+    for (int s = threadIdx.x; s < n; s += BT) {
+      double tot = 0.0;
+      for (int k = 0; k < n; ++k) {
+        int i = k - m.l;
+        if (i < 0) i += n;
+        tot += X[static_cast<int64_t>(i) * n + s] * V.invs[k];
+      }
+      double U = 0.0, tv = 0.0;
+      for (int j = 0; j < n; ++j) {
+        int i = j - m.l;
+        if (i < 0) i += n;
+        U += X[static_cast<int64_t>(i) * n + s] * V.invs[j];
+        const double y = V.g[j] * (c * tot + (1.0 - c) * U);
+        Y[static_cast<int64_t>(j) * n + s] = y;
+        tv += fabs(y - V.x[j]);
+      }
+      worst = fmax(worst, 0.5 * tv);
+    }
+    // block max
+    for (int off = 32; off > 0; off >>= 1) worst = fmax(worst, __shfl_xor(worst, off, kWave));
+    __syncthreads();
+    if ((threadIdx.x % kWave) == 0) red[threadIdx.x / kWave] = worst;
+    __syncthreads();
+    double wmax = 0.0;
+    for (int i = 0; i < BT / kWave; ++i) wmax = fmax(wmax, red[i]);
+    double* tmp = X;
+    X = Y;
+    Y = tmp;
+    if (wmax <= eps) {
+      steps = t;
+      break;
+    }
+  }
+  if (threadIdx.x == 0) out[m.index].mixing_steps = steps;
+}
+
+}  // namespace fact
+}  // namespace dtm
+
+using namespace dtm;
+
+extern "C" {
+
+int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, void* pi_packed_dev,
+                               dtm_solve_info* infos_dev, dtm_stream_t stream) {
+  if (!plan || !plan->ws || !pi_packed_dev || !infos_dev) return DTM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(plan->ws);
+  const PixelMeta* metas = reinterpret_cast<const PixelMeta*>(w + plan->off_meta);
+  double* fact = reinterpret_cast<double*>(w + plan->off_fact);
+  KOpts o = plan->kopts;
+  o.pad = 0;
+  if (plan->dt == DTM_F32)
+    hipLaunchKernelGGL((fact::k_solve_factored<float>), dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas,
+                       fact, plan->vec_elems, static_cast<const float*>(x0_packed_dev),
+                       static_cast<float*>(pi_packed_dev), infos_dev, o);
+  else
+    hipLaunchKernelGGL((fact::k_solve_factored<double>), dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas,
+                       fact, plan->vec_elems, static_cast<const double*>(x0_packed_dev),
+                       static_cast<double*>(pi_packed_dev), infos_dev, o);
+  return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP;
+}
+
+size_t dtm_spectral_scratch_bytes(const dtm_plan* plan, int32_t with_mixing) {
+  if (!plan) return 0;
+  // 8 float64 vectors per pixel for the deflated iteration, c per pixel, and
+  // optionally two n x n float64 blocks per pixel plus their offsets
+  size_t b = align256(8 * fact::NVEC * static_cast<size_t>(plan->vec_elems));
+  b += align256(8 * static_cast<size_t>(plan->n_pixels));
+  if (with_mixing) {
+    size_t mix = 0;
+    for (const PixelMeta& m : plan->meta) mix += 2 * static_cast<size_t>(m.n) * m.n;
+    b += align256(8 * mix) + align256(8 * static_cast<size_t>(plan->n_pixels));
+  }
+  return b;
+}
+
+int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_steps,
+                         dtm_spectral_info* out_dev, void* scratch_dev, size_t scratch_bytes,
+                         dtm_stream_t stream) {
+  if (!plan || !plan->ws || !out_dev || !scratch_dev || max_steps < 1) return DTM_EINVAL;
+  const bool with_mix = mixing_eps > 0.0;
+  if (scratch_bytes < dtm_spectral_scratch_bytes(plan, with_mix ? 1 : 0)) return DTM_ENOSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(plan->ws);
+  const PixelMeta* metas = reinterpret_cast<const PixelMeta*>(w + plan->off_meta);
+  char* s = static_cast<char*>(scratch_dev);
+  double* fact = reinterpret_cast<double*>(s);
+  size_t off = align256(8 * fact::NVEC * static_cast<size_t>(plan->vec_elems));
+  double* scal = reinterpret_cast<double*>(s + off);
+  off += align256(8 * static_cast<size_t>(plan->n_pixels));
+  KOpts o = plan->kopts;
+  o.tol = 1e-13;
+  o.safety = 1.0;
+  o.stop_rule = DTM_STOP_BOUND;
+  o.pad = 0;
+  hipLaunchKernelGGL(fact::k_spectral, dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas, fact,
+                     plan->vec_elems, scal, out_dev, o, max_steps);
+  if (hipGetLastError() != hipSuccess) return DTM_EHIP;
+  if (!with_mix) return DTM_OK;
+  // k_spectral left g, 1/S, pi and c in the scratch
+  std::vector<int64_t> offs(plan->n_pixels);
+  size_t mix = 0;
+  for (int32_t q = 0; q < plan->n_pixels; ++q) {
+    offs[q] = static_cast<int64_t>(mix);
+    mix += 2 * static_cast<size_t>(plan->meta[q].n) * plan->meta[q].n;
+  }
+  double* mixbuf = reinterpret_cast<double*>(s + off);
+  off += align256(8 * mix);
+  int64_t* mix_off = reinterpret_cast<int64_t*>(s + off);
+  if (hipMemcpyAsync(mix_off, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice, st) !=
+      hipSuccess)
+    return DTM_EHIP;
+  hipLaunchKernelGGL(fact::k_mixing, dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas, fact,
+                     plan->vec_elems, mixbuf, mix_off, scal, out_dev, mixing_eps, max_steps);
+  if (hipGetLastError() != hipSuccess) return DTM_EHIP;
+  // the offsets must outlive the asynchronous copy
+  if (hipStreamSynchronize(st) != hipSuccess) return DTM_EHIP;
+  return DTM_OK;
+}
+
+}  // extern "C"

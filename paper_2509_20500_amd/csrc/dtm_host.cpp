@@ -62,13 +62,13 @@ int fill_opts(const dtm_solve_opts* opt, KOpts* k, int32_t* check_every) {
   if (!(o.safety > 0.0 && o.safety <= 1.0)) return DTM_EINVAL;
   if (o.max_iter < 1 || o.check_every < 1) return DTM_EINVAL;
   if (o.stop_rule != DTM_STOP_CHANGE && o.stop_rule != DTM_STOP_BOUND) return DTM_EINVAL;
-  if (o.flags & ~DTM_FLAG_NO_FINAL_CHECK) return DTM_EINVAL;
+  if (o.flags & ~(DTM_FLAG_NO_FINAL_CHECK | DTM_FLAG_NO_DENSE)) return DTM_EINVAL;
   k->tol = o.tol_l1;
   k->safety = o.safety;
   k->max_iter = o.max_iter;
   k->stop_rule = o.stop_rule;
   k->final_check = (o.flags & DTM_FLAG_NO_FINAL_CHECK) ? 0 : 1;
-  k->pad = 0;
+  k->pad = (o.flags & DTM_FLAG_NO_DENSE) ? 1 : 0;  // no dense pool
   if (check_every) *check_every = o.check_every;
   return DTM_OK;
 }
@@ -275,8 +275,12 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   off = align_up(off + 8 * acc_vec, 256);
   plan->off_part = off;
   off = align_up(off + 8 * static_cast<size_t>(acc_part), 256);
+  // float64 scratch of the factored solver and the spectral analysis:
+  // g, 1/S, x, u, previous difference (5 vectors of ld per pixel)
+  plan->off_fact = off;
+  off = align_up(off + 5 * 8 * static_cast<size_t>(acc_vec), 256);
   plan->off_pool = off;
-  off = align_up(off + es * static_cast<size_t>(acc_pool), 256);
+  if (!ko.pad) off = align_up(off + es * static_cast<size_t>(acc_pool), 256);
   plan->total_bytes = off;
   plan->ws = nullptr;
   plan->ws_bytes = 0;

@@ -55,7 +55,7 @@ struct KOpts {
   int32_t max_iter;
   int32_t stop_rule;
   int32_t final_check;
-  int32_t pad;
+  int32_t pad;  // host only: 1 = the plan has no dense matrix pool
 };
 
 // Convergence bookkeeping of one pixel, shared by both solvers.
@@ -147,7 +147,7 @@ struct dtm_plan {
   int64_t part_elems;              // doubles of band partial sums
   // workspace layout, byte offsets
   size_t off_meta, off_pool, off_colf, off_invs, off_scal, off_state, total_bytes;
-  size_t off_small, off_big, off_items, off_xbuf, off_dprev, off_part;
+  size_t off_small, off_big, off_items, off_xbuf, off_dprev, off_part, off_fact;
   void* ws;            // bound workspace (device), or nullptr
   size_t ws_bytes;
   // created at bind: a second stream (default priority) and two events that

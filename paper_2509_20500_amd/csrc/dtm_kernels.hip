@@ -140,138 +140,6 @@ __global__ __launch_bounds__(BT) void k_shift(const PixelMeta* metas, PixelMeta 
 }
 
 // ============================================================================
-// Stop rule.  The error of power iteration decays like |lambda_2|^t
-// (Section 4); its phase decides whether the iterates approach pi
-// monotonically or oscillate around it.  After sweep t with difference
-// vector d_t = x_{t+1} - x_t:
-//   rho  = max(c_t / c_{t-1}, sqrt(c_t / c_{t-2}))     (|lambda_2| estimate)
-//   if d_t is parallel to d_{t-1} (a real dominant eigenvalue mu, estimated
-//   by projection), the remaining error is |mu| / (1 - mu) * ||d_t||, which
-//   is small for an alternating mu < 0; otherwise the phase-free worst case
-//   rho / (1 - rho) is used.
-// Every thread of a block runs this on identical inputs.
-// ============================================================================
-
-__device__ inline void stop_init(StopState& s, int warm, int flags) {
-  s.c1 = s.c2 = s.c3 = 0.0;
-  s.rho = 0.999;
-  s.gain = 999.0;
-  s.resid = 0.0;
-  s.dd_prev = 0.0;
-  s.iter = 0;
-  s.total_iter = 0;
-  s.check_next = 0;
-  s.done = 0;
-  s.status = DTM_OK;
-  s.flags = flags;
-  s.warm = warm;
-  s.stalled = 0;
-}
-
-__device__ inline double estimate_rho(double c1, double c2, double c3, int t) {
-  double rho;
-  if (t <= 1 || !(c2 > 0.0)) {
-    rho = (t <= 1) ? 0.999 : 0.0;
-  } else {
-    rho = c1 / c2;
-    if (t >= 3 && c3 > 0.0) rho = fmax(rho, sqrt(c1 / c3));
-  }
-  return fmin(fmax(rho, 0.0), 0.999);
-}
-
-// Updates the state after a sweep: change = ||d_t||_1, dd = ||d_t||_2^2,
-// ddp = <d_t, d_{t-1}>, resid = ||x_t P - x_t||_1 (float64 on a check
-// sweep), eps = unit round-off of the iterate's type.  Returns true when the
-// caller must restart from the uniform vector (a warm start that failed).
-__device__ inline bool stop_update(StopState& s, const KOpts& o, double change, double dd,
-                                   double ddp, double resid, bool was_check, double eps) {
-  s.iter += 1;
-  s.total_iter += 1;
-  s.c3 = s.c2;
-  s.c2 = s.c1;
-  s.c1 = change;
-  // Ratios of changes near the round-off floor are noise: keep the last
-  // estimate made above 64 units of round-off.
-  if (s.iter <= 2 || change >= 64.0 * eps) {
-    s.rho = estimate_rho(s.c1, s.c2, s.c3, s.iter);
-    double g = s.rho / (1.0 - s.rho);
-    if (s.iter >= 2 && s.dd_prev > 0.0 && dd > 0.0) {
-      const double mu = ddp / s.dd_prev;
-      const double cos2 = (ddp * ddp) / (dd * s.dd_prev);
-      if (cos2 >= 0.99 && mu < 0.999) g = fmin(g, fabs(mu) / (1.0 - mu));
-    }
-    s.gain = g;
-  }
-  const double gain = s.gain;
-  s.dd_prev = dd;
-  // No progress over two sweeps at the round-off floor of the iterate.
-  const bool stalled = s.iter >= 3 && change > 0.0 && change >= s.c3 && change < 4096.0 * eps;
-  if (stalled) s.stalled = 1;
-  s.resid = resid;
-  if (was_check) {
-    s.flags |= DTM_INFO_CHECKED;
-    const bool ok = (o.stop_rule == DTM_STOP_CHANGE) ? (change < o.tol)
-                                                     : (resid * gain <= o.safety * o.tol);
-    if (ok) {
-      s.done = 1;
-      s.status = DTM_OK;
-      return false;
-    }
-    if (s.stalled) {  // cannot improve further in this precision
-      s.flags |= DTM_INFO_STALLED;
-      s.done = 1;
-      s.status = DTM_ENOTCONV;
-      return false;
-    }
-    s.check_next = 0;
-  } else {
-    const bool fire = (o.stop_rule == DTM_STOP_CHANGE)
-                          ? (change < o.tol)
-                          : (change == 0.0 || (s.iter >= 2 && change * gain <= o.safety * o.tol));
-    if (fire || s.stalled) {
-      if (o.final_check) {
-        s.check_next = 1;
-      } else if (fire) {
-        s.done = 1;
-        s.status = DTM_OK;
-        return false;
-      } else {
-        s.flags |= DTM_INFO_STALLED;
-        s.done = 1;
-        s.status = DTM_ENOTCONV;
-        return false;
-      }
-    }
-  }
-  if (s.iter >= o.max_iter) {
-    if (s.warm && !(s.flags & DTM_INFO_RESTARTED)) {
-      s.flags |= DTM_INFO_RESTARTED;
-      s.iter = 0;
-      s.c1 = s.c2 = s.c3 = 0.0;
-      s.dd_prev = 0.0;
-      s.check_next = 0;
-      s.stalled = 0;
-      return true;
-    }
-    s.done = 1;
-    s.status = DTM_ENOTCONV;
-  }
-  return false;
-}
-
-__device__ inline dtm_solve_info make_info(const StopState& s) {
-  dtm_solve_info info;
-  info.iterations = s.total_iter;
-  info.status = s.status;
-  info.flags = s.flags;
-  info.reserved = 0;
-  info.change_l1 = s.c1;
-  info.residual_l1 = s.resid;
-  info.rho_hat = s.rho;
-  return info;
-}
-
-// ============================================================================
 // Batched fused solver: one block per pixel does the row sums, the shifted
 // build fused with the first power-iteration sweep, the remaining sweeps,
 // the float64 check sweep and the stop rule.  The bin tables g_j and
@@ -1480,6 +1348,7 @@ void dtm_plan_destroy(dtm_plan* plan) {
 int dtm_solve_batched(const dtm_plan* plan, const void* x0_packed_dev, void* pi_packed_dev,
                       dtm_solve_info* infos_dev, dtm_stream_t stream) {
   if (!plan || !plan->ws || !pi_packed_dev || !infos_dev) return DTM_EINVAL;
+  if (plan->kopts.pad) return DTM_ENOTSUP;  // created with DTM_FLAG_NO_DENSE
   const size_t es = dtype_size(plan->dt);
   if (overlaps(pi_packed_dev, es * plan->pi_elems, plan->ws, plan->total_bytes)) return DTM_EALIAS;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1497,6 +1366,7 @@ int dtm_graph_create(const dtm_plan* plan, const void* x0_packed_dev, void* pi_p
   if (!graph_out) return DTM_EINVAL;
   *graph_out = nullptr;
   if (!plan || !plan->ws || !pi_packed_dev || !infos_dev) return DTM_EINVAL;
+  if (plan->kopts.pad) return DTM_ENOTSUP;
   const size_t es = dtype_size(plan->dt);
   if (overlaps(pi_packed_dev, es * plan->pi_elems, plan->ws, plan->total_bytes)) return DTM_EALIAS;
   hipStream_t user = static_cast<hipStream_t>(stream);

@@ -32,6 +32,7 @@ DTM_F32 = 1
 DTM_STOP_CHANGE = 0
 DTM_STOP_BOUND = 1
 DTM_FLAG_NO_FINAL_CHECK = 0x1
+DTM_FLAG_NO_DENSE = 0x2
 
 DTM_INFO_WARM_REJECTED = 0x1
 DTM_INFO_RESTARTED = 0x2
@@ -51,6 +52,7 @@ SYMBOLS = [
     "dtm_graph_create", "dtm_graph_launch", "dtm_graph_destroy",
     "dtm_mlp_workspace_layout", "dtm_mlp_features", "dtm_mlp_sync_bf16", "dtm_mlp_forward",
     "dtm_mlp_backward", "dtm_mlp_adam", "dtm_mlp_gemm_bf16",
+    "dtm_solve_factored_batched", "dtm_spectral_scratch_bytes", "dtm_spectral_batched",
 ]
 
 
@@ -96,6 +98,12 @@ class TileConfig(ctypes.Structure):
 def tiles(fused_threads=0, fused_unroll=0, fused_max_bins=0, band_rows=0, band_sweeps=0):
     return TileConfig(fused_threads, fused_unroll, fused_max_bins, band_rows, band_sweeps)
 
+
+SPECTRAL_INFO_DTYPE = np.dtype([
+    ("lambda2_re", "<f8"), ("lambda2_im", "<f8"), ("lambda2_abs", "<f8"), ("lambda2_arg", "<f8"),
+    ("fit_residual", "<f8"), ("iterations", "<i4"), ("mixing_steps", "<i4"),
+])
+assert SPECTRAL_INFO_DTYPE.itemsize == 48
 
 SOLVE_INFO_DTYPE = np.dtype([
     ("iterations", "<i4"), ("status", "<i4"), ("flags", "<i4"), ("reserved", "<i4"),
@@ -150,6 +158,9 @@ def lib() -> ctypes.CDLL:
         "dtm_graph_create": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
         "dtm_graph_launch": (ctypes.c_int, [_P, _P]),
         "dtm_graph_destroy": (None, [_P]),
+        "dtm_solve_factored_batched": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+        "dtm_spectral_scratch_bytes": (_SZ, [_P, _I32]),
+        "dtm_spectral_batched": (ctypes.c_int, [_P, _D, _I32, _P, _P, _SZ, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -350,6 +361,21 @@ class Plan:
         check(lib().dtm_apply_deadtime_shift_batched(self.handle, _ptr(P_base), _ptr(P), _stream(stream)),
               "dtm_apply_deadtime_shift_batched")
 
+    def solve_factored(self, pi, infos, x0=None, stream=None):
+        """Power iteration on the factored matrix (O(n) per sweep, float64)."""
+        check(lib().dtm_solve_factored_batched(self.handle, _ptr(x0), _ptr(pi), _ptr(infos),
+                                               _stream(stream)), "dtm_solve_factored_batched")
+
+    def spectral_scratch_bytes(self, with_mixing=False):
+        return lib().dtm_spectral_scratch_bytes(self.handle, int(with_mixing))
+
+    def spectral(self, out, scratch, mixing_eps=0.0, max_steps=10000, stream=None):
+        """lambda_2 (and mixing steps when mixing_eps > 0) of every pixel into
+        ``out`` (uint8 tensor of 48 bytes per pixel)."""
+        check(lib().dtm_spectral_batched(self.handle, float(mixing_eps), int(max_steps), _ptr(out),
+                                         _ptr(scratch), scratch.numel(), _stream(stream)),
+              "dtm_spectral_batched")
+
     def graph(self, pi, infos, x0=None, stream=None):
         """Capture one solve into a HIP graph (see Graph)."""
         return Graph(self, pi, infos, x0, stream)
@@ -389,6 +415,11 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def spectral_to_numpy(out_tensor):
+    raw = out_tensor.cpu().numpy().tobytes()
+    return np.frombuffer(raw, dtype=SPECTRAL_INFO_DTYPE).copy()
 
 
 def infos_to_numpy(infos_tensor):

@@ -1,0 +1,108 @@
+"""GPU tests of the factored solver (O(n) sweeps on the same matrix) and of
+the spectral convergence analysis (Section 4) against the float64 oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import dtm as odtm, spectral as ospec
+from synth import scenes as sc
+
+from gpu_helpers import lib, oracle_pi, split, tdtype
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(scenes, dt, opts, no_dense=True):
+    d = lib()
+    if no_dense:
+        opts.flags |= d.DTM_FLAG_NO_DENSE
+    plan = d.Plan(scenes, dt, opts)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.bind(ws)
+    return d, plan, ws
+
+
+@pytest.mark.parametrize("dt,tol,bar", [("f64", 1e-12, 1e-10), ("f32", 1e-10, 1e-6)])
+def test_factored_solver_matches_oracle(dt, tol, bar):
+    scenes = np.concatenate([sc.random_small(40, seed=121), sc.batched_uniform(8, seed=122),
+                             sc.paper_grid(dead_time=95.0), sc.single_pixel_n1000()])
+    d, plan, ws = _plan(scenes, dt, lib().opts(tol=tol))
+    pi = torch.full((plan.pi_elems,), float("nan"), dtype=tdtype(dt), device="cuda")
+    infos = torch.zeros(plan.n_pixels * 40, dtype=torch.uint8, device="cuda")
+    plan.solve_factored(pi, infos)
+    torch.cuda.synchronize()
+    info = d.infos_to_numpy(infos)
+    got = pi.cpu().numpy().astype(np.float64)
+    assert np.all(info["status"] == 0), info[info["status"] != 0]
+    for p, (s, v) in enumerate(zip(scenes, split(got, plan.pi_offsets))):
+        assert np.abs(v - oracle_pi(s)).sum() <= bar, (p, s)
+    # the dense solver cannot run on a plan without matrices
+    with pytest.raises(d.DtmError):
+        plan.solve(pi, infos)
+    plan.close()
+
+
+def test_factored_solver_at_large_n():
+    """n = 65536 (a 16 GiB float32 matrix if formed): check pi by the residual
+    of the factorised left product, written out independently in NumPy."""
+    s = sc.scene(dead_time=41.3, center=33.0, sigma=0.3, signal=2.0, background=0.4, n_bins=65536)
+    d, plan, ws = _plan(s, "f64", lib().opts(tol=1e-11))
+    pi = torch.empty(plan.pi_elems, dtype=torch.float64, device="cuda")
+    infos = torch.zeros(40, dtype=torch.uint8, device="cuda")
+    plan.solve_factored(pi, infos)
+    torch.cuda.synchronize()
+    assert d.infos_to_numpy(infos)["status"][0] == 0
+    x = pi.cpu().numpy()
+    lam, F, Lam, l = odtm.bin_tables(s)
+    g = lam * np.exp(-F)
+    c = math.exp(-Lam)
+    Rh = c * g.sum() + (1 - c) * np.cumsum(g[::-1])[::-1]
+    U = np.cumsum(np.roll(x, l) / Rh)
+    y = g * (c * U[-1] + (1 - c) * U)
+    assert abs(x.sum() - 1) < 1e-12
+    assert np.abs(y - x).sum() < 1e-11
+
+
+def test_spectral_second_eigenvalue_matches_dense_eig():
+    """|lambda_2| and its phase on the paper's (S, B) grids at t_d = 75 and
+    95 ns (Section 4), N = 128, against LAPACK eigenvalues."""
+    levels = (0.1, 3.0, 6.0, 9.0)
+    scenes = np.concatenate([sc.paper_grid(levels, dead_time=75.0, n_bins=128),
+                             sc.paper_grid(levels, dead_time=95.0, n_bins=128),
+                             sc.random_small(12, seed=131)])
+    d, plan, ws = _plan(scenes, "f64", lib().opts(tol=1e-12))
+    scratch = torch.empty(plan.spectral_scratch_bytes(False), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(plan.n_pixels * 48, dtype=torch.uint8, device="cuda")
+    plan.spectral(out, scratch, 0.0, 5000)
+    torch.cuda.synchronize()
+    res = d.spectral_to_numpy(out)
+    checked = 0
+    for p, s in enumerate(scenes):
+        lam, third = ospec.second_eigenvalue(odtm.transition_matrix(s))
+        if third > 0.9 * abs(lam) or abs(lam) < 1e-6:
+            continue  # the two-term fit needs a separated dominant eigenvalue
+        checked += 1
+        assert abs(res["lambda2_abs"][p] - abs(lam)) < 1e-6 * max(1.0, abs(lam)), (p, s, res[p], lam)
+        assert abs(res["lambda2_arg"][p] - abs(np.angle(lam))) < 1e-4, (p, s, res[p], lam)
+    assert checked >= 24
+    plan.close()
+
+
+def test_mixing_steps_match_dense_powers():
+    levels = (0.1, 3.0, 9.0)
+    scenes = np.concatenate([sc.paper_grid(levels, dead_time=75.0, n_bins=64),
+                             sc.paper_grid(levels, dead_time=95.0, n_bins=96)])
+    d, plan, ws = _plan(scenes, "f64", lib().opts(tol=1e-12))
+    scratch = torch.empty(plan.spectral_scratch_bytes(True), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(plan.n_pixels * 48, dtype=torch.uint8, device="cuda")
+    for eps in (0.25, 1e-3):
+        plan.spectral(out, scratch, eps, 5000)
+        torch.cuda.synchronize()
+        res = d.spectral_to_numpy(out)
+        for p, s in enumerate(scenes):
+            Pt = odtm.transition_matrix(s)
+            ref = ospec.mixing_steps(Pt, odtm.stationary_solve(Pt), eps)
+            assert res["mixing_steps"][p] == ref, (p, s, eps, res[p], ref)
+    plan.close()

@@ -290,3 +290,40 @@ def test_monte_carlo_without_dead_time_is_the_arrival_pdf():
     F = dtm.cumulative_flux(edges, s)
     ref = np.diff(F) / F[-1]
     assert np.abs(h - ref).sum() < 3 * mc.noise_floor_l1(20, n_reg)
+
+
+# ---------------------------------------------------------------------------
+# Spectral quantities (Section 4)
+# ---------------------------------------------------------------------------
+def test_second_eigenvalue_two_state_closed_form():
+    from oracle import spectral
+    s = sc.scene(dead_time=13.0, center=20.0, sigma=5.0, signal=1.3, background=0.4, n_bins=2)
+    Pt = dtm.transition_matrix(s)
+    lam, _ = spectral.second_eigenvalue(Pt)
+    assert abs(lam - (1.0 - Pt[0, 1] - Pt[1, 0])) < 1e-15
+
+
+def test_second_eigenvalue_of_pure_background_is_a_dft_value():
+    """S = 0: P~ is circulant, so its eigenvalues are the discrete Fourier
+    transform of its first row."""
+    from oracle import spectral
+    s = sc.scene(dead_time=31.0, signal=0.0, background=3.0, n_bins=64)
+    Pt = dtm.transition_matrix(s)
+    row = Pt[0]
+    k = np.arange(64)
+    dft = np.array([np.sum(row * np.exp(2j * np.pi * k * m / 64)) for m in range(64)])
+    dft = dft[np.argsort(-np.abs(dft))]
+    lam, _ = spectral.second_eigenvalue(Pt)
+    assert abs(abs(lam) - abs(dft[1])) < 1e-12
+
+
+def test_mixing_steps_two_state_closed_form():
+    """Two states: d(n) = |lambda_2|^n max(pi_0, pi_1)."""
+    from oracle import spectral
+    s = sc.scene(dead_time=45.0, center=20.0, sigma=5.0, signal=3.0, background=2.0, n_bins=2)
+    Pt = dtm.transition_matrix(s)
+    pi = dtm.stationary_solve(Pt)
+    lam = abs(1.0 - Pt[0, 1] - Pt[1, 0])
+    for eps in (0.25, 1e-3, 1e-6):
+        ref = next(n for n in range(1, 10000) if lam ** n * pi.max() <= eps)
+        assert spectral.mixing_steps(Pt, pi, eps) == ref
