@@ -262,6 +262,32 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
                          dtm_spectral_info* out_dev, void* scratch_dev, size_t scratch_bytes,
                          dtm_stream_t stream);
 
+/* Monte Carlo simulation of the detector the chain models (Section 2.1), for
+ * checking the model against physics (Section 3.5 does the same): for every
+ * pixel, runs_per_pixel independent runs of `cycles` laser periods with
+ * Poisson arrivals of rate lambda(t), a non-paralyzable dead time and
+ * free-running rearm; registrations in periods >= burn_cycles are counted in
+ * n_b bins of X = T mod t_r (bin ceil(X / Delta) - 1).
+ *
+ * Random numbers: Philox4x32-10 with key = seed and counter = (draw block,
+ * period, run, pixel index); the sampling steps (Knuth Poisson draws,
+ * Box-Muller pulse times, time-ordered visit with the rearm time carried from
+ * period to period) are fixed, so another implementation of the same steps
+ * reproduces the counts exactly.
+ *
+ * hist_packed_dev: uint32 counts packed like pi (runs summed), overwritten.
+ * overflow_dev: one uint32 per pixel (input order), zeroed by the caller; set
+ * when a period held more than 64 photons (then only 64 were used).
+ * lanes_per_run: 0 = automatic, else a power of two <= 64 (lanes that share
+ * one run; the counts do not depend on it).  Requires S + B <= 24,
+ * n_b <= 16384, 1 <= runs_per_pixel <= 65535, 0 <= burn_cycles < cycles <
+ * 2^32 and runs_per_pixel * (cycles - burn_cycles) < 2^26 (so no bin can pass
+ * 2^32); else DTM_EINVAL or DTM_ENOTSUP and nothing is launched.  The plan
+ * must be bound; launch only. */
+int dtm_mc_histograms(const dtm_plan* plan, int32_t runs_per_pixel, int64_t cycles,
+                      int64_t burn_cycles, uint64_t seed, int32_t lanes_per_run,
+                      uint32_t* hist_packed_dev, uint32_t* overflow_dev, dtm_stream_t stream);
+
 /* HIP graph of one dtm_solve_batched call: every launch of the solve is
  * captured once and replayed by dtm_graph_launch, which saves the per-launch
  * host cost of the banded path's sweep loop.  The plan, its workspace and the

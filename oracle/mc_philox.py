@@ -1,0 +1,117 @@
+"""Monte Carlo dead-time detector driven by a counter-based generator.
+
+TEST INFRASTRUCTURE ONLY.  The same physics as ``montecarlo`` (Section 2.1:
+Poisson arrivals of rate lambda(t) per period, non-paralyzable dead time,
+free-running rearm, X_k = T_k mod t_r), but every random number comes from
+Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as
+easy as 1, 2, 3", SC 2011), written here from its published definition, and
+the sampling steps are spelled out so that another implementation of the
+same steps (the GPU simulator) can be compared count for count:
+
+* stream of a period: key = (seed low word, seed high word), counter =
+  (draw block, period c, run, pixel); each block gives four 32-bit words,
+  consumed in order; a uniform is (w + 0.5) / 2^32.  Periods draw from
+  streams of their own, so a simulator may generate them in any order;
+* per period: Knuth's product-of-uniforms Poisson draw for the pulse count
+  (threshold exp(-S)), then for the background count (threshold exp(-B));
+  each pulse photon: t = tau + sigma sqrt(-2 ln u1) cos(2 pi u2), kept when
+  0 <= t < t_r; each background photon: t = t_r u;
+* the detector state is the rearm time a, measured from the start of the
+  current period (0 at the start of a run: armed).  The period's photons are
+  sorted by time and visited in order; a photon at t >= a is registered and
+  sets a = t + t_d.  At the end of the period a becomes max(a - t_r, 0);
+* registrations in the first `burn` periods are not counted; the bin of a
+  count is ceil(t / Delta) - 1 (0 maps to the last bin).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+M0, M1 = 0xD2511F53, 0xCD9E8D57
+W0, W1 = 0x9E3779B9, 0xBB67AE85
+MASK = 0xFFFFFFFF
+
+
+def philox4x32_10(ctr, key):
+    """Ten Philox rounds on a 4-word counter with a 2-word key."""
+    c0, c1, c2, c3 = (int(x) & MASK for x in ctr)
+    k0, k1 = (int(x) & MASK for x in key)
+    for r in range(10):
+        if r:
+            k0 = (k0 + W0) & MASK
+            k1 = (k1 + W1) & MASK
+        p0 = M0 * c0
+        p1 = M1 * c2
+        hi0, lo0 = p0 >> 32, p0 & MASK
+        hi1, lo1 = p1 >> 32, p1 & MASK
+        c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+    return c0, c1, c2, c3
+
+
+class Stream:
+    def __init__(self, seed, cycle, run, pixel):
+        self.key = (seed & MASK, (seed >> 32) & MASK)
+        self.ctr = (cycle & MASK, run & MASK, pixel & MASK)
+        self.block = 0
+        self.buf = []
+
+    def uniform(self):
+        if not self.buf:
+            self.buf = list(philox4x32_10((self.block,) + self.ctr, self.key))
+            self.block += 1
+        return (self.buf.pop(0) + 0.5) / 4294967296.0
+
+
+def poisson(st, threshold):
+    k = 0
+    p = st.uniform()
+    while p > threshold:
+        k += 1
+        p *= st.uniform()
+    return k
+
+
+def simulate_run(scene_fields, cycles, burn, seed, run, pixel, hist):
+    """Adds the registrations of one run to ``hist`` (n_b integer counts)."""
+    t_r, t_d, tau, sigma, S, B, n = scene_fields
+    e_s, e_b = math.exp(-S), math.exp(-B)
+    delta = t_r / n
+    a = 0.0
+    for c in range(cycles):
+        st = Stream(seed, c, run, pixel)
+        ns = poisson(st, e_s)
+        nb = poisson(st, e_b)
+        ts = []
+        for _ in range(ns):
+            u1 = st.uniform()
+            u2 = st.uniform()
+            t = tau + sigma * (math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2))
+            if 0.0 <= t < t_r:
+                ts.append(t)
+        for _ in range(nb):
+            ts.append(t_r * st.uniform())
+        ts.sort()
+        for t in ts:
+            if t >= a:
+                a = t + t_d
+                if c >= burn:
+                    j = math.ceil(t / delta) - 1
+                    hist[j % n] += 1
+        a = max(a - t_r, 0.0)
+    return hist
+
+
+def histograms(scenes, runs, cycles, burn, seed):
+    """Counts per pixel (list of int arrays), runs summed."""
+    out = []
+    for p, s in enumerate(np.asarray(scenes).reshape(-1)):
+        f = (float(s["period_ns"]), float(s["dead_time_ns"]), float(s["pulse_center_ns"]),
+             float(s["pulse_sigma_ns"]), float(s["signal_flux"]), float(s["background_flux"]),
+             int(s["n_bins"]))
+        h = np.zeros(f[6], dtype=np.int64)
+        for r in range(runs):
+            simulate_run(f, cycles, burn, seed, r, p, h)
+        out.append(h)
+    return out

@@ -202,6 +202,9 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
     shift_bins(s, &m.l);
     m.ld = padded_ld(s.n_bins, dt);
     m.index = p;
+    m.t_d = s.dead_time_ns;
+    m.e_s = std::exp(-s.signal_flux);
+    m.e_b = std::exp(-s.background_flux);
     m.pi_off = pi_off[p];
     m.vec_off = acc_vec;
     m.mat_off = acc_pool;

@@ -36,8 +36,10 @@ struct PixelMeta {
   int64_t part_off; // banded pixels: offset (in doubles) of the band partial sums
   int32_t bands;    // banded pixels: row bands (0 for pixels of the fused kernel)
   int32_t big;      // position in the banded-pixel list, or -1
+  double t_d;       // dead time (Monte Carlo simulator)
+  double e_s, e_b;  // exp(-S), exp(-B), from the host's libm (Monte Carlo simulator)
 };
-static_assert(sizeof(PixelMeta) == 104, "PixelMeta layout");
+static_assert(sizeof(PixelMeta) == 128, "PixelMeta layout");
 
 // One work item of the banded sweep: a band of rows times a block of columns
 // of one pixel.

@@ -875,6 +875,12 @@ PixelMeta single_meta(const dtm_scene& s, dtm_dtype dt) {
   shift_bins(s, &m.l);
   m.ld = padded_ld(s.n_bins, dt);
   m.index = 0;
+  m.t_d = s.dead_time_ns;
+  m.e_s = std::exp(-s.signal_flux);
+  m.e_b = std::exp(-s.background_flux);
+  m.bands = 0;
+  m.big = -1;
+  m.part_off = 0;
   m.pi_off = 0;
   m.vec_off = 0;
   m.mat_off = 0;

@@ -1,0 +1,261 @@
+// Monte Carlo simulation of the asynchronous SPAD with dead time (Section 2.1):
+// Poisson photon arrivals of rate lambda(t) in every laser period, a
+// non-paralyzable dead time after each registration, free-running rearm, and
+// a histogram of X_k = T_k mod t_r.  It checks the Markov model against the
+// physics it approximates (Section 3.5 compares with Monte Carlo the same way).
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011), one
+// stream per period: key = seed, counter = (draw block, period, run, pixel).
+// Each block yields four 32-bit words, consumed in order; u = (w + 1/2) / 2^32.
+// Per period: Knuth's product-of-uniforms Poisson draws (pulse, then
+// background; thresholds exp(-S), exp(-B) computed on the host), pulse
+// photons tau + sigma sqrt(-2 ln u1) cos(2 pi u2) kept inside [0, t_r),
+// background photons t_r u.  The detector state is the rearm time a relative
+// to the period start (0 = armed): photons are visited in time order, one at
+// t >= a is registered and sets a = t + t_d; the period ends with
+// a = max(a - t_r, 0).
+//
+// A run is sequential only through a, so a group of L lanes simulates one
+// run: each lane draws and sorts one period of a chunk of L periods (its own
+// stream), then the group hands a from lane to lane through the chunk.  L = 1
+// (a lane per run) has the highest throughput when runs fill the chip; L = 64
+// (a wave per run) the lowest latency when there are few runs (a run's time
+// is then set by its hand-over chain, not by its drawing).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "dtm_internal.h"
+
+// Every product and sum below is rounded on its own (no fused multiply-add),
+// so that the pulse times, period bases and dead-time comparisons are the
+// ones any IEEE double implementation of the same steps computes.
+#pragma clang fp contract(off)
+
+namespace dtm {
+namespace mc {
+
+constexpr int BT = 64;    // one wave per block
+constexpr int MAXP = 64;  // photons of one period kept (S + B <= 24: P(more) < 1e-10)
+
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+    const uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+struct Stream {
+  uint32_t k0, k1, cycle, run, pixel, block;
+  uint32_t buf[4];
+  int pos;
+
+  __device__ double uniform() {
+    if (pos == 4) {
+      buf[0] = block++;
+      buf[1] = cycle;
+      buf[2] = run;
+      buf[3] = pixel;
+      philox4x32_10(buf, k0, k1);
+      pos = 0;
+    }
+    const uint32_t w = pos == 0 ? buf[0] : pos == 1 ? buf[1] : pos == 2 ? buf[2] : buf[3];
+    ++pos;
+    return (static_cast<double>(w) + 0.5) * (1.0 / 4294967296.0);
+  }
+};
+
+__device__ inline int poisson(Stream& st, double threshold) {
+  int k = 0;
+  double p = st.uniform();
+  while (p > threshold) {
+    ++k;
+    p *= st.uniform();
+  }
+  return k;
+}
+
+// Value of lane `src` (wave-uniform) on every lane.
+__device__ inline double broadcast_wave(double v, int src) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(u)), src));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(u >> 32)), src));
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+__global__ __launch_bounds__(BT) void k_zero(uint32_t* __restrict__ p, size_t n) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * BT + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Grid (pixel, run block); block = one wave = 64 / L runs of one pixel.
+// LDS: the period photon lists, column per lane ([MAXP][64] doubles), then
+// the pixel's histogram (n uint32), added atomically to HBM at the end.
+__global__ __launch_bounds__(BT) void k_mc(const PixelMeta* __restrict__ metas, int runs, int64_t cycles,
+                                           int64_t burn, uint64_t seed, int L,
+                                           uint32_t* __restrict__ hist, uint32_t* __restrict__ overflow) {
+  extern __shared__ double lds_d[];
+  double* ts = lds_d;                                         // [MAXP][BT]
+  uint32_t* h = reinterpret_cast<uint32_t*>(lds_d + MAXP * BT);
+  const PixelMeta m = metas[blockIdx.x];
+  const int n = m.n;
+  const int lane = threadIdx.x;
+  for (int j = lane; j < n; j += BT) h[j] = 0u;
+  __syncthreads();
+  const int k_in = lane % L, base_lane = lane - k_in;
+  const int run = blockIdx.y * (BT / L) + lane / L;
+  const bool run_ok = run < runs;
+  const double delta = m.t_r / n;
+  const double two_pi = 2.0 * 3.141592653589793;
+  bool over = false;
+  double a = 0.0;  // rearm time of this lane's run, relative to the chunk's next period
+  for (int64_t c0 = 0; c0 < cycles; c0 += L) {
+    const int64_t c = c0 + k_in;
+    const bool mine = run_ok && c < cycles;
+    int cnt = 0;
+    if (mine) {
+      Stream st;
+      st.k0 = static_cast<uint32_t>(seed);
+      st.k1 = static_cast<uint32_t>(seed >> 32);
+      st.cycle = static_cast<uint32_t>(c);
+      st.run = static_cast<uint32_t>(run);
+      st.pixel = static_cast<uint32_t>(m.index);
+      st.block = 0u;
+      st.pos = 4;
+      const int ns = poisson(st, m.e_s);
+      const int nb = poisson(st, m.e_b);
+      for (int i = 0; i < ns; ++i) {
+        const double u1 = st.uniform();
+        const double u2 = st.uniform();
+        const double t = m.tau + m.sigma * (sqrt(-2.0 * log(u1)) * cos(two_pi * u2));
+        if (t >= 0.0 && t < m.t_r) {
+          if (cnt < MAXP) ts[cnt++ * BT + lane] = t;
+          else over = true;
+        }
+      }
+      for (int i = 0; i < nb; ++i) {
+        const double t = m.t_r * st.uniform();
+        if (cnt < MAXP) ts[cnt++ * BT + lane] = t;
+        else over = true;
+      }
+      for (int x = 1; x < cnt; ++x) {  // insertion sort of this lane's column
+        const double v = ts[x * BT + lane];
+        int y = x - 1;
+        while (y >= 0 && ts[y * BT + lane] > v) {
+          ts[(y + 1) * BT + lane] = ts[y * BT + lane];
+          --y;
+        }
+        ts[(y + 1) * BT + lane] = v;
+      }
+    }
+    // Entering at or before the first photon, the period's registrations do
+    // not depend on a: its exit rearm time A0 is found here, in parallel.
+    double t0 = 0.0, A0 = 0.0;
+    if (mine && cnt > 0) {
+      t0 = ts[lane];
+      double aa = 0.0;
+      for (int x = 0; x < cnt; ++x) {
+        const double t = ts[x * BT + lane];
+        if (t >= aa) aa = t + m.t_d;
+      }
+      A0 = fmax(aa - m.t_r, 0.0);
+    }
+    // Hand a through the chunk: the lane holding period c0 + k notes its
+    // entry rearm time and forms its exit one, which every lane of the group
+    // then takes.
+    double a_in = 0.0;
+    for (int k = 0; k < L; ++k) {
+      if (mine && k_in == k) {
+        a_in = a;
+        if (cnt == 0) {
+          a = fmax(a - m.t_r, 0.0);
+        } else if (a <= t0) {
+          a = A0;
+        } else {
+          for (int x = 0; x < cnt; ++x) {
+            const double t = ts[x * BT + lane];
+            if (t >= a) a = t + m.t_d;
+          }
+          a = fmax(a - m.t_r, 0.0);
+        }
+      }
+      if (L == BT) a = broadcast_wave(a, k);
+      else if (L > 1) a = __shfl(a, base_lane + k, BT);
+    }
+    // Registrations of every period of the chunk, in parallel.
+    if (mine && c >= burn) {
+      double aa = a_in;
+      for (int x = 0; x < cnt; ++x) {
+        const double t = ts[x * BT + lane];
+        if (t >= aa) {
+          aa = t + m.t_d;
+          int j = static_cast<int>(ceil(t / delta)) - 1;
+          if (j < 0) j += n;
+          if (j >= n) j -= n;
+          atomicAdd(&h[j], 1u);
+        }
+      }
+    }
+  }
+  if (over) atomicOr(&overflow[m.index], 1u);
+  __syncthreads();
+  for (int j = lane; j < n; j += BT)
+    if (h[j]) atomicAdd(&hist[m.pi_off + j], h[j]);
+}
+
+}  // namespace mc
+}  // namespace dtm
+
+using namespace dtm;
+
+extern "C" int dtm_mc_histograms(const dtm_plan* plan, int32_t runs_per_pixel, int64_t cycles,
+                                 int64_t burn_cycles, uint64_t seed, int32_t lanes_per_run,
+                                 uint32_t* hist_packed_dev, uint32_t* overflow_dev, dtm_stream_t stream) {
+  if (!plan || !plan->ws || !hist_packed_dev || !overflow_dev) return DTM_EINVAL;
+  if (runs_per_pixel < 1 || runs_per_pixel > 65535 || cycles < 1 || cycles > 0xFFFFFFFFll ||
+      burn_cycles < 0 || burn_cycles >= cycles)
+    return DTM_EINVAL;
+  if (static_cast<double>(runs_per_pixel) * static_cast<double>(cycles - burn_cycles) >= 67108864.0)
+    return DTM_EINVAL;
+  if (lanes_per_run < 0 || lanes_per_run > mc::BT || (lanes_per_run & (lanes_per_run - 1)))
+    return DTM_EINVAL;
+  if (plan->max_n > 16384) return DTM_ENOTSUP;
+  for (const PixelMeta& m : plan->meta)
+    if (m.S + m.B > 24.0) return DTM_ENOTSUP;
+  int L = lanes_per_run;
+  if (L == 0) {
+    // At least 8 lanes per run, more until the runs give about one and a
+    // half waves to each SIMD of the 256 CUs (measured: the longer hand-over
+    // chain of a larger group costs less than an idle SIMD).
+    const double chains = static_cast<double>(plan->n_pixels) * runs_per_pixel;
+    L = 8;
+    while (L < mc::BT && chains * L < 256.0 * 4 * 64 * 1.5) L *= 2;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const char* w = static_cast<const char*>(plan->ws);
+  const PixelMeta* metas = reinterpret_cast<const PixelMeta*>(w + plan->off_meta);
+  const size_t lds = sizeof(double) * mc::MAXP * mc::BT + sizeof(uint32_t) * static_cast<size_t>(plan->max_n);
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(mc::k_mc), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          static_cast<int>(lds)) != hipSuccess)
+    return DTM_EHIP;
+  const size_t total = plan->pi_elems;
+  hipLaunchKernelGGL(mc::k_zero, dim3(static_cast<unsigned>((total + mc::BT - 1) / mc::BT)), dim3(mc::BT), 0, st,
+                     hist_packed_dev, total);
+  const int per_block = mc::BT / L;
+  const unsigned run_blocks = static_cast<unsigned>((runs_per_pixel + per_block - 1) / per_block);
+  hipLaunchKernelGGL(mc::k_mc, dim3(plan->n_pixels, run_blocks), dim3(mc::BT), lds, st, metas, runs_per_pixel,
+                     cycles, burn_cycles, seed, L, hist_packed_dev, overflow_dev);
+  return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP;
+}

@@ -53,6 +53,7 @@ SYMBOLS = [
     "dtm_mlp_workspace_layout", "dtm_mlp_features", "dtm_mlp_sync_bf16", "dtm_mlp_forward",
     "dtm_mlp_backward", "dtm_mlp_adam", "dtm_mlp_gemm_bf16",
     "dtm_solve_factored_batched", "dtm_spectral_scratch_bytes", "dtm_spectral_batched",
+    "dtm_mc_histograms",
 ]
 
 
@@ -161,6 +162,7 @@ def lib() -> ctypes.CDLL:
         "dtm_solve_factored_batched": (ctypes.c_int, [_P, _P, _P, _P, _P]),
         "dtm_spectral_scratch_bytes": (_SZ, [_P, _I32]),
         "dtm_spectral_batched": (ctypes.c_int, [_P, _D, _I32, _P, _P, _SZ, _P]),
+        "dtm_mc_histograms": (ctypes.c_int, [_P, _I32, _I64, _I64, ctypes.c_uint64, _I32, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -375,6 +377,17 @@ class Plan:
         check(lib().dtm_spectral_batched(self.handle, float(mixing_eps), int(max_steps), _ptr(out),
                                          _ptr(scratch), scratch.numel(), _stream(stream)),
               "dtm_spectral_batched")
+
+    def mc_histograms(self, runs, cycles, burn, seed, lanes_per_run=0, stream=None):
+        """Monte Carlo registration counts (packed like pi, uint32 as int32
+        tensor) and per-pixel overflow flags."""
+        import torch
+        hist = torch.zeros(self.pi_elems, dtype=torch.int32, device="cuda")
+        over = torch.zeros(self.n_pixels, dtype=torch.int32, device="cuda")
+        check(lib().dtm_mc_histograms(self.handle, int(runs), int(cycles), int(burn), int(seed),
+                                      int(lanes_per_run), _ptr(hist), _ptr(over), _stream(stream)),
+              "dtm_mc_histograms")
+        return hist, over
 
     def graph(self, pi, infos, x0=None, stream=None):
         """Capture one solve into a HIP graph (see Graph)."""

@@ -327,3 +327,34 @@ def test_mixing_steps_two_state_closed_form():
     for eps in (0.25, 1e-3, 1e-6):
         ref = next(n for n in range(1, 10000) if lam ** n * pi.max() <= eps)
         assert spectral.mixing_steps(Pt, pi, eps) == ref
+
+
+# ---------------------------------------------------------------------------
+# Counter-based Monte Carlo (Philox4x32-10)
+# ---------------------------------------------------------------------------
+def test_philox_known_answers():
+    import os
+    from oracle.mc_philox import philox4x32_10
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert list(philox4x32_10(v[0:4], v[4:6])) == v[6:10]
+
+
+@pytest.mark.slow
+def test_philox_monte_carlo_agrees_with_numpy_monte_carlo_and_model():
+    """Two independent simulators of the same detector (different generators
+    and sampling code) agree within their noise, and both approach the
+    Markov model."""
+    from oracle import mc_philox
+    s = sc.scene(period=100.0, dead_time=75.0, center=30.0, sigma=2.0, signal=2.0, background=0.5,
+                 n_bins=32)
+    hp = mc_philox.histograms(s, runs=2, cycles=15000, burn=150, seed=12345)[0].astype(float)
+    hp /= hp.sum()
+    hn, n_reg = mc.registration_histogram(s, 60000, seed=4)
+    noise = mc.noise_floor_l1(32, 30000) + mc.noise_floor_l1(32, n_reg)
+    assert np.abs(hp - hn).sum() < 2.0 * noise
+    pi = dtm.stationary_pdf(s)
+    assert np.abs(hp - pi).sum() < 0.1 + 2 * mc.noise_floor_l1(32, 30000)
