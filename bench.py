@@ -53,6 +53,236 @@ def measured_traffic(kernel, workload):
     return None
 
 
+MC_SOURCES = ("dtm_mc.hip", "dtm_internal.h", "dtm_host.cpp")
+VALU_PEAK_G = 256 * 4 * 2.4e9 / 4 / 1e9  # wave64 VALU instructions/s: 256 CUs x 4 SIMDs, 4 cycles each
+
+
+def sources_sha1(files):
+    import hashlib
+    h = hashlib.sha1()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2509_20500_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profile_record(tag, kernel, workload, files):
+    """Value of a 'tag: kernel=... workload=... sha1=... value=...' line in
+    the committed rocprofv3 summaries (profiles/*.md), or None when there is
+    none for these sources."""
+    import glob
+    sha = sources_sha1(files)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith(tag + ":"):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("sha1") == sha:
+                    return float(kv["value"])
+    return None
+
+
+def _mc_oracle_one(rec):
+    import numpy as np
+
+    from oracle import mc_philox
+    fields, cycles, seed, run, pixel = rec
+    h = np.zeros(fields[6], dtype=np.int64)
+    mc_philox.simulate_run(fields, cycles, 0, seed, run, pixel, h)
+    return int(h.sum())
+
+
+def mc_cpu_baseline(scenes, cycles=6000, runs=4):
+    """The counter-based oracle simulator (pure Python) on a bounded sample:
+    `runs` runs of `cycles` periods for every scene, one process per host
+    core (capped at 16)."""
+    import multiprocessing as mp
+    workers = max(1, min(os.cpu_count() or 1, 16))
+    recs = []
+    for p, s in enumerate(scenes):
+        f = (float(s["period_ns"]), float(s["dead_time_ns"]), float(s["pulse_center_ns"]),
+             float(s["pulse_sigma_ns"]), float(s["signal_flux"]), float(s["background_flux"]),
+             int(s["n_bins"]))
+        recs += [(f, cycles, 5, r, p) for r in range(runs)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        pool.map(_noop, range(workers))
+        t0 = time.perf_counter()
+        pool.map(_mc_oracle_one, recs, chunksize=1)
+        dt = time.perf_counter() - t0
+    periods = len(recs) * cycles
+    return {"value": periods / dt, "unit": "laser periods/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(scenes)} scenes of the S,B in {{0.1,3,6,9}} grid x {runs} runs x {cycles} "
+                      f"periods (pure-Python Philox simulator); {workers} processes; {dt:.2f} s wall"}
+
+
+def mc_sweep_workload(args):
+    """The Monte Carlo validation of the model (Section 3.5): (b) S, B in
+    {0.1, 3, 6, 9}, 100 runs x 50,000 periods at 2^10 bins, against the
+    model at 2^5..2^10 bins; (c) S, B over [0, 10] (levels 0.1, 1..10), 25
+    runs x 50,000 periods at 2^8 bins.  Dead time 75 ns, period 100 ns,
+    pulse at 30 ns with sigma 0.5 ns.  One step = both simulations and the
+    float64 model solves for all (S, B, N), on the GPU."""
+    import numpy as np
+    import torch
+
+    from paper_2509_20500_amd import dtm
+    from synth import scenes as sc
+
+    cycles, burn = 50_000, 100
+    e2 = sc.paper_grid(dead_time=75.0, n_bins=1024)
+    e3 = sc.paper_rmse_grid(n_bins=256, dead_time=75.0)
+    levels = [2 ** k for k in range(5, 11)]
+    model = np.concatenate([sc.paper_grid(dead_time=75.0, n_bins=nb) for nb in levels] + [e3])
+    plans, keep = [], []
+    for scenes, opts in ((e2, dtm.opts(tol=1e-10)), (e3, dtm.opts(tol=1e-10)), (model, dtm.opts(tol=1e-12))):
+        pl = dtm.Plan(scenes, "f64", opts)
+        ws = torch.empty(pl.workspace_bytes, dtype=torch.uint8, device="cuda")
+        pl.bind(ws)
+        plans.append(pl)
+        keep.append(ws)
+    p2, p3, pm = plans
+    h2 = torch.empty(p2.pi_elems, dtype=torch.int32, device="cuda")
+    h3 = torch.empty(p3.pi_elems, dtype=torch.int32, device="cuda")
+    o2 = torch.zeros(p2.n_pixels, dtype=torch.int32, device="cuda")
+    o3 = torch.zeros(p3.n_pixels, dtype=torch.int32, device="cuda")
+    pi = torch.empty(pm.pi_elems, dtype=torch.float64, device="cuda")
+    infos = torch.zeros(pm.n_pixels * 40, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    mc_ms = []
+
+    def step(record=False):
+        if record:
+            ev[0].record(stream)
+        p2.mc_histograms(100, cycles, burn, 2509, hist=h2, over=o2)
+        if record:
+            ev[1].record(stream)
+            ev[2].record(stream)
+        p3.mc_histograms(25, cycles, burn, 20500, hist=h3, over=o3)
+        if record:
+            ev[3].record(stream)
+        pm.solve(pi, infos)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(args.steps):
+        step(record=True)
+        torch.cuda.synchronize()  # per-launch events are read after each step
+        mc_ms.append((ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])))
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms_step = start.elapsed_time(end) / args.steps
+    periods = cycles * (100 * p2.n_pixels + 25 * p3.n_pixels)
+    k2 = float(np.mean([a for a, _ in mc_ms]))
+    k3 = float(np.mean([b for _, b in mc_ms]))
+
+    info = dtm.infos_to_numpy(infos)
+    pis = pi.cpu().numpy()
+    offm = pm.pi_offsets
+    hist2 = h2.cpu().numpy().view(np.uint32).astype(np.float64)
+    hist3 = h3.cpu().numpy().view(np.uint32).astype(np.float64)
+    off2, off3 = p2.pi_offsets, p3.pi_offsets
+    table = {}
+    for li, nb in enumerate(levels):
+        l1s, rms = [], []
+        for q in range(p2.n_pixels):
+            h = hist2[off2[q]:off2[q + 1]]
+            hn = h.reshape(nb, 1024 // nb).sum(axis=1) / h.sum()
+            k = li * p2.n_pixels + q
+            d = pis[offm[k]:offm[k + 1]] - hn
+            l1s.append(float(np.abs(d).sum()))
+            rms.append(float(np.sqrt(np.mean(d * d))))
+        table[str(nb)] = {"l1_mean": float(np.mean(l1s)), "l1_min": float(np.min(l1s)),
+                          "l1_max": float(np.max(l1s)), "rmse_mean": float(np.mean(rms))}
+    base = len(levels) * p2.n_pixels
+    rmse3, noise3 = [], []
+    for q in range(p3.n_pixels):
+        h = hist3[off3[q]:off3[q + 1]]
+        m = h.sum()
+        hn = h / m
+        d = pis[offm[base + q]:offm[base + q + 1]] - hn
+        rmse3.append(float(np.sqrt(np.mean(d * d))))
+        noise3.append(float(np.sqrt(np.mean(hn * (1.0 - hn) / m))))
+    rmse3, noise3 = np.array(rmse3), np.array(noise3)
+
+    # Discretisation variants of the model against the same Monte Carlo
+    # histograms (after the timed region; factored float64 solves).
+    variants = {}
+    vflags = {"shift_nearest": dtm.DTM_FLAG_SHIFT_NEAREST, "shift_interp": dtm.DTM_FLAG_SHIFT_INTERP,
+              "lambda_bin_mean": dtm.DTM_FLAG_LAMBDA_BIN_MEAN, "bin_integral": dtm.DTM_FLAG_BIN_INTEGRAL,
+              "paper": 0}
+    for name, fl in vflags.items():
+        o = dtm.opts(tol=1e-12)
+        o.flags |= fl | dtm.DTM_FLAG_NO_DENSE
+        pv = dtm.Plan(model, "f64", o)
+        wv = torch.empty(pv.workspace_bytes, dtype=torch.uint8, device="cuda")
+        pv.bind(wv)
+        piv = torch.empty(pv.pi_elems, dtype=torch.float64, device="cuda")
+        infv = torch.zeros(pv.n_pixels * 40, dtype=torch.uint8, device="cuda")
+        pv.solve_factored(piv, infv)
+        torch.cuda.synchronize()
+        pvs = piv.cpu().numpy()
+        ov_ = pv.pi_offsets
+        l1n = {}
+        for li, nb in enumerate(levels):
+            l1s = []
+            for q in range(p2.n_pixels):
+                h = hist2[off2[q]:off2[q + 1]]
+                hn = h.reshape(nb, 1024 // nb).sum(axis=1) / h.sum()
+                k = li * p2.n_pixels + q
+                l1s.append(float(np.abs(pvs[ov_[k]:ov_[k + 1]] - hn).sum()))
+            l1n[str(nb)] = float(np.mean(l1s))
+        rm = []
+        for q in range(p3.n_pixels):
+            h = hist3[off3[q]:off3[q + 1]]
+            d = pvs[ov_[base + q]:ov_[base + q + 1]] - h / h.sum()
+            rm.append(float(np.sqrt(np.mean(d * d))))
+        variants[name] = {"grid_4x4_l1_mean_by_bins": l1n, "grid_11x11_n256_rmse_mean": float(np.mean(rm)),
+                          "all_converged": bool(np.all(dtm.infos_to_numpy(infv)["status"] == 0))}
+        pv.close()
+        del wv
+
+    valu = profile_record("valu-record", "k_mc", "mc_sweep_e2", MC_SOURCES)
+    out = {
+        "metric": "Monte Carlo laser periods/s (model-validation sweeps, 2.31e8 periods per step)",
+        "value": periods / (ms_step * 1e-3),
+        "unit": "laser periods/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Section 3.5 validation: S,B in {0.1,3,6,9} x 100 runs x 50,000 periods "
+                               "at 2^10 bins vs model at 2^5..2^10; S,B in {0.1,1..10} x 25 runs x 50,000 "
+                               "periods at 2^8 bins; t_r 100 ns, t_d 75 ns, pulse 30 ns sigma 0.5 ns; "
+                               "Philox4x32-10 streams; float64 model solves in the step",
+                   "periods_per_step": periods},
+        "roofline": {
+            "bound": "alu", "unit": "G VALU wave-instructions/s", "peak": VALU_PEAK_G,
+            "achieved": (valu / (k2 * 1e-3) / 1e9) if valu else None,
+            "frac": (valu / (k2 * 1e-3) / 1e9 / VALU_PEAK_G) if valu else None,
+            "traffic": None, "kernel": "k_mc (S,B in {0.1,3,6,9} launch)",
+            "valu_insts_per_launch": valu,
+        },
+        "k_mc_ms": {"grid_4x4_n1024": k2, "grid_11x11_n256": k3},
+        "model_vs_mc_grid_4x4": table,
+        "model_vs_mc_grid_11x11_n256": {"rmse_mean": float(rmse3.mean()), "rmse_max": float(rmse3.max()),
+                                        "mc_noise_rmse_mean": float(noise3.mean()),
+                                        "rmse_over_noise_max": float((rmse3 / noise3).max())},
+        "model_variants_vs_mc": variants,
+        "overflow_pixels": int(o2.sum().item() + o3.sum().item()),
+        "model_all_converged": bool(np.all(info["status"] == 0)),
+    }
+    for pl in plans:
+        pl.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = mc_cpu_baseline(e2)
+    return out
+
+
 def _oracle_one(rec):
     import numpy as np
 
@@ -230,7 +460,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--workload", default="batched_uniform",
-                    choices=["batched_uniform", "batched_uneven", "warm_start"])
+                    choices=["batched_uniform", "batched_uneven", "warm_start", "mc_sweep"])
     ap.add_argument("--epochs", type=int, default=150, help="warm_start: training epochs")
     ap.add_argument("--pixels", type=int, default=0, help="0 = the workload's own count")
     ap.add_argument("--graph", action="store_true", help="replay the solve as a captured HIP graph")
@@ -259,8 +489,8 @@ def main():
 
     dtm.lib()
     torch.cuda.set_device(0)
-    if args.workload == "warm_start":
-        out = warm_start_workload(args)
+    if args.workload in ("warm_start", "mc_sweep"):
+        out = warm_start_workload(args) if args.workload == "warm_start" else mc_sweep_workload(args)
         print(json.dumps(out), flush=True)
         return
     uneven = args.workload == "batched_uneven"

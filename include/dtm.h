@@ -91,6 +91,29 @@ typedef struct dtm_scene {
 #define DTM_FLAG_NO_DENSE       0x2 /* plan without the dense matrix pool: only the
                                        factored solver and the spectral analysis */
 
+/* Discretisation variants (default: the paper's model, Section 3.4 with
+ * Theorem 2's shift and lambda sampled at the bin centres).  With
+ * q = x_d / Delta (x_d = t_d mod t_r, bins (j Delta, (j+1) Delta]):
+ *   SHIFT_NEAREST  the exact "shift then quantize" bin that Theorem 2
+ *                  approximates: row i is base row i + ceil(q - 1/2)
+ *                  (q - 1/2 within a relative 1e-9 of an integer is taken
+ *                  as that integer; a centre on an edge is in the lower bin);
+ *   SHIFT_INTERP   reactivation between two centres: q = m + f, row i is
+ *                  (1 - f) base row i + m plus f base row i + m + 1
+ *                  (factored solver and spectral analysis only: a plan with
+ *                  a dense pool returns DTM_ENOTSUP);
+ *   LAMBDA_BIN_MEAN  lambda_j = (F(e_{j+1}) - F(e_j)) / Delta, the flux
+ *                  averaged over the bin, in place of lambda(s_j);
+ *   BIN_INTEGRAL   lambda_j e^{-F(s_j)} replaced by its bin average
+ *                  (e^{-F(e_j)} - e^{-F(e_{j+1})}) / Delta: the exact
+ *                  first-arrival mass of the bin.
+ * SHIFT_NEAREST and SHIFT_INTERP exclude each other, as do LAMBDA_BIN_MEAN
+ * and BIN_INTEGRAL (else DTM_EINVAL). */
+#define DTM_FLAG_SHIFT_NEAREST   0x4
+#define DTM_FLAG_SHIFT_INTERP    0x8
+#define DTM_FLAG_LAMBDA_BIN_MEAN 0x10
+#define DTM_FLAG_BIN_INTEGRAL    0x20
+
 typedef struct dtm_solve_opts {
   double tol_l1;       /* target L1 distance (rule 1) or change threshold (rule 0) */
   double safety;       /* rule 1: fraction of tol_l1 the bound must reach (0,1]   */
@@ -271,13 +294,14 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
  *
  * Random numbers: Philox4x32-10 with key = seed and counter = (draw block,
  * period, run, pixel index); the sampling steps (Knuth Poisson draws,
- * Box-Muller pulse times, time-ordered visit with the rearm time carried from
+ * Box-Muller pairs of pulse times, time-ordered visit with the rearm time carried from
  * period to period) are fixed, so another implementation of the same steps
  * reproduces the counts exactly.
  *
  * hist_packed_dev: uint32 counts packed like pi (runs summed), overwritten.
  * overflow_dev: one uint32 per pixel (input order), zeroed by the caller; set
- * when a period held more than 64 photons (then only 64 were used).
+ * when the 64 periods a wave draws at once held more photons than its pool
+ * (their mean plus ten standard deviations; the excess is dropped).
  * lanes_per_run: 0 = automatic, else a power of two <= 64 (lanes that share
  * one run; the counts do not depend on it).  Requires S + B <= 24,
  * n_b <= 16384, 1 <= runs_per_pixel <= 65535, 0 <= burn_cycles < cycles <

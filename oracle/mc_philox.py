@@ -14,8 +14,10 @@ same steps (the GPU simulator) can be compared count for count:
   streams of their own, so a simulator may generate them in any order;
 * per period: Knuth's product-of-uniforms Poisson draw for the pulse count
   (threshold exp(-S)), then for the background count (threshold exp(-B));
-  each pulse photon: t = tau + sigma sqrt(-2 ln u1) cos(2 pi u2), kept when
-  0 <= t < t_r; each background photon: t = t_r u;
+  pulse photons come in Box-Muller pairs: two uniforms u1, u2 give
+  r = sqrt(-2 ln u1), theta = 2 pi u2 and the times tau + sigma r cos(theta)
+  and (when the count is not yet reached) tau + sigma r sin(theta), each kept
+  when 0 <= t < t_r; each background photon: t = t_r u;
 * the detector state is the rearm time a, measured from the start of the
   current period (0 at the start of a run: armed).  The period's photons are
   sorted by time and visited in order; a photon at t >= a is registered and
@@ -84,12 +86,15 @@ def simulate_run(scene_fields, cycles, burn, seed, run, pixel, hist):
         ns = poisson(st, e_s)
         nb = poisson(st, e_b)
         ts = []
-        for _ in range(ns):
+        for i in range(0, ns, 2):
             u1 = st.uniform()
             u2 = st.uniform()
-            t = tau + sigma * (math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2))
-            if 0.0 <= t < t_r:
-                ts.append(t)
+            r = math.sqrt(-2.0 * math.log(u1))
+            theta = 2.0 * math.pi * u2
+            pair = (tau + sigma * (r * math.cos(theta)), tau + sigma * (r * math.sin(theta)))
+            for t in pair[:min(2, ns - i)]:
+                if 0.0 <= t < t_r:
+                    ts.append(t)
         for _ in range(nb):
             ts.append(t_r * st.uniform())
         ts.sort()

@@ -176,9 +176,20 @@ __device__ double pixel_tables(const PixelMeta& m, T* g, T* lam_out, double* F_o
   for (int j = j0; j < j1; ++j) {
     const double lo = j * delta;
     const double F = acc + flux_integral(m, lo, lo + 0.5 * delta);
-    acc += flux_integral(m, lo, (j + 1) * delta);
-    const double lj = flux_at(m, lo + 0.5 * delta);
-    g[j] = static_cast<T>(lj * exp(-F));
+    const double dF = flux_integral(m, lo, (j + 1) * delta);
+    double lj, gj;
+    if (m.lam_mode == 0) {  // lambda at the bin centre (Section 3.4)
+      lj = flux_at(m, lo + 0.5 * delta);
+      gj = lj * exp(-F);
+    } else if (m.lam_mode == 1) {  // lambda averaged over the bin
+      lj = dF / delta;
+      gj = lj * exp(-F);
+    } else {  // lambda e^{-F} averaged over the bin: (e^{-F(lo)} - e^{-F(hi)}) / Delta
+      gj = exp(-acc) * -expm1(-dF) / delta;
+      lj = gj * exp(F);
+    }
+    acc += dF;
+    g[j] = static_cast<T>(gj);
     if (lam_out) lam_out[j] = static_cast<T>(lj);
     if (F_out) F_out[j] = F;
   }

@@ -28,17 +28,28 @@ __device__ inline void chunk_of(int n, int& j0, int& j1) {
   j1 = min(j0 + ch, n);
 }
 
+// The vector the base rows see: x_{k - l}, or with an interpolated shift
+// (row i = (1 - f) base row i + l + f base row i + l + 1)
+// (1 - f) x_{k - l} + f x_{k - l - 1}; indices mod n.
+template <typename X>
+__device__ inline double shifted_x(X x, int n, int l, double f, int k) {
+  int i = k - l;
+  if (i < 0) i += n;
+  if (f == 0.0) return x(i);
+  const int i2 = i == 0 ? n - 1 : i - 1;
+  return (1.0 - f) * x(i) + f * x(i2);
+}
+
 // y = x P~ (unnormalised).  u is scratch of n doubles; y may alias u but not
 // x.  Ends with block barriers (inside the scan), so callers may reduce.
-__device__ void apply(int n, int l, const double* x, const double* g, const double* invs, double c,
-                      double* u, double* y, double* red) {
+__device__ void apply(int n, int l, double f, const double* x, const double* g, const double* invs,
+                      double c, double* u, double* y, double* red) {
   int j0, j1;
   chunk_of(n, j0, j1);
   double cs = 0.0;
+  const auto xv = [x](int i) { return x[i]; };
   for (int k = j0; k < j1; ++k) {
-    int i = k - l;
-    if (i < 0) i += n;
-    const double v = x[i] * invs[k];
+    const double v = shifted_x(xv, n, l, f, k) * invs[k];
     u[k] = v;
     cs += v;
   }
@@ -107,7 +118,7 @@ __device__ StopState power(const PixelMeta& m, const Vecs& V, double c, const TI
   }
   __syncthreads();
   for (;;) {
-    apply(n, m.l, V.x, V.g, V.invs, c, V.u, V.u, red);
+    apply(n, m.l, m.frac, V.x, V.g, V.invs, c, V.u, V.u, red);
     double sy = 0.0, rs = 0.0;
     for (int j = j0; j < j1; ++j) {
       sy += V.u[j];
@@ -165,7 +176,7 @@ __device__ void deflated(const PixelMeta& m, const Vecs& V, double c, const doub
   double s = 0.0;
   for (int j = j0; j < j1; ++j) s += v[j];
   s = block_sum<BT>(s, red);
-  apply(m.n, m.l, v, V.g, V.invs, c, V.u, out, red);
+  apply(m.n, m.l, m.frac, v, V.g, V.invs, c, V.u, out, red);
   for (int j = j0; j < j1; ++j) out[j] -= s * V.x[j];
   __syncthreads();
 }
@@ -290,17 +301,12 @@ __global__ __launch_bounds__(BT) void k_mixing(const PixelMeta* __restrict__ met
   for (int t = 1; t <= max_steps; ++t) {
     double worst = 0.0;
     for (int s = threadIdx.x; s < n; s += BT) {
+      const auto xs = [X, n, s](int i) { return X[static_cast<int64_t>(i) * n + s]; };
       double tot = 0.0;
-      for (int k = 0; k < n; ++k) {
-        int i = k - m.l;
-        if (i < 0) i += n;
-        tot += X[static_cast<int64_t>(i) * n + s] * V.invs[k];
-      }
+      for (int k = 0; k < n; ++k) tot += shifted_x(xs, n, m.l, m.frac, k) * V.invs[k];
       double U = 0.0, tv = 0.0;
       for (int j = 0; j < n; ++j) {
-        int i = j - m.l;
-        if (i < 0) i += n;
-        U += X[static_cast<int64_t>(i) * n + s] * V.invs[j];
+        U += shifted_x(xs, n, m.l, m.frac, j) * V.invs[j];
         const double y = V.g[j] * (c * tot + (1.0 - c) * U);
         Y[static_cast<int64_t>(j) * n + s] = y;
         tv += fabs(y - V.x[j]);

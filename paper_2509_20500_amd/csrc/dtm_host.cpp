@@ -46,6 +46,40 @@ int shift_bins(const dtm_scene& s, int32_t* l) {
   return DTM_OK;
 }
 
+// Shift of a pixel under the discretisation flags.  SHIFT_NEAREST: the bin
+// of the shifted centre, (i + 1/2 + q) Delta in (j Delta, (j + 1) Delta],
+// i.e. row i + ceil(q - 1/2); SHIFT_INTERP: q = l + frac with 0 <= frac < 1.
+// Both snap to an integer within 1e-9 (relative), like Theorem 2's shift.
+void model_shift(const dtm_scene& s, int32_t model, int32_t* l, double* frac) {
+  *frac = 0.0;
+  if (!(model & (DTM_FLAG_SHIFT_NEAREST | DTM_FLAG_SHIFT_INTERP))) {
+    shift_bins(s, l);
+    return;
+  }
+  const double x_d = std::fmod(s.dead_time_ns, s.period_ns);
+  const double q = x_d * static_cast<double>(s.n_bins) / s.period_ns;
+  const double p = (model & DTM_FLAG_SHIFT_NEAREST) ? q - 0.5 : q;
+  const double r = std::nearbyint(p);
+  double lq;
+  if (std::fabs(p - r) <= 1e-9 * std::max(1.0, std::fabs(p))) {
+    lq = r;
+  } else if (model & DTM_FLAG_SHIFT_NEAREST) {
+    lq = std::ceil(p);
+  } else {
+    lq = std::floor(p);
+    *frac = p - lq;
+  }
+  int64_t li = static_cast<int64_t>(lq) % s.n_bins;
+  if (li < 0) li += s.n_bins;
+  *l = static_cast<int32_t>(li);
+}
+
+int32_t model_lam_mode(int32_t model) {
+  if (model & DTM_FLAG_LAMBDA_BIN_MEAN) return 1;
+  if (model & DTM_FLAG_BIN_INTEGRAL) return 2;
+  return 0;
+}
+
 int fill_opts(const dtm_solve_opts* opt, KOpts* k, int32_t* check_every) {
   dtm_solve_opts o;
   if (opt) {
@@ -62,13 +96,19 @@ int fill_opts(const dtm_solve_opts* opt, KOpts* k, int32_t* check_every) {
   if (!(o.safety > 0.0 && o.safety <= 1.0)) return DTM_EINVAL;
   if (o.max_iter < 1 || o.check_every < 1) return DTM_EINVAL;
   if (o.stop_rule != DTM_STOP_CHANGE && o.stop_rule != DTM_STOP_BOUND) return DTM_EINVAL;
-  if (o.flags & ~(DTM_FLAG_NO_FINAL_CHECK | DTM_FLAG_NO_DENSE)) return DTM_EINVAL;
+  constexpr int32_t kModel =
+      DTM_FLAG_SHIFT_NEAREST | DTM_FLAG_SHIFT_INTERP | DTM_FLAG_LAMBDA_BIN_MEAN | DTM_FLAG_BIN_INTEGRAL;
+  if (o.flags & ~(DTM_FLAG_NO_FINAL_CHECK | DTM_FLAG_NO_DENSE | kModel)) return DTM_EINVAL;
+  if ((o.flags & DTM_FLAG_SHIFT_NEAREST) && (o.flags & DTM_FLAG_SHIFT_INTERP)) return DTM_EINVAL;
+  if ((o.flags & DTM_FLAG_LAMBDA_BIN_MEAN) && (o.flags & DTM_FLAG_BIN_INTEGRAL)) return DTM_EINVAL;
   k->tol = o.tol_l1;
   k->safety = o.safety;
   k->max_iter = o.max_iter;
   k->stop_rule = o.stop_rule;
   k->final_check = (o.flags & DTM_FLAG_NO_FINAL_CHECK) ? 0 : 1;
   k->pad = (o.flags & DTM_FLAG_NO_DENSE) ? 1 : 0;  // no dense pool
+  k->model = o.flags & kModel;
+  k->pad2 = 0;
   if (check_every) *check_every = o.check_every;
   return DTM_OK;
 }
@@ -124,6 +164,8 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   int32_t ce = 4;
   int st = fill_opts(opt, &ko, &ce);
   if (st != DTM_OK) return st;
+  // the dense kernels take whole rows of the shifted matrix
+  if ((ko.model & DTM_FLAG_SHIFT_INTERP) && !ko.pad) return DTM_ENOTSUP;
   for (int32_t p = 0; p < n_pixels; ++p) {
     st = validate_scene(scenes_host[p], dt);
     if (st != DTM_OK) return st;
@@ -199,7 +241,9 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
     m.S = s.signal_flux;
     m.B = s.background_flux;
     m.n = s.n_bins;
-    shift_bins(s, &m.l);
+    model_shift(s, ko.model, &m.l, &m.frac);
+    m.lam_mode = model_lam_mode(ko.model);
+    m.pad2 = 0;
     m.ld = padded_ld(s.n_bins, dt);
     m.index = p;
     m.t_d = s.dead_time_ns;

@@ -38,8 +38,11 @@ struct PixelMeta {
   int32_t big;      // position in the banded-pixel list, or -1
   double t_d;       // dead time (Monte Carlo simulator)
   double e_s, e_b;  // exp(-S), exp(-B), from the host's libm (Monte Carlo simulator)
+  double frac;      // interpolated shift: weight f of base row i + l + 1 (0 otherwise)
+  int32_t lam_mode; // 0: lambda at the bin centre, 1: bin-mean lambda, 2: bin integral
+  int32_t pad2;
 };
-static_assert(sizeof(PixelMeta) == 128, "PixelMeta layout");
+static_assert(sizeof(PixelMeta) == 144, "PixelMeta layout");
 
 // One work item of the banded sweep: a band of rows times a block of columns
 // of one pixel.
@@ -57,7 +60,9 @@ struct KOpts {
   int32_t max_iter;
   int32_t stop_rule;
   int32_t final_check;
-  int32_t pad;  // host only: 1 = the plan has no dense matrix pool
+  int32_t pad;    // host only: 1 = the plan has no dense matrix pool
+  int32_t model;  // host only: DTM_FLAG_SHIFT_* / LAMBDA_BIN_MEAN / BIN_INTEGRAL
+  int32_t pad2;
 };
 
 // Convergence bookkeeping of one pixel, shared by both solvers.
@@ -87,6 +92,8 @@ struct SolveState {
 // Shared host logic (dtm_host.cpp).
 int validate_scene(const dtm_scene& s, dtm_dtype dt);
 int shift_bins(const dtm_scene& s, int32_t* l);
+void model_shift(const dtm_scene& s, int32_t model, int32_t* l, double* frac);
+int32_t model_lam_mode(int32_t model);
 int fill_opts(const dtm_solve_opts* opt, KOpts* k, int32_t* check_every);
 inline int32_t padded_ld(int32_t n, dtm_dtype dt) {
   const int32_t vec = dt == DTM_F32 ? 4 : 2;  // 16 bytes

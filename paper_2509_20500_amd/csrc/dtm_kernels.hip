@@ -873,6 +873,9 @@ PixelMeta single_meta(const dtm_scene& s, dtm_dtype dt) {
   m.B = s.background_flux;
   m.n = s.n_bins;
   shift_bins(s, &m.l);
+  m.frac = 0.0;
+  m.lam_mode = 0;
+  m.pad2 = 0;
   m.ld = padded_ld(s.n_bins, dt);
   m.index = 0;
   m.t_d = s.dead_time_ns;
@@ -1282,6 +1285,7 @@ int dtm_stationary_pdf(const void* P_dev, int32_t n, int64_t ld, dtm_dtype dt,
   int32_t ce = 4;
   int rc = fill_opts(opt, &ko, &ce);
   if (rc) return rc;
+  if (ko.model) return DTM_EINVAL;  // discretisation flags describe a plan's matrices, not a given one
   const SingleLayout L = single_layout(n, dt);
   if (workspace_bytes < L.total) return DTM_ENOSPACE;
   const size_t es = dtype_size(dt);

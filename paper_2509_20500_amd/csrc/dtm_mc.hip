@@ -9,20 +9,22 @@
 // Each block yields four 32-bit words, consumed in order; u = (w + 1/2) / 2^32.
 // Per period: Knuth's product-of-uniforms Poisson draws (pulse, then
 // background; thresholds exp(-S), exp(-B) computed on the host), pulse
-// photons tau + sigma sqrt(-2 ln u1) cos(2 pi u2) kept inside [0, t_r),
+// photons in Box-Muller pairs tau + sigma sqrt(-2 ln u1) (cos, sin)(2 pi u2)
+// (the second only while the count is not reached) kept inside [0, t_r),
 // background photons t_r u.  The detector state is the rearm time a relative
 // to the period start (0 = armed): photons are visited in time order, one at
 // t >= a is registered and sets a = t + t_d; the period ends with
 // a = max(a - t_r, 0).
 //
 // A run is sequential only through a, so a group of L lanes simulates one
-// run: each lane draws and sorts one period of a chunk of L periods (its own
+// run: each lane draws one period of a chunk of L periods (its own
 // stream), then the group hands a from lane to lane through the chunk.  L = 1
 // (a lane per run) has the highest throughput when runs fill the chip; L = 64
 // (a wave per run) the lowest latency when there are few runs (a run's time
 // is then set by its hand-over chain, not by its drawing).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -36,8 +38,8 @@
 namespace dtm {
 namespace mc {
 
-constexpr int BT = 64;    // one wave per block
-constexpr int MAXP = 64;  // photons of one period kept (S + B <= 24: P(more) < 1e-10)
+constexpr int BT = 64;        // one wave per block
+constexpr int kCoopMin = 16;  // lanes per run from which the hand-over search is shared
 
 __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
   const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
@@ -87,28 +89,35 @@ __device__ inline int poisson(Stream& st, double threshold) {
   return k;
 }
 
-// Value of lane `src` (wave-uniform) on every lane.
-__device__ inline double broadcast_wave(double v, int src) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(u)), src));
-  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(u >> 32)), src));
-  return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
-}
-
 __global__ __launch_bounds__(BT) void k_zero(uint32_t* __restrict__ p, size_t n) {
   const size_t i = static_cast<size_t>(blockIdx.x) * BT + threadIdx.x;
   if (i < n) p[i] = 0u;
 }
 
+// Exclusive prefix sum over the wave.
+__device__ inline int wave_exclusive_sum(int v, int lane) {
+  int s = v;
+#pragma unroll
+  for (int d = 1; d < BT; d <<= 1) {
+    const int u = __shfl_up(s, d, BT);
+    if (lane >= d) s += u;
+  }
+  return s - v;
+}
+
 // Grid (pixel, run block); block = one wave = 64 / L runs of one pixel.
-// LDS: the period photon lists, column per lane ([MAXP][64] doubles), then
-// the pixel's histogram (n uint32), added atomically to HBM at the end.
+// LDS: a pool of `cap` photon times shared by the wave's 64 periods of a
+// chunk (each lane owns a contiguous segment, placed by a prefix sum of its
+// Poisson counts, sorted), for each photon the last registration of the
+// chain that starts with it (uint16, same offsets), then the pixel's
+// histogram (n uint32), added atomically to HBM at the end.
 __global__ __launch_bounds__(BT) void k_mc(const PixelMeta* __restrict__ metas, int runs, int64_t cycles,
-                                           int64_t burn, uint64_t seed, int L,
+                                           int64_t burn, uint64_t seed, int L, int cap,
                                            uint32_t* __restrict__ hist, uint32_t* __restrict__ overflow) {
   extern __shared__ double lds_d[];
-  double* ts = lds_d;                                         // [MAXP][BT]
-  uint32_t* h = reinterpret_cast<uint32_t*>(lds_d + MAXP * BT);
+  double* pool = lds_d;
+  uint16_t* jend = reinterpret_cast<uint16_t*>(lds_d + cap);
+  uint32_t* h = reinterpret_cast<uint32_t*>(lds_d + cap) + (cap + 1) / 2;
   const PixelMeta m = metas[blockIdx.x];
   const int n = m.n;
   const int lane = threadIdx.x;
@@ -124,81 +133,133 @@ __global__ __launch_bounds__(BT) void k_mc(const PixelMeta* __restrict__ metas, 
   for (int64_t c0 = 0; c0 < cycles; c0 += L) {
     const int64_t c = c0 + k_in;
     const bool mine = run_ok && c < cycles;
+    Stream st;
+    st.k0 = static_cast<uint32_t>(seed);
+    st.k1 = static_cast<uint32_t>(seed >> 32);
+    st.cycle = static_cast<uint32_t>(c);
+    st.run = static_cast<uint32_t>(run);
+    st.pixel = static_cast<uint32_t>(m.index);
+    st.block = 0u;
+    st.pos = 4;
+    int ns = 0, nb = 0;
+    if (mine) {
+      ns = poisson(st, m.e_s);
+      nb = poisson(st, m.e_b);
+    }
+    const int off = wave_exclusive_sum(ns + nb, lane);
+    const int room = min(ns + nb, max(cap - off, 0));
+    double* seg = pool + off;
     int cnt = 0;
     if (mine) {
-      Stream st;
-      st.k0 = static_cast<uint32_t>(seed);
-      st.k1 = static_cast<uint32_t>(seed >> 32);
-      st.cycle = static_cast<uint32_t>(c);
-      st.run = static_cast<uint32_t>(run);
-      st.pixel = static_cast<uint32_t>(m.index);
-      st.block = 0u;
-      st.pos = 4;
-      const int ns = poisson(st, m.e_s);
-      const int nb = poisson(st, m.e_b);
-      for (int i = 0; i < ns; ++i) {
+      for (int i = 0; i < ns; i += 2) {  // Box-Muller pairs
         const double u1 = st.uniform();
         const double u2 = st.uniform();
-        const double t = m.tau + m.sigma * (sqrt(-2.0 * log(u1)) * cos(two_pi * u2));
-        if (t >= 0.0 && t < m.t_r) {
-          if (cnt < MAXP) ts[cnt++ * BT + lane] = t;
+        const double r = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincos(two_pi * u2, &sn, &cs);
+        const double t1 = m.tau + m.sigma * (r * cs);
+        if (t1 >= 0.0 && t1 < m.t_r) {
+          if (cnt < room) seg[cnt++] = t1;
+          else over = true;
+        }
+        const double t2 = m.tau + m.sigma * (r * sn);
+        if (i + 1 < ns && t2 >= 0.0 && t2 < m.t_r) {
+          if (cnt < room) seg[cnt++] = t2;
           else over = true;
         }
       }
       for (int i = 0; i < nb; ++i) {
         const double t = m.t_r * st.uniform();
-        if (cnt < MAXP) ts[cnt++ * BT + lane] = t;
+        if (cnt < room) seg[cnt++] = t;
         else over = true;
       }
-      for (int x = 1; x < cnt; ++x) {  // insertion sort of this lane's column
-        const double v = ts[x * BT + lane];
+      for (int x = 1; x < cnt; ++x) {  // insertion sort of this lane's segment
+        const double v = seg[x];
         int y = x - 1;
-        while (y >= 0 && ts[y * BT + lane] > v) {
-          ts[(y + 1) * BT + lane] = ts[y * BT + lane];
+        while (y >= 0 && seg[y] > v) {
+          seg[y + 1] = seg[y];
           --y;
         }
-        ts[(y + 1) * BT + lane] = v;
+        seg[y + 1] = v;
       }
-    }
-    // Entering at or before the first photon, the period's registrations do
-    // not depend on a: its exit rearm time A0 is found here, in parallel.
-    double t0 = 0.0, A0 = 0.0;
-    if (mine && cnt > 0) {
-      t0 = ts[lane];
-      double aa = 0.0;
-      for (int x = 0; x < cnt; ++x) {
-        const double t = ts[x * BT + lane];
-        if (t >= aa) aa = t + m.t_d;
-      }
-      A0 = fmax(aa - m.t_r, 0.0);
-    }
-    // Hand a through the chunk: the lane holding period c0 + k notes its
-    // entry rearm time and forms its exit one, which every lane of the group
-    // then takes.
-    double a_in = 0.0;
-    for (int k = 0; k < L; ++k) {
-      if (mine && k_in == k) {
-        a_in = a;
-        if (cnt == 0) {
-          a = fmax(a - m.t_r, 0.0);
-        } else if (a <= t0) {
-          a = A0;
-        } else {
-          for (int x = 0; x < cnt; ++x) {
-            const double t = ts[x * BT + lane];
-            if (t >= a) a = t + m.t_d;
-          }
-          a = fmax(a - m.t_r, 0.0);
+      if (L >= kCoopMin) {
+        // A registration at photon i is followed by one at the first photon
+        // q > i with t_q >= t_i + t_d; q only moves left as i does.  jend[i]:
+        // the last registration of the period once photon i is registered.
+        int q = cnt;
+        for (int i = cnt - 1; i >= 0; --i) {
+          const double thr = seg[i] + m.t_d;
+          while (q - 1 > i && seg[q - 1] >= thr) --q;
+          jend[off + i] = static_cast<uint16_t>(q == cnt ? i : jend[off + q]);
         }
       }
-      if (L == BT) a = broadcast_wave(a, k);
-      else if (L > 1) a = __shfl(a, base_lane + k, BT);
+    }
+    double a_in = 0.0;
+    if (L < kCoopMin) {
+      // Small groups: the lane holding period c0 + k walks its own sorted
+      // segment (entering at or before its first photon, the exit does not
+      // depend on a and was found beforehand) and passes a on.
+      double A0 = 0.0;
+      if (mine && cnt > 0) {
+        double aa = 0.0;
+        for (int x = 0; x < cnt; ++x) {
+          const double t = seg[x];
+          if (t >= aa) aa = t + m.t_d;
+        }
+        A0 = fmax(aa - m.t_r, 0.0);
+      }
+      for (int k = 0; k < L; ++k) {
+        if (mine && k_in == k) {
+          a_in = a;
+          if (cnt > 0 && a <= seg[0]) {
+            a = A0;
+          } else {
+            for (int x = 0; x < cnt; ++x) {
+              const double t = seg[x];
+              if (t >= a) a = t + m.t_d;
+            }
+            a = fmax(a - m.t_r, 0.0);
+          }
+        }
+        if (L > 1) a = __shfl(a, base_lane + k, BT);
+      }
+    } else {
+      // Large groups: for period c0 + k the group's lanes look in parallel for
+      // the first photon at or after a (the segment is sorted); the period's
+      // exit rearm time follows from that photon's jend.
+      const int cnt_or_none = mine ? cnt : -1;
+      const uint64_t gmask = L == BT ? ~0ull : ((1ull << L) - 1ull);
+      for (int k = 0; k < L; ++k) {
+        const int src = base_lane + k;
+        const int off_k = __shfl(off, src, BT);
+        const int cnt_k = __shfl(cnt_or_none, src, BT);
+        if (k_in == k) a_in = a;
+        int first = cnt_k;
+        bool searching = cnt_k > 0;
+        for (int r0 = 0; __any(searching); r0 += L) {
+          const int idx = r0 + k_in;
+          const bool hit = searching && idx < cnt_k && pool[off_k + idx] >= a;
+          const uint64_t g = (static_cast<uint64_t>(__ballot(hit)) >> base_lane) & gmask;
+          if (searching) {
+            if (g) {
+              first = r0 + __ffsll(static_cast<unsigned long long>(g)) - 1;
+              searching = false;
+            } else if (r0 + L >= cnt_k) {
+              searching = false;
+            }
+          }
+        }
+        if (cnt_k >= 0) {
+          const double exit_from = first < cnt_k ? pool[off_k + jend[off_k + first]] + m.t_d : a;
+          a = fmax(exit_from - m.t_r, 0.0);
+        }
+      }
     }
     // Registrations of every period of the chunk, in parallel.
     if (mine && c >= burn) {
       double aa = a_in;
       for (int x = 0; x < cnt; ++x) {
-        const double t = ts[x * BT + lane];
+        const double t = seg[x];
         if (t >= aa) {
           aa = t + m.t_d;
           int j = static_cast<int>(ceil(t / delta)) - 1;
@@ -246,7 +307,17 @@ extern "C" int dtm_mc_histograms(const dtm_plan* plan, int32_t runs_per_pixel, i
   hipStream_t st = static_cast<hipStream_t>(stream);
   const char* w = static_cast<const char*>(plan->ws);
   const PixelMeta* metas = reinterpret_cast<const PixelMeta*>(w + plan->off_meta);
-  const size_t lds = sizeof(double) * mc::MAXP * mc::BT + sizeof(uint32_t) * static_cast<size_t>(plan->max_n);
+  // Photon pool of a wave: the 64 periods of a chunk draw Poisson(S' + B)
+  // photons in all, S' + B <= S + B; the pool holds that mean plus ten
+  // standard deviations (a wave that draws more drops the excess and flags
+  // the pixel).
+  double lam = 0.0;
+  for (const PixelMeta& m : plan->meta) lam = std::max(lam, m.S + m.B);
+  const double mean = mc::BT * lam;
+  const int cap = static_cast<int>(std::ceil(mean + 10.0 * std::sqrt(mean) + 64.0));
+  const size_t lds = sizeof(double) * static_cast<size_t>(cap) + sizeof(uint32_t) * static_cast<size_t>((cap + 1) / 2) +
+                    sizeof(uint32_t) * static_cast<size_t>(plan->max_n);
+  if (lds > 160 * 1024) return DTM_ENOTSUP;
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(mc::k_mc), hipFuncAttributeMaxDynamicSharedMemorySize,
                           static_cast<int>(lds)) != hipSuccess)
     return DTM_EHIP;
@@ -256,6 +327,6 @@ extern "C" int dtm_mc_histograms(const dtm_plan* plan, int32_t runs_per_pixel, i
   const int per_block = mc::BT / L;
   const unsigned run_blocks = static_cast<unsigned>((runs_per_pixel + per_block - 1) / per_block);
   hipLaunchKernelGGL(mc::k_mc, dim3(plan->n_pixels, run_blocks), dim3(mc::BT), lds, st, metas, runs_per_pixel,
-                     cycles, burn_cycles, seed, L, hist_packed_dev, overflow_dev);
+                     cycles, burn_cycles, seed, L, cap, hist_packed_dev, overflow_dev);
   return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP;
 }

@@ -33,6 +33,10 @@ DTM_STOP_CHANGE = 0
 DTM_STOP_BOUND = 1
 DTM_FLAG_NO_FINAL_CHECK = 0x1
 DTM_FLAG_NO_DENSE = 0x2
+DTM_FLAG_SHIFT_NEAREST = 0x4
+DTM_FLAG_SHIFT_INTERP = 0x8
+DTM_FLAG_LAMBDA_BIN_MEAN = 0x10
+DTM_FLAG_BIN_INTEGRAL = 0x20
 
 DTM_INFO_WARM_REJECTED = 0x1
 DTM_INFO_RESTARTED = 0x2
@@ -378,12 +382,20 @@ class Plan:
                                          _ptr(scratch), scratch.numel(), _stream(stream)),
               "dtm_spectral_batched")
 
-    def mc_histograms(self, runs, cycles, burn, seed, lanes_per_run=0, stream=None):
-        """Monte Carlo registration counts (packed like pi, uint32 as int32
-        tensor) and per-pixel overflow flags."""
+    def mc_histograms(self, runs, cycles, burn, seed, lanes_per_run=0, stream=None, hist=None, over=None):
+        """Monte Carlo registration counts (packed like pi, uint32 held in an
+        int32 tensor) and per-pixel overflow flags.  hist/over may be given
+        (int32 CUDA tensors of pi_elems and n_pixels elements); over is
+        cleared here."""
         import torch
-        hist = torch.zeros(self.pi_elems, dtype=torch.int32, device="cuda")
-        over = torch.zeros(self.n_pixels, dtype=torch.int32, device="cuda")
+        if hist is None:
+            hist = torch.empty(self.pi_elems, dtype=torch.int32, device="cuda")
+        if over is None:
+            over = torch.zeros(self.n_pixels, dtype=torch.int32, device="cuda")
+        else:
+            over.zero_()
+        if hist.numel() < self.pi_elems or over.numel() < self.n_pixels:
+            raise ValueError("mc_histograms: output tensors too small")
         check(lib().dtm_mc_histograms(self.handle, int(runs), int(cycles), int(burn), int(seed),
                                       int(lanes_per_run), _ptr(hist), _ptr(over), _stream(stream)),
               "dtm_mc_histograms")

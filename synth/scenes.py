@@ -138,6 +138,13 @@ def paper_grid(levels=(0.1, 3.0, 6.0, 9.0), dead_time=75.0, n_bins=256, sigma=0.
     return make_scenes(100.0, dead_time, center, sigma, s.ravel(), b.ravel(), n_bins)
 
 
+def paper_rmse_grid(n_bins=256, dead_time=75.0):
+    """The (S, B) grid over [0, 10] of the RMSE study: levels 0.1, 1, 2, ...,
+    10 (0.1 stands for the empty end, where S = B = 0 has no photons)."""
+    return paper_grid(levels=(0.1,) + tuple(float(v) for v in range(1, 11)), dead_time=dead_time,
+                      n_bins=n_bins)
+
+
 def random_small(n_scenes, seed, n_bins_choices=(2, 3, 5, 8, 17, 31, 64, 100, 129, 257)):
     """Varied small scenes for parity at sizes the oracle finishes quickly:
     ragged N, dead time below and above one period, wide flux range."""

@@ -106,7 +106,8 @@ def test_argument_errors_before_any_launch(d):
     bad = d.opts(tol=-1.0)
     st, _ = d.dtm_stationary_pdf(fake, 1000, 1000, "f64", bad, None, fake, fake * 4, ws, None)
     assert st == d.DTM_EINVAL
-    for o in (d.opts(max_iter=0), d.opts(safety=0.0), d.opts(stop_rule=7), d.opts(flags=0x10)):
+    for o in (d.opts(max_iter=0), d.opts(safety=0.0), d.opts(stop_rule=7), d.opts(flags=0x40),
+              d.opts(flags=d.DTM_FLAG_LAMBDA_BIN_MEAN), d.opts(flags=d.DTM_FLAG_SHIFT_INTERP)):
         st, _ = d.dtm_stationary_pdf(fake, 1000, 1000, "f64", o, None, fake, fake * 4, ws, None)
         assert st == d.DTM_EINVAL
 
