@@ -258,7 +258,9 @@ int dtm_solve_batched(const dtm_plan* plan, const void* x0_packed_dev, void* pi_
  * one float64 block scan per sweep (O(n) instead of O(n^2)).  Same stop
  * rule as dtm_solve_batched, every sweep in float64 (eps 1.1e-16), so tol can
  * go down to ~1e-12.  Uses only the plan's tables and a float64 scratch
- * region of its workspace; works with DTM_FLAG_NO_DENSE plans.  Launch only. */
+ * region of its workspace; works with DTM_FLAG_NO_DENSE plans.  With
+ * DTM_FLAG_SHIFT_INTERP (q = l + f), u_k = ((1 - f) x_{k-l} + f x_{k-l-1}) / S_k.
+ * Launch only. */
 int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, void* pi_packed_dev,
                                dtm_solve_info* infos_dev, dtm_stream_t stream);
 
