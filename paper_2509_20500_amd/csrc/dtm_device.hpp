@@ -264,6 +264,7 @@ __device__ inline void stop_init(StopState& s, int warm, int flags) {
   s.c1 = s.c2 = s.c3 = 0.0;
   s.rho = 0.999;
   s.gain = 999.0;
+  s.contr = 0.999;
   s.resid = 0.0;
   s.dd_prev = 0.0;
   s.iter = 0;
@@ -302,13 +303,17 @@ __device__ inline bool stop_update(StopState& s, const KOpts& o, double change, 
   // estimate made above 64 units of round-off.
   if (s.iter <= 2 || change >= 64.0 * eps) {
     s.rho = estimate_rho(s.c1, s.c2, s.c3, s.iter);
-    double g = s.rho / (1.0 - s.rho);
+    double g = s.rho / (1.0 - s.rho), k = s.rho;
     if (s.iter >= 2 && s.dd_prev > 0.0 && dd > 0.0) {
       const double mu = ddp / s.dd_prev;
       const double cos2 = (ddp * ddp) / (dd * s.dd_prev);
-      if (cos2 >= 0.99 && mu < 0.999) g = fmin(g, fabs(mu) / (1.0 - mu));
+      if (cos2 >= 0.99 && mu < 0.999 && fabs(mu) / (1.0 - mu) < g) {
+        g = fabs(mu) / (1.0 - mu);
+        k = fabs(mu);
+      }
     }
     s.gain = g;
+    s.contr = k;
   }
   const double gain = s.gain;
   s.dd_prev = dd;
@@ -333,9 +338,13 @@ __device__ inline bool stop_update(StopState& s, const KOpts& o, double change, 
     }
     s.check_next = 0;
   } else {
+    // The check sweep's residual will be about the next change, contr times
+    // this one: fire when that one is predicted to pass.  A check that fails
+    // costs nothing extra (its output is the next iterate), and the check
+    // never comes later than when this change itself passes.
     const bool fire = (o.stop_rule == DTM_STOP_CHANGE)
                           ? (change < o.tol)
-                          : (change == 0.0 || (s.iter >= 2 && change * gain <= o.safety * o.tol));
+                          : (change == 0.0 || (s.iter >= 2 && change * gain * s.contr <= o.safety * o.tol));
     if (fire || s.stalled) {
       if (o.final_check) {
         s.check_next = 1;

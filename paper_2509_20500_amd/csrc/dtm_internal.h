@@ -70,6 +70,7 @@ struct StopState {
   double c1, c2, c3;  // last three L1 changes (c1 newest)
   double rho;         // |lambda_2| estimate
   double gain;        // estimated error of the iterate per unit of change
+  double contr;       // estimated contraction of the change per sweep
   double resid;       // float64 residual of the last check sweep
   double dd_prev;     // ||d_{t-1}||_2^2 of the previous difference vector
   int32_t iter;       // sweeps since the (re)start

