@@ -20,6 +20,7 @@ namespace fact {
 
 constexpr int BT = 256;
 constexpr int NVEC = 8;  // float64 vectors of ld per pixel in the scratch region
+constexpr int kLdsMaxN = 2048;  // largest n whose solver vectors are kept in LDS
 
 // Chunk of bins owned by this thread (the layout of pixel_tables).
 __device__ inline void chunk_of(int n, int& j0, int& j1) {
@@ -149,15 +150,26 @@ __device__ StopState power(const PixelMeta& m, const Vecs& V, double c, const TI
   return st;
 }
 
-template <typename T>
+// IN_LDS: the five vectors the iteration touches (g, 1/S, x, u, the last
+// difference) live in LDS (5 n doubles, n <= kLdsMaxN) instead of the
+// workspace, so every pass over them is an LDS pass.
+template <typename T, bool IN_LDS>
 __global__ __launch_bounds__(BT) void k_solve_factored(const PixelMeta* __restrict__ metas,
                                                        double* __restrict__ fact, int64_t vec_elems,
                                                        const T* __restrict__ x0_packed,
                                                        T* __restrict__ pi_packed,
                                                        dtm_solve_info* __restrict__ infos, KOpts o) {
   __shared__ double red[3 * BT / kWave];
+  extern __shared__ double lds_vec[];
   const PixelMeta m = metas[blockIdx.x];
-  const Vecs V = vecs(fact, vec_elems, m);
+  Vecs V = vecs(fact, vec_elems, m);
+  if constexpr (IN_LDS) {
+    V.g = lds_vec;
+    V.invs = lds_vec + m.n;
+    V.x = lds_vec + 2 * m.n;
+    V.u = lds_vec + 3 * m.n;
+    V.dp = lds_vec + 4 * m.n;
+  }
   const double c = tables(m, V, red);
   const StopState st = power<T>(m, V, c, x0_packed ? x0_packed + m.pi_off : nullptr, o, red);
   int j0, j1;
@@ -347,14 +359,36 @@ int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, 
   double* fact = reinterpret_cast<double*>(w + plan->off_fact);
   KOpts o = plan->kopts;
   o.pad = 0;
-  if (plan->dt == DTM_F32)
-    hipLaunchKernelGGL((fact::k_solve_factored<float>), dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas,
-                       fact, plan->vec_elems, static_cast<const float*>(x0_packed_dev),
-                       static_cast<float*>(pi_packed_dev), infos_dev, o);
-  else
-    hipLaunchKernelGGL((fact::k_solve_factored<double>), dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas,
-                       fact, plan->vec_elems, static_cast<const double*>(x0_packed_dev),
-                       static_cast<double*>(pi_packed_dev), infos_dev, o);
+  const bool in_lds = plan->max_n <= fact::kLdsMaxN;
+  const size_t lds = in_lds ? 5 * sizeof(double) * static_cast<size_t>(plan->max_n) : 0;
+  const dim3 grid(plan->n_pixels), block(fact::BT);
+  if (plan->dt == DTM_F32) {
+    const float* x0 = static_cast<const float*>(x0_packed_dev);
+    float* pi = static_cast<float*>(pi_packed_dev);
+    if (in_lds) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(fact::k_solve_factored<float, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+        return DTM_EHIP;
+      hipLaunchKernelGGL((fact::k_solve_factored<float, true>), grid, block, lds, st, metas, fact,
+                         plan->vec_elems, x0, pi, infos_dev, o);
+    } else {
+      hipLaunchKernelGGL((fact::k_solve_factored<float, false>), grid, block, 0, st, metas, fact,
+                         plan->vec_elems, x0, pi, infos_dev, o);
+    }
+  } else {
+    const double* x0 = static_cast<const double*>(x0_packed_dev);
+    double* pi = static_cast<double*>(pi_packed_dev);
+    if (in_lds) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(fact::k_solve_factored<double, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+        return DTM_EHIP;
+      hipLaunchKernelGGL((fact::k_solve_factored<double, true>), grid, block, lds, st, metas, fact,
+                         plan->vec_elems, x0, pi, infos_dev, o);
+    } else {
+      hipLaunchKernelGGL((fact::k_solve_factored<double, false>), grid, block, 0, st, metas, fact,
+                         plan->vec_elems, x0, pi, infos_dev, o);
+    }
+  }
   return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP;
 }
 
