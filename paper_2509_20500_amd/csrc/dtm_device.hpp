@@ -134,20 +134,17 @@ __device__ inline void comp_add(double& s, double& c, double v) {
 
 // ---- bin tables ------------------------------------------------------------
 
-// Probability mass of the standard normal on [za, zb] (za <= zb), from the
-// tail that keeps the difference accurate.
-__device__ inline double gauss_mass(double za, double zb) {
-  const double r = 0.70710678118654752440;  // 1/sqrt(2)
-  if (za >= 0.0) return 0.5 * (erfc(za * r) - erfc(zb * r));
-  if (zb <= 0.0) return 0.5 * (erfc(-zb * r) - erfc(-za * r));
-  return 0.5 * (erf(zb * r) - erf(za * r));
+// Normal tail beyond z on z's side: 1 - Phi(z) for z >= 0, Phi(z) for z < 0.
+__device__ inline double gauss_tail(double z) {
+  return 0.5 * erfc(fabs(z) * 0.70710678118654752440);
 }
 
-// Flux integral of lambda over [a, b] inside one period (Eq. arrival_flux):
-// S times the normal mass plus the background share B (b - a) / t_r.
-__device__ inline double flux_integral(const PixelMeta& m, double a, double b) {
-  const double is = 1.0 / m.sigma;
-  return m.S * gauss_mass((a - m.tau) * is, (b - m.tau) * is) + m.B * (b - a) / m.t_r;
+// Normal mass on [za, zb] (za <= zb) from the tails at its ends (gauss_tail),
+// each difference taken where it keeps its digits.
+__device__ inline double mass_from_tails(double za, double ta, double zb, double tb) {
+  if (za >= 0.0) return ta - tb;
+  if (zb <= 0.0) return tb - ta;
+  return 1.0 - ta - tb;
 }
 
 // lambda(t) = S N(t - tau; 0, sigma^2) + B / t_r (Eq. arrival_flux).
@@ -169,14 +166,26 @@ __device__ double pixel_tables(const PixelMeta& m, T* g, T* lam_out, double* F_o
   const int chunk = (n + BT - 1) / BT;
   const int j0 = min(static_cast<int>(threadIdx.x) * chunk, n);
   const int j1 = min(j0 + chunk, n);
+  // Normal tails at the bin edges and centres: one erfc per edge and one per
+  // centre (an edge is shared by two bins; a chunk's total needs only its
+  // two end edges).
+  const double is = 1.0 / m.sigma;
+  const double bq = m.B / m.t_r;
+  const double z0 = (j0 * delta - m.tau) * is, z1 = (j1 * delta - m.tau) * is;
   double part = 0.0;
-  for (int j = j0; j < j1; ++j) part += flux_integral(m, j * delta, (j + 1) * delta);
+  if (j1 > j0)
+    part = m.S * mass_from_tails(z0, gauss_tail(z0), z1, gauss_tail(z1)) + bq * ((j1 - j0) * delta);
   double total;
   double acc = block_exclusive_scan<BT>(part, red, total);
+  double zl = z0, tl = gauss_tail(z0);
   for (int j = j0; j < j1; ++j) {
     const double lo = j * delta;
-    const double F = acc + flux_integral(m, lo, lo + 0.5 * delta);
-    const double dF = flux_integral(m, lo, (j + 1) * delta);
+    const double zm = (lo + 0.5 * delta - m.tau) * is, zh = ((j + 1) * delta - m.tau) * is;
+    const double tm = gauss_tail(zm), th = gauss_tail(zh);
+    const double F = acc + m.S * mass_from_tails(zl, tl, zm, tm) + bq * (0.5 * delta);
+    const double dF = m.S * mass_from_tails(zl, tl, zh, th) + bq * delta;
+    zl = zh;
+    tl = th;
     double lj, gj;
     if (m.lam_mode == 0) {  // lambda at the bin centre (Section 3.4)
       lj = flux_at(m, lo + 0.5 * delta);
