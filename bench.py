@@ -321,6 +321,36 @@ def cpu_baseline(scenes, sample):
     }
 
 
+def plain_single_pixel(scenes, sample=256):
+    """The plain single-pixel GPU path on the first `sample` pixels: per
+    pixel one dtm_build_transition and one dtm_stationary_pdf (float32, the
+    same stop rule and 1e-6 target, host polling), one pixel after another."""
+    import numpy as np
+    import torch
+
+    from paper_2509_20500_amd import dtm
+    n = int(scenes["n_bins"][0])
+    P = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    ws = dtm.workspace(n, "f32")
+    pi = torch.empty(n, dtype=torch.float32, device="cuda")
+    o = dtm.opts(tol=1e-6)
+    dtm.build_transition(scenes[0], P, ws)
+    dtm.stationary_pdf(P, pi, ws, o)
+    torch.cuda.synchronize()
+    sweeps = []
+    t0 = time.perf_counter()
+    for s in scenes[:sample]:
+        dtm.build_transition(s, P, ws)
+        info = dtm.stationary_pdf(P, pi, ws, o)
+        if info.status != dtm.DTM_OK:
+            raise RuntimeError(f"single-pixel solve failed: {info.status}")
+        sweeps.append(info.iterations)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"pixels_per_s": sample / dt, "sample": f"first {sample} pixels, one build + one solve each",
+            "mean_sweeps": float(np.mean(sweeps))}
+
+
 def copy_calibration(nbytes=1 << 30, reps=10):
     """A plain device-to-device copy of known size (torch's elementwise copy
     kernel): its achieved GB/s, and the reference whose FETCH_SIZE and
@@ -469,6 +499,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="pick tile shapes by timing candidates")
     ap.add_argument("--check", type=int, default=16, help="pixels compared with the oracle after timing")
     ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--single-sample", type=int, default=256,
+                    help="pixels timed on the plain single-pixel GPU path (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--threads", type=int, default=0, help="fused block size (0 = default)")
     ap.add_argument("--unroll", type=int, default=0, help="rows in flight per thread (0 = default)")
@@ -623,6 +655,9 @@ def main():
     del ws
     if args.calibrate:
         out["copy_calibration"] = copy_calibration()
+    if not uneven and not factored and args.single_sample > 0:
+        out["plain_single_pixel_gpu"] = plain_single_pixel(scenes, args.single_sample)
+        out["plain_single_pixel_gpu"]["batched_speedup"] = value / out["plain_single_pixel_gpu"]["pixels_per_s"]
     if not args.no_cpu_baseline and not uneven and not factored:
         out["cpu_baseline"] = cpu_baseline(scenes, args.cpu_sample)
     print(json.dumps(out), flush=True)
