@@ -504,6 +504,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--threads", type=int, default=0, help="fused block size (0 = default)")
     ap.add_argument("--unroll", type=int, default=0, help="rows in flight per thread (0 = default)")
+    ap.add_argument("--fused-max-bins", type=int, default=0, help="largest n of the fused kernel (0 = default)")
+    ap.add_argument("--band-rows", type=int, default=0, help="rows per banded work item (0 = default)")
+    ap.add_argument("--band-cpt", type=int, default=0, help="column vectors per thread, banded (0 = default)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also time a plain 1 GiB device copy (the reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -532,8 +535,8 @@ def main():
         scenes = sc.batched_uniform(n_pixels=args.pixels or 4096)
     sopts = dtm.opts(tol=1e-6)
     tune_report = None
-    if args.threads or args.unroll:
-        tiles = dtm.tiles(args.threads, args.unroll)
+    if args.threads or args.unroll or args.band_rows or args.band_cpt or args.fused_max_bins:
+        tiles = dtm.tiles(args.threads, args.unroll, args.fused_max_bins, args.band_rows, 0, args.band_cpt)
     elif args.autotune:
         from paper_2509_20500_amd.autotune import autotune
         tiles, tune_report = autotune(scenes, args.dtype, sopts)

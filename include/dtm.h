@@ -203,10 +203,14 @@ typedef struct dtm_tile_config {
   int32_t fused_threads;   /* threads per workgroup of the fused kernel: 256 or 512     */
   int32_t fused_unroll;    /* rows in flight per thread in a sweep: 2, 4 or 8           */
   int32_t fused_max_bins;  /* pixels with n_b above this take the banded path (>= 2)    */
-  int32_t band_rows;       /* rows per workgroup in the banded sweep, multiple of 16   */
+  int32_t band_rows;       /* rows per workgroup in the banded sweep, multiple of 16,
+                              at most 8192 (0 = 1024)                                  */
   int32_t band_sweeps;     /* sweeps launched for banded pixels (<= max_iter); a banded
                               pixel not converged by then ends with DTM_ENOTCONV       */
-  int32_t reserved[3];     /* must be 0                                                 */
+  int32_t band_cpt;        /* column vectors per thread in the banded sweep: 1, 2 or 4
+                              (0 = 1); a workgroup covers 256 x band_cpt x (4 float /
+                              2 double) columns of its rows                            */
+  int32_t reserved[2];     /* must be 0                                                 */
 } dtm_tile_config;
 
 typedef struct dtm_plan dtm_plan; /* opaque host object */

@@ -33,15 +33,16 @@ def candidates(scenes):
     """The search space, pruned to shapes that differ for these scenes."""
     n_max = int(np.max(scenes["n_bins"]))
     out, seen = [], set()
-    for unroll, fmax, band in itertools.product((2, 4, 8), (1024, 2048, 4096), (128, 256, 512)):
+    for unroll, fmax, band, cpt in itertools.product((4, 8), (1024, 2048, 4096), (256, 1024, 8192),
+                                                     (1, 4)):
         eff_fmax = min(fmax, n_max)
-        eff_band = band if n_max > fmax else 0
-        sig = (unroll, eff_fmax, eff_band)
+        big = n_max > fmax
+        sig = (unroll, eff_fmax, band if big else 0, cpt if big else 0)
         if sig in seen:
             continue
         seen.add(sig)
         out.append(dtm.tiles(fused_threads=256, fused_unroll=unroll, fused_max_bins=fmax,
-                             band_rows=band))
+                             band_rows=band, band_cpt=cpt))
     return out
 
 

@@ -181,13 +181,14 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   if (tc.fused_threads == 0) tc.fused_threads = 256;
   if (tc.fused_unroll == 0) tc.fused_unroll = 8;
   if (tc.fused_max_bins == 0) tc.fused_max_bins = 2048;
-  if (tc.band_rows == 0) tc.band_rows = 256;
+  if (tc.band_rows == 0) tc.band_rows = 1024;
   if (tc.band_sweeps == 0) tc.band_sweeps = std::min(ko.max_iter, 64);
+  if (tc.band_cpt == 0) tc.band_cpt = 1;
   if ((tc.fused_threads != 256 && tc.fused_threads != 512) ||
       (tc.fused_unroll != 2 && tc.fused_unroll != 4 && tc.fused_unroll != 8) ||
-      tc.fused_max_bins < 2 || tc.band_rows < 16 || tc.band_rows % 16 != 0 ||
-      tc.band_sweeps < 1 || tc.band_sweeps > ko.max_iter || tc.reserved[0] || tc.reserved[1] ||
-      tc.reserved[2]) {
+      tc.fused_max_bins < 2 || tc.band_rows < 16 || tc.band_rows % 16 != 0 || tc.band_rows > 8192 ||
+      tc.band_sweeps < 1 || tc.band_sweeps > ko.max_iter ||
+      (tc.band_cpt != 1 && tc.band_cpt != 2 && tc.band_cpt != 4) || tc.reserved[0] || tc.reserved[1]) {
     delete plan;
     return DTM_EINVAL;
   }
@@ -271,7 +272,7 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   // others the banded path (row bands x column blocks, one block each).
   const int32_t vn = dt == DTM_F32 ? 4 : 2;
   plan->band_threads = 256;
-  plan->band_cpt = 4;
+  plan->band_cpt = tc.band_cpt;
   const int32_t colw = plan->band_threads * vn * plan->band_cpt;
   plan->max_n_small = plan->max_ld_small = plan->max_n_big = plan->max_ld_big = 0;
   int64_t acc_part = 0;

@@ -1081,7 +1081,7 @@ int launch_refine(const dtm_plan* plan, const PixelMeta* metas, T* pi, dtm_solve
 template <typename T>
 int launch_banded(const dtm_plan* plan, const PixelMeta* metas, const T* colf, const double* scal,
                   const T* invs, T* pool, const T* x0, T* pi, dtm_solve_info* infos, hipStream_t st) {
-  constexpr int BT = 256, CPT = 4;
+  constexpr int BT = 256;
   char* w = static_cast<char*>(plan->ws);
   const int32_t* big = reinterpret_cast<const int32_t*>(w + plan->off_big);
   const BandItem* items = reinterpret_cast<const BandItem*>(w + plan->off_items);
@@ -1098,10 +1098,11 @@ int launch_banded(const dtm_plan* plan, const PixelMeta* metas, const T* colf, c
   if (rc) return rc;
   void (*sweep)(const PixelMeta*, const BandItem*, const T*, const double*, const T*, T*, const T*,
                 const SolveState*, double*, int, int) = nullptr;
-  switch (plan->tiles.fused_unroll) {
-    case 2: sweep = k_band_sweep<T, BT, CPT, 2>; break;
-    case 4: sweep = k_band_sweep<T, BT, CPT, 4>; break;
-    default: sweep = k_band_sweep<T, BT, CPT, 8>; break;
+  const int u = plan->tiles.fused_unroll;
+  switch (plan->band_cpt) {
+    case 1: sweep = u == 2 ? k_band_sweep<T, BT, 1, 2> : u == 4 ? k_band_sweep<T, BT, 1, 4> : k_band_sweep<T, BT, 1, 8>; break;
+    case 2: sweep = u == 2 ? k_band_sweep<T, BT, 2, 2> : u == 4 ? k_band_sweep<T, BT, 2, 4> : k_band_sweep<T, BT, 2, 8>; break;
+    default: sweep = u == 2 ? k_band_sweep<T, BT, 4, 2> : u == 4 ? k_band_sweep<T, BT, 4, 4> : k_band_sweep<T, BT, 4, 8>; break;
   }
   for (int t = 0; t < plan->tiles.band_sweeps; ++t) {
     hipLaunchKernelGGL(sweep, dim3(nitems), dim3(BT), lds, st, metas, items, colf, scal, invs, pool,
