@@ -283,6 +283,96 @@ def mc_sweep_workload(args):
     return out
 
 
+def single_pixel_workload(args):
+    """The single-pixel configurations: N=1000 float64 to change < 1e-12
+    (period 100 ns, sigma 0.5 ns at 30 ns, S 0.5, B 0.1, dead time 75 ns),
+    and N=4096 at dead times {10, 33, 75, 150} ns for eight seeded scenes
+    (seed 2), float64 and float32.  One step = dtm_build_transition +
+    dtm_stationary_pdf of one pixel (host polling); the 4096-bin sweep points
+    are also solved as one batched plan for comparison."""
+    import numpy as np
+    import torch
+
+    from oracle import dtm as odtm
+    from paper_2509_20500_amd import dtm
+    from synth import scenes as sc
+
+    def solve_one(s, dt, o, P, ws, pi):
+        dtm.build_transition(s, P, ws)
+        return dtm.stationary_pdf(P, pi, ws, o)
+
+    res = {}
+    # N = 1000, float64, change < 1e-12
+    s1 = sc.single_pixel_n1000()
+    n = 1000
+    P = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    ws = dtm.workspace(n, "f64")
+    pi = torch.empty(n, dtype=torch.float64, device="cuda")
+    o1 = dtm.opts(tol=1e-12, stop_rule=dtm.DTM_STOP_CHANGE, max_iter=100000)
+    for _ in range(args.warmup):
+        solve_one(s1, "f64", o1, P, ws, pi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = solve_one(s1, "f64", o1, P, ws, pi)
+    torch.cuda.synchronize()
+    ms1 = (time.perf_counter() - t0) * 1e3 / args.steps
+    err1 = float(np.abs(pi.cpu().numpy() - odtm.stationary_solve(odtm.transition_matrix(s1))).sum())
+    res["n1000_f64"] = {"ms_per_pixel": ms1, "sweeps": int(info.iterations), "l1_vs_oracle": err1}
+    # N = 4096 sweep points
+    scenes = sc.single_pixel_n4096()
+    n = 4096
+    refs = [odtm.stationary_solve(odtm.transition_matrix(s)) for s in scenes[:args.check]]
+    for dt, o in (("f64", dtm.opts(tol=1e-10)), ("f32", dtm.opts(tol=1e-6))):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        P = torch.empty((n, n), dtype=tdt, device="cuda")
+        ws = dtm.workspace(n, dt)
+        pi = torch.empty(n, dtype=tdt, device="cuda")
+        solve_one(scenes[0], dt, o, P, ws, pi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        errs, sweeps = [], []
+        for k, s in enumerate(scenes):
+            info = solve_one(s, dt, o, P, ws, pi)
+            sweeps.append(info.iterations)
+            if k < len(refs):
+                errs.append(float(np.abs(pi.cpu().numpy().astype(np.float64) - refs[k]).sum()))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / len(scenes)
+        del P
+        plan = dtm.Plan(scenes, dt, o)
+        wsb = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+        plan.bind(wsb)
+        pib = torch.empty(plan.pi_elems, dtype=tdt, device="cuda")
+        infos = torch.zeros(plan.n_pixels * 40, dtype=torch.uint8, device="cuda")
+        plan.solve(pib, infos)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.solve(pib, infos)
+        torch.cuda.synchronize()
+        msb = (time.perf_counter() - t1) * 1e3 / args.steps
+        got = pib.cpu().numpy().astype(np.float64)
+        off = plan.pi_offsets
+        errb = max(float(np.abs(got[off[k]:off[k + 1]] - refs[k]).sum()) for k in range(len(refs)))
+        plan.close()
+        del wsb
+        res[f"n4096_{dt}"] = {"ms_per_pixel_single_path": ms, "mean_sweeps": float(np.mean(sweeps)),
+                              "l1_vs_oracle_max": max(errs) if errs else None,
+                              "batched_ms_all_sweep_points": msb, "batched_pixels": len(scenes),
+                              "batched_l1_vs_oracle_max": errb}
+    return {
+        "metric": "single-pixel stationary PDF latency (N=1000 float64 to change < 1e-12)",
+        "value": 1e3 / ms1, "unit": "pixels/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "single pixels: N=1000 float64 (t_d 75 ns, sigma 0.5 ns at 30 ns, S 0.5, B 0.1); "
+                               "N=4096 sigma 0.2 ns, t_d in {10,33,75,150} ns x 8 seeded scenes (seed 2), "
+                               "float64 and float32"},
+        "single_pixel": res,
+    }
+
+
 def _oracle_one(rec):
     import numpy as np
 
@@ -490,7 +580,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--workload", default="batched_uniform",
-                    choices=["batched_uniform", "batched_uneven", "warm_start", "mc_sweep"])
+                    choices=["batched_uniform", "batched_uneven", "warm_start", "mc_sweep", "single_pixel"])
     ap.add_argument("--epochs", type=int, default=150, help="warm_start: training epochs")
     ap.add_argument("--pixels", type=int, default=0, help="0 = the workload's own count")
     ap.add_argument("--graph", action="store_true", help="replay the solve as a captured HIP graph")
@@ -524,8 +614,9 @@ def main():
 
     dtm.lib()
     torch.cuda.set_device(0)
-    if args.workload in ("warm_start", "mc_sweep"):
-        out = warm_start_workload(args) if args.workload == "warm_start" else mc_sweep_workload(args)
+    if args.workload in ("warm_start", "mc_sweep", "single_pixel"):
+        out = {"warm_start": warm_start_workload, "mc_sweep": mc_sweep_workload,
+               "single_pixel": single_pixel_workload}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     uneven = args.workload == "batched_uneven"
