@@ -152,6 +152,15 @@ int dtm_validate_scene(const dtm_scene* s);
  * it is one to 1e-9 relative (a dead time of whole bins is not rounded up). */
 int dtm_shift_bins(const dtm_scene* s, int32_t* l_out);
 
+/* Host only, pure: the shift a plan uses under the discretisation flags
+ * (see DTM_FLAG_SHIFT_NEAREST / DTM_FLAG_SHIFT_INTERP): with q = x_d n_b / t_r
+ * and the same 1e-9 integer snapping, NEAREST gives l = ceil(q - 1/2),
+ * INTERP gives q = l + frac with 0 <= frac < 1, neither gives Theorem 2's l
+ * and frac = 0; l is taken mod n_b.  Other flag bits are ignored; both
+ * SHIFT flags together, an invalid scene or a null output return
+ * DTM_EINVAL. */
+int dtm_model_shift(const dtm_scene* s, int32_t flags, int32_t* l_out, double* frac_out);
+
 /* ---- single pixel ------------------------------------------------------- */
 
 /* Device workspace every single-pixel call below needs, in bytes, for a

@@ -148,6 +148,15 @@ int dtm_shift_bins(const dtm_scene* s, int32_t* l_out) {
   return shift_bins(*s, l_out);
 }
 
+int dtm_model_shift(const dtm_scene* s, int32_t flags, int32_t* l_out, double* frac_out) {
+  if (!s || !l_out || !frac_out) return DTM_EINVAL;
+  if ((flags & DTM_FLAG_SHIFT_NEAREST) && (flags & DTM_FLAG_SHIFT_INTERP)) return DTM_EINVAL;
+  const int st = validate_scene(*s, DTM_F64);
+  if (st != DTM_OK) return st;
+  model_shift(*s, flags, l_out, frac_out);
+  return DTM_OK;
+}
+
 size_t dtm_workspace_bytes(int32_t n, dtm_dtype dt) {
   if (n < 2 || n > DTM_MAX_BINS || (dt != DTM_F32 && dt != DTM_F64)) return 0;
   return single_layout(n, dt).total;

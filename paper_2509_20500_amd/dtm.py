@@ -47,7 +47,7 @@ DTM_INFO_REFINED = 0x10
 DTM_MAX_BINS = 65536
 
 SYMBOLS = [
-    "dtm_status_string", "dtm_version", "dtm_validate_scene", "dtm_shift_bins",
+    "dtm_status_string", "dtm_version", "dtm_validate_scene", "dtm_shift_bins", "dtm_model_shift",
     "dtm_workspace_bytes", "dtm_bin_tables", "dtm_build_base", "dtm_apply_deadtime_shift",
     "dtm_build_transition", "dtm_stationary_pdf", "dtm_plan_create", "dtm_plan_destroy",
     "dtm_plan_workspace_bytes", "dtm_plan_pi_elems", "dtm_plan_matrix_elems", "dtm_plan_offsets",
@@ -140,6 +140,8 @@ def lib() -> ctypes.CDLL:
         "dtm_version": (ctypes.c_int, []),
         "dtm_validate_scene": (ctypes.c_int, [ctypes.POINTER(Scene)]),
         "dtm_shift_bins": (ctypes.c_int, [ctypes.POINTER(Scene), ctypes.POINTER(_I32)]),
+        "dtm_model_shift": (ctypes.c_int, [ctypes.POINTER(Scene), _I32, ctypes.POINTER(_I32),
+                                           ctypes.POINTER(ctypes.c_double)]),
         "dtm_workspace_bytes": (_SZ, [_I32, ctypes.c_int]),
         "dtm_bin_tables": (ctypes.c_int, [ctypes.POINTER(Scene), ctypes.c_int, _P, _P, _P, _SZ, _P]),
         "dtm_build_base": (ctypes.c_int, [ctypes.POINTER(Scene), ctypes.c_int, _P, _I64, _P, _SZ, _P]),
@@ -245,6 +247,15 @@ def dtm_shift_bins(scene) -> int:
     out = _I32(0)
     check(lib().dtm_shift_bins(ctypes.byref(s), ctypes.byref(out)), "dtm_shift_bins")
     return out.value
+
+
+def dtm_model_shift(scene, flags):
+    """(l, frac) of a plan's pixel under the discretisation flags."""
+    s = scene_struct(scene)
+    l, f = _I32(0), ctypes.c_double(0.0)
+    check(lib().dtm_model_shift(ctypes.byref(s), int(flags), ctypes.byref(l), ctypes.byref(f)),
+          "dtm_model_shift")
+    return l.value, f.value
 
 
 def dtm_workspace_bytes(n: int, dtype) -> int:

@@ -141,3 +141,71 @@ def test_plan_rejects_bad_inputs(d):
     # an unbound plan launches nothing
     assert d.lib().dtm_solve_batched(plan.handle, None, 1 << 20, 1 << 21, None) == d.DTM_EINVAL
     plan.close()
+
+
+def test_tile_config_defaults_and_limits(d):
+    scenes = sc.batched_uneven(64)
+    plan = d.Plan(scenes, "f32")
+    t = plan.tiles
+    assert (t.band_rows, t.band_cpt) == (1024, 1)
+    plan.close()
+    for bad in (d.tiles(band_cpt=3), d.tiles(band_cpt=8), d.tiles(band_rows=8208), d.tiles(band_rows=24),
+                d.tiles(fused_unroll=16)):
+        with pytest.raises(d.DtmError):
+            d.Plan(scenes, "f32", tiles=bad)
+    t = d.tiles(band_rows=512, band_cpt=2)
+    t.reserved[1] = 1
+    with pytest.raises(d.DtmError):
+        d.Plan(scenes, "f32", tiles=t)
+
+
+def test_model_shift_matches_oracle_variants(d):
+    """The host's shift under the discretisation flags against the oracle's
+    independent rules (Theorem 2, the bin of the shifted centre, the
+    fractional shift), including whole-bin and half-bin dead times."""
+    from oracle import variants as ov
+    scenes = list(np.concatenate([sc.random_small(200, seed=42), sc.batched_uneven(200)]))
+    scenes += [sc.scene(period=64.0, dead_time=6.0, n_bins=16), sc.scene(period=100.0, dead_time=40.625, n_bins=16),
+               sc.scene(period=100.0, dead_time=50.0, n_bins=1024), sc.scene(period=100.0, dead_time=0.0, n_bins=7),
+               sc.scene(period=100.0, dead_time=200.0, n_bins=9)]
+    for s in scenes:
+        assert d.dtm_model_shift(s, 0) == (odtm.shift_bins(s), 0.0)
+        assert d.dtm_model_shift(s, d.DTM_FLAG_SHIFT_NEAREST) == (ov.shift_bins_nearest(s), 0.0)
+        l, f = d.dtm_model_shift(s, d.DTM_FLAG_SHIFT_INTERP | d.DTM_FLAG_BIN_INTEGRAL)
+        lo, fo = ov.fractional_shift(s)
+        assert l == lo and abs(f - fo) <= 1e-12 and 0.0 <= f < 1.0
+    with pytest.raises(d.DtmError):
+        d.dtm_model_shift(scenes[0], d.DTM_FLAG_SHIFT_NEAREST | d.DTM_FLAG_SHIFT_INTERP)
+
+
+def test_variant_flags_on_plans(d):
+    s = sc.random_small(4, seed=43)
+    for flags in (d.DTM_FLAG_SHIFT_NEAREST | d.DTM_FLAG_SHIFT_INTERP,
+                  d.DTM_FLAG_LAMBDA_BIN_MEAN | d.DTM_FLAG_BIN_INTEGRAL, 0x40):
+        with pytest.raises(d.DtmError):
+            d.Plan(s, "f64", d.opts(flags=flags | d.DTM_FLAG_NO_DENSE))
+    with pytest.raises(d.DtmError) as e:  # the dense kernels read whole shifted rows
+        d.Plan(s, "f64", d.opts(flags=d.DTM_FLAG_SHIFT_INTERP))
+    assert e.value.status == d.DTM_ENOTSUP
+    for flags in (d.DTM_FLAG_SHIFT_NEAREST, d.DTM_FLAG_LAMBDA_BIN_MEAN | d.DTM_FLAG_SHIFT_NEAREST,
+                  d.DTM_FLAG_BIN_INTEGRAL, d.DTM_FLAG_SHIFT_INTERP | d.DTM_FLAG_NO_DENSE):
+        d.Plan(s, "f32", d.opts(flags=flags)).close()
+
+
+def test_monte_carlo_arguments_before_any_launch(d):
+    """An unbound plan and bad arguments return before anything launches."""
+    lib = d.lib()
+    plan = d.Plan(sc.random_small(3, seed=44), "f64")
+    fake = 1 << 20
+    assert lib.dtm_mc_histograms(plan.handle, 4, 100, 0, 1, 0, fake, fake, None) == d.DTM_EINVAL  # unbound
+    assert lib.dtm_mc_histograms(None, 4, 100, 0, 1, 0, fake, fake, None) == d.DTM_EINVAL
+    plan.close()
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
