@@ -283,6 +283,77 @@ def mc_sweep_workload(args):
     return out
 
 
+def spectral_workload(args):
+    """Section 4's spectral analysis on the GPU: for S, B in {0.1, 1, ..., 10}
+    at dead times 75 and 95 ns (242 pixels, N = 1024, period 100 ns, pulse at
+    30 ns with sigma 0.5 ns), lambda_2 (gap and phase) and the empirical
+    mixing steps to a total-variation distance of 0.25.  One step = one
+    dtm_spectral_batched call (factored float64 operator, no matrix)."""
+    import numpy as np
+    import torch
+
+    from oracle import dtm as odtm, spectral as ospec
+    from paper_2509_20500_amd import dtm
+    from synth import scenes as sc
+
+    grids = [sc.paper_rmse_grid(n_bins=1024, dead_time=td) for td in (75.0, 95.0)]
+    scenes = np.concatenate(grids)
+    o = dtm.opts(tol=1e-12)
+    o.flags |= dtm.DTM_FLAG_NO_DENSE
+    plan = dtm.Plan(scenes, "f64", o)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.bind(ws)
+    eps = 0.25
+    scratch = torch.empty(plan.spectral_scratch_bytes(True), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(plan.n_pixels * 48, dtype=torch.uint8, device="cuda")
+    ms = timed(lambda: plan.spectral(out, scratch, eps, 10000), args.steps, args.warmup)
+    res = dtm.spectral_to_numpy(out)
+    plan.close()
+    n = 1024
+    # algorithmic bytes: every mixing step reads the n x n block of start-state
+    # distributions once and writes the next one (float64); the deflated
+    # power steps move O(n) per pixel and are left out
+    alg_bytes = float(np.sum(16.0 * n * n * np.maximum(res["mixing_steps"], 0)))
+    # sampled check against LAPACK eigenvalues of the oracle's dense matrix
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for p in rng.choice(len(scenes), min(args.check, 4), replace=False):
+        lam, third = ospec.second_eigenvalue(odtm.transition_matrix(scenes[p]))
+        if third < 0.9 * abs(lam):
+            worst = max(worst, abs(res["lambda2_abs"][p] - abs(lam)))
+    summary = {}
+    for g, td in zip(range(2), (75.0, 95.0)):
+        r = res[g * 121:(g + 1) * 121]
+        B = grids[g]["background_flux"]
+        gap = 1.0 - r["lambda2_abs"]
+        # the gap as B grows, at each S: fraction of S rows where it shrinks
+        gs = gap.reshape(11, 11)
+        summary[f"td{int(td)}"] = {
+            "gap_min": float(gap.min()), "gap_max": float(gap.max()),
+            "gap_decreases_with_B_rows": int(np.sum(gs[:, -1] < gs[:, 0])),
+            "corr_gap_B": float(np.corrcoef(gap, B)[0, 1]),
+            "phase_min": float(r["lambda2_arg"].min()), "phase_max": float(r["lambda2_arg"].max()),
+            "frac_phase_below_0.1": float(np.mean(r["lambda2_arg"] < 0.1)),
+            "corr_phase_B": float(np.corrcoef(r["lambda2_arg"], B)[0, 1]),
+            "mixing_steps_min": int(r["mixing_steps"].min()), "mixing_steps_max": int(r["mixing_steps"].max()),
+        }
+    return {
+        "metric": "spectral analysis pixels/s (lambda_2 and mixing steps, N=1024)",
+        "value": plan.n_pixels / (ms * 1e-3), "unit": "pixels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "S,B in {0.1,1..10} x t_d in {75,95} ns (242 pixels), N=1024, t_r 100 ns, "
+                               "pulse 30 ns sigma 0.5 ns; lambda_2 by deflated power steps on the factored "
+                               "operator, mixing steps to TV 0.25 from all 1024 start states",
+                   "pixels": int(len(scenes))},
+        "roofline": {"bound": "hbm", "achieved": alg_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_mixing", "alg_bytes_per_launch": alg_bytes},
+        "lambda2_abs_vs_lapack_sampled_max": worst,
+        "section4": summary,
+    }
+
+
 def single_pixel_workload(args):
     """The single-pixel configurations: N=1000 float64 to change < 1e-12
     (period 100 ns, sigma 0.5 ns at 30 ns, S 0.5, B 0.1, dead time 75 ns),
@@ -580,7 +651,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--workload", default="batched_uniform",
-                    choices=["batched_uniform", "batched_uneven", "warm_start", "mc_sweep", "single_pixel"])
+                    choices=["batched_uniform", "batched_uneven", "warm_start", "mc_sweep", "single_pixel",
+                             "spectral"])
     ap.add_argument("--epochs", type=int, default=150, help="warm_start: training epochs")
     ap.add_argument("--pixels", type=int, default=0, help="0 = the workload's own count")
     ap.add_argument("--graph", action="store_true", help="replay the solve as a captured HIP graph")
@@ -614,9 +686,9 @@ def main():
 
     dtm.lib()
     torch.cuda.set_device(0)
-    if args.workload in ("warm_start", "mc_sweep", "single_pixel"):
+    if args.workload in ("warm_start", "mc_sweep", "single_pixel", "spectral"):
         out = {"warm_start": warm_start_workload, "mc_sweep": mc_sweep_workload,
-               "single_pixel": single_pixel_workload}[args.workload](args)
+               "single_pixel": single_pixel_workload, "spectral": spectral_workload}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     uneven = args.workload == "batched_uneven"

@@ -280,7 +280,7 @@ int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, 
 /* Spectral convergence analysis (Section 4): for every pixel, the second
  * eigenvalue lambda_2 of P~ (magnitude and phase; the spectral gap is
  * 1 - |lambda_2|) and, when mixing_eps > 0, the empirical mixing steps
- *   min n : max_s (1/2) || e_s P~^n - pi ||_1 <= mixing_eps   (n <= max_steps,
+ *   min n : max_s (1/2) || e_s P~^n - pi ||_1 <= mixing_eps   (n <= max_steps <= 2^30,
  * else -1).  lambda_2 comes from power iteration on the deflated operator
  * x -> x P~ - (x 1) pi with a two-term recurrence fit
  * v_{t+2} = a v_{t+1} + b v_t, whose roots are the dominant eigenvalue (or

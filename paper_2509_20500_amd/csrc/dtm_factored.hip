@@ -288,50 +288,60 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
   }
 }
 
-// Empirical mixing steps: all n start states e_s advanced together, one
+// Empirical mixing steps: every start state e_s advanced on its own, one
 // thread per start state (each thread runs its own prefix scan over the n
-// bins).  X and Y are n x n, stored state-minor (X[k * n + s]) so that a
-// warp reads consecutive states.  Requires the tables and pi in V (from
-// k_spectral).
+// bins); block y of a pixel owns states [y BT, (y + 1) BT).  X and Y are
+// n x n, stored state-minor (X[k * n + s]) so that a wavefront reads
+// consecutive states.  The distance of each start state from pi does not
+// grow from one step to the next (P~ is stochastic), so the pixel mixes at
+// the largest over its states of the first step within eps: each block stops
+// when all its states are within eps and merges its step by atomicMax (a
+// block that runs out of steps posts max_steps + 1, read as "not reached").
+// Requires the tables and pi in V and mixing_steps = -1 (from k_spectral).
 __global__ __launch_bounds__(BT) void k_mixing(const PixelMeta* __restrict__ metas,
                                                double* __restrict__ fact, int64_t vec_elems,
                                                double* __restrict__ mix, const int64_t* __restrict__ mix_off,
                                                const double* __restrict__ scal,
                                                dtm_spectral_info* __restrict__ out, double eps,
                                                int max_steps) {
-  __shared__ double red[3 * BT / kWave];
+  __shared__ double red[BT / kWave];
   const PixelMeta m = metas[blockIdx.x];
   const int n = m.n;
+  const int s0 = blockIdx.y * BT;
+  if (s0 >= n) return;
   const Vecs V = vecs(fact, vec_elems, m);
   const double c = scal[blockIdx.x];
   double* X = mix + mix_off[blockIdx.x];
   double* Y = X + static_cast<int64_t>(n) * n;
-  for (int s = threadIdx.x; s < n; s += BT)
+  const int s = s0 + static_cast<int>(threadIdx.x);
+  const bool mine = s < n;
+  if (mine)
     for (int k = 0; k < n; ++k) X[static_cast<int64_t>(k) * n + s] = (k == s) ? 1.0 : 0.0;
-  __syncthreads();
-  int steps = -1;
+  int steps = max_steps + 1;
   for (int t = 1; t <= max_steps; ++t) {
-    double worst = 0.0;
-    for (int s = threadIdx.x; s < n; s += BT) {
+    double tv = 0.0;
+    if (mine) {
       const auto xs = [X, n, s](int i) { return X[static_cast<int64_t>(i) * n + s]; };
       double tot = 0.0;
+#pragma unroll 8
       for (int k = 0; k < n; ++k) tot += shifted_x(xs, n, m.l, m.frac, k) * V.invs[k];
-      double U = 0.0, tv = 0.0;
+      double U = 0.0;
+#pragma unroll 8
       for (int j = 0; j < n; ++j) {
         U += shifted_x(xs, n, m.l, m.frac, j) * V.invs[j];
         const double y = V.g[j] * (c * tot + (1.0 - c) * U);
         Y[static_cast<int64_t>(j) * n + s] = y;
         tv += fabs(y - V.x[j]);
       }
-      worst = fmax(worst, 0.5 * tv);
+      tv *= 0.5;
     }
     // block max
-    for (int off = 32; off > 0; off >>= 1) worst = fmax(worst, __shfl_xor(worst, off, kWave));
-    __syncthreads();
-    if ((threadIdx.x % kWave) == 0) red[threadIdx.x / kWave] = worst;
+    for (int off = 32; off > 0; off >>= 1) tv = fmax(tv, __shfl_xor(tv, off, kWave));
+    if ((threadIdx.x % kWave) == 0) red[threadIdx.x / kWave] = tv;
     __syncthreads();
     double wmax = 0.0;
     for (int i = 0; i < BT / kWave; ++i) wmax = fmax(wmax, red[i]);
+    __syncthreads();
     double* tmp = X;
     X = Y;
     Y = tmp;
@@ -340,7 +350,16 @@ __global__ __launch_bounds__(BT) void k_mixing(const PixelMeta* __restrict__ met
       break;
     }
   }
-  if (threadIdx.x == 0) out[m.index].mixing_steps = steps;
+  if (threadIdx.x == 0) atomicMax(&out[m.index].mixing_steps, steps);
+}
+
+// Pixels some of whose start states did not mix within max_steps: -1.
+__global__ __launch_bounds__(BT) void k_mixing_final(const PixelMeta* __restrict__ metas, int n_pixels,
+                                                     dtm_spectral_info* __restrict__ out, int max_steps) {
+  const int p = blockIdx.x * BT + threadIdx.x;
+  if (p >= n_pixels) return;
+  const int idx = metas[p].index;
+  if (out[idx].mixing_steps > max_steps) out[idx].mixing_steps = -1;
 }
 
 }  // namespace fact
@@ -409,7 +428,8 @@ size_t dtm_spectral_scratch_bytes(const dtm_plan* plan, int32_t with_mixing) {
 int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_steps,
                          dtm_spectral_info* out_dev, void* scratch_dev, size_t scratch_bytes,
                          dtm_stream_t stream) {
-  if (!plan || !plan->ws || !out_dev || !scratch_dev || max_steps < 1) return DTM_EINVAL;
+  if (!plan || !plan->ws || !out_dev || !scratch_dev || max_steps < 1 || max_steps > (1 << 30))
+    return DTM_EINVAL;
   const bool with_mix = mixing_eps > 0.0;
   if (scratch_bytes < dtm_spectral_scratch_bytes(plan, with_mix ? 1 : 0)) return DTM_ENOSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -442,8 +462,12 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
   if (hipMemcpyAsync(mix_off, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice, st) !=
       hipSuccess)
     return DTM_EHIP;
-  hipLaunchKernelGGL(fact::k_mixing, dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas, fact,
+  const unsigned state_blocks = static_cast<unsigned>((plan->max_n + fact::BT - 1) / fact::BT);
+  hipLaunchKernelGGL(fact::k_mixing, dim3(plan->n_pixels, state_blocks), dim3(fact::BT), 0, st, metas, fact,
                      plan->vec_elems, mixbuf, mix_off, scal, out_dev, mixing_eps, max_steps);
+  if (hipGetLastError() != hipSuccess) return DTM_EHIP;
+  hipLaunchKernelGGL(fact::k_mixing_final, dim3((plan->n_pixels + fact::BT - 1) / fact::BT), dim3(fact::BT), 0, st,
+                     metas, plan->n_pixels, out_dev, max_steps);
   if (hipGetLastError() != hipSuccess) return DTM_EHIP;
   // the offsets must outlive the asynchronous copy
   if (hipStreamSynchronize(st) != hipSuccess) return DTM_EHIP;
