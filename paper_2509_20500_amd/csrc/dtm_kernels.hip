@@ -1077,7 +1077,23 @@ int launch_refine(const dtm_plan* plan, const PixelMeta* metas, T* pi, dtm_solve
   return last_launch();
 }
 
-// Banded path: init, then band_sweeps x (sweep over all items, combine).
+// Banded path: k_band_init (launched by the caller before the fused kernel
+// is forked off, so that it does not queue behind the fused kernel's
+// long-running blocks), then band_sweeps x (sweep over all items, combine).
+template <typename T>
+int launch_band_init(const dtm_plan* plan, const PixelMeta* metas, const T* x0, hipStream_t st) {
+  constexpr int BT = 256;
+  char* w = static_cast<char*>(plan->ws);
+  const int32_t* big = reinterpret_cast<const int32_t*>(w + plan->off_big);
+  T* xbuf = reinterpret_cast<T*>(w + plan->off_xbuf);
+  double* dprev = reinterpret_cast<double*>(w + plan->off_dprev);
+  SolveState* states = reinterpret_cast<SolveState*>(w + plan->off_state);
+  const int nbig = static_cast<int>(plan->big_sel.size());
+  hipLaunchKernelGGL((k_band_init<T, BT>), dim3(nbig), dim3(BT), 0, st, metas, big, x0, xbuf, dprev,
+                     states);
+  return last_launch();
+}
+
 template <typename T>
 int launch_banded(const dtm_plan* plan, const PixelMeta* metas, const T* colf, const double* scal,
                   const T* invs, T* pool, const T* x0, T* pi, dtm_solve_info* infos, hipStream_t st) {
@@ -1092,10 +1108,7 @@ int launch_banded(const dtm_plan* plan, const PixelMeta* metas, const T* colf, c
   const int nbig = static_cast<int>(plan->big_sel.size());
   const int nitems = static_cast<int>(plan->items.size());
   const size_t lds = sizeof(T) * static_cast<size_t>(plan->tiles.band_rows);
-  hipLaunchKernelGGL((k_band_init<T, BT>), dim3(nbig), dim3(BT), 0, st, metas, big, x0, xbuf, dprev,
-                     states);
-  int rc = last_launch();
-  if (rc) return rc;
+  int rc = DTM_OK;
   void (*sweep)(const PixelMeta*, const BandItem*, const T*, const double*, const T*, T*, const T*,
                 const SolveState*, double*, int, int) = nullptr;
   const int u = plan->tiles.fused_unroll;
@@ -1140,6 +1153,10 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
   // stream alongside the banded launches, which leave most of the GPU idle
   // while a sweep's last bands and the combines finish.
   const bool fork = nsmall > 0 && nbig > 0;
+  if (nbig > 0) {
+    rc = launch_band_init<T>(plan, metas, x0t, st);
+    if (rc) return rc;
+  }
   hipStream_t fst = st;
   if (fork) {
     fst = static_cast<hipStream_t>(plan->aux_stream);
