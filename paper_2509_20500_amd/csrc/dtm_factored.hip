@@ -193,15 +193,30 @@ __device__ void deflated(const PixelMeta& m, const Vecs& V, double c, const doub
   __syncthreads();
 }
 
+// IN_LDS: the eight vectors live in LDS (8 n doubles, n <= kLdsMaxN); g, 1/S
+// and pi are copied to the workspace at the end for k_mixing.
+template <bool IN_LDS>
 __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ metas,
                                                  double* __restrict__ fact, int64_t vec_elems,
                                                  double* __restrict__ scal_out,
                                                  dtm_spectral_info* __restrict__ out, KOpts o,
                                                  int max_iter) {
   __shared__ double red[3 * BT / kWave];
+  extern __shared__ double lds_vec[];
   const PixelMeta m = metas[blockIdx.x];
   const int n = m.n;
-  const Vecs V = vecs(fact, vec_elems, m);
+  const Vecs G = vecs(fact, vec_elems, m);
+  Vecs V = G;
+  if constexpr (IN_LDS) {
+    V.g = lds_vec;
+    V.invs = lds_vec + n;
+    V.x = lds_vec + 2 * n;
+    V.u = lds_vec + 3 * n;
+    V.dp = lds_vec + 4 * n;
+    V.v0 = lds_vec + 5 * n;
+    V.v1 = lds_vec + 6 * n;
+    V.v2 = lds_vec + 7 * n;
+  }
   const double c = tables(m, V, red);
   if (threadIdx.x == 0) scal_out[blockIdx.x] = c;
   power<double>(m, V, c, static_cast<const double*>(nullptr), o, red);  // pi -> V.x
@@ -274,6 +289,13 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
     prev_re = re;
     prev_im = im;
     if (settled && it >= 4) break;
+  }
+  if constexpr (IN_LDS) {
+    for (int j = j0; j < j1; ++j) {
+      G.g[j] = V.g[j];
+      G.invs[j] = V.invs[j];
+      G.x[j] = V.x[j];
+    }
   }
   if (threadIdx.x == 0) {
     dtm_spectral_info s;
@@ -445,8 +467,17 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
   o.safety = 1.0;
   o.stop_rule = DTM_STOP_BOUND;
   o.pad = 0;
-  hipLaunchKernelGGL(fact::k_spectral, dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas, fact,
-                     plan->vec_elems, scal, out_dev, o, max_steps);
+  if (plan->max_n <= fact::kLdsMaxN) {
+    const size_t lds = 8 * sizeof(double) * static_cast<size_t>(plan->max_n);
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(fact::k_spectral<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+      return DTM_EHIP;
+    hipLaunchKernelGGL(fact::k_spectral<true>, dim3(plan->n_pixels), dim3(fact::BT), lds, st, metas, fact,
+                       plan->vec_elems, scal, out_dev, o, max_steps);
+  } else {
+    hipLaunchKernelGGL(fact::k_spectral<false>, dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas, fact,
+                       plan->vec_elems, scal, out_dev, o, max_steps);
+  }
   if (hipGetLastError() != hipSuccess) return DTM_EHIP;
   if (!with_mix) return DTM_OK;
   // k_spectral left g, 1/S, pi and c in the scratch
