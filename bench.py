@@ -532,6 +532,32 @@ def copy_calibration(nbytes=1 << 30, reps=10):
             "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def pattern_ceiling(n_chunks, chunk_bytes, passes, reps=3):
+    """GB/s of the dense solver's access pattern without its arithmetic
+    (dtm_stream_probe): each workgroup writes its chunk once and reads it
+    back; the time for `passes` (fractional) reads is interpolated between
+    the whole numbers around it."""
+    import math
+
+    import torch
+
+    from paper_2509_20500_amd import dtm
+    buf = torch.empty(n_chunks * chunk_bytes, dtype=torch.uint8, device="cuda")
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    lo = max(0, int(math.floor(passes)))
+    ms = {}
+    for r in (lo, lo + 1):
+        def run():
+            dtm.check(dtm.lib().dtm_stream_probe(buf.data_ptr(), chunk_bytes, n_chunks, r, sink.data_ptr(),
+                                                 dtm._stream(None)), "dtm_stream_probe")
+        ms[r] = timed(run, reps, 1)
+    f = passes - lo
+    t = ms[lo] + f * (ms[lo + 1] - ms[lo])
+    del buf
+    return {"gbs": n_chunks * chunk_bytes * (1.0 + passes) / (t * 1e-3) / 1e9, "chunks": n_chunks,
+            "chunk_bytes": chunk_bytes, "reads": passes, "ms": t}
+
+
 def timed(step, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -821,6 +847,11 @@ def main():
     del ws
     if args.calibrate:
         out["copy_calibration"] = copy_calibration()
+        if not uneven and not factored:
+            pc = pattern_ceiling(plan.n_pixels, 4 * 1024 * 1024 if args.dtype == "f32" else 8 * 1024 * 1024,
+                                 float(info["iterations"].mean()) - 1.0)
+            pc["kernel_frac_of_pattern"] = achieved / pc["gbs"]
+            out["pattern_ceiling"] = pc
     if not uneven and not factored and args.single_sample > 0:
         out["plain_single_pixel_gpu"] = plain_single_pixel(scenes, args.single_sample)
         out["plain_single_pixel_gpu"]["batched_speedup"] = value / out["plain_single_pixel_gpu"]["pixels_per_s"]

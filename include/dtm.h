@@ -327,6 +327,17 @@ int dtm_mc_histograms(const dtm_plan* plan, int32_t runs_per_pixel, int64_t cycl
                       int64_t burn_cycles, uint64_t seed, int32_t lanes_per_run,
                       uint32_t* hist_packed_dev, uint32_t* overflow_dev, dtm_stream_t stream);
 
+/* Calibration probe, not part of the method: the dense solver's memory
+ * access pattern without its arithmetic.  Each of n_chunks workgroups writes
+ * its own chunk_bytes of buf_dev (nontemporal stores), then reads it back
+ * `reads` times (nontemporal loads), as the fused kernel writes one pixel's
+ * matrix and sweeps it.  buf_dev holds n_chunks * chunk_bytes bytes (caller
+ * owned, contents overwritten); sink_dev is one float that is never written
+ * for these values.  chunk_bytes a positive multiple of 16, n_chunks >= 1,
+ * reads >= 0, else DTM_EINVAL.  Launch only. */
+int dtm_stream_probe(void* buf_dev, size_t chunk_bytes, int32_t n_chunks, int32_t reads, float* sink_dev,
+                     dtm_stream_t stream);
+
 /* HIP graph of one dtm_solve_batched call: every launch of the solve is
  * captured once and replayed by dtm_graph_launch, which saves the per-launch
  * host cost of the banded path's sweep loop.  The plan, its workspace and the

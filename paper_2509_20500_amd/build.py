@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdtm.so")
 
-SOURCES = ["dtm_kernels.hip", "dtm_factored.hip", "dtm_mc.hip", "dtm_mlp.hip", "dtm_host.cpp"]
+SOURCES = ["dtm_kernels.hip", "dtm_factored.hip", "dtm_mc.hip", "dtm_mlp.hip", "dtm_probe.hip", "dtm_host.cpp"]
 HEADERS = ["dtm_internal.h", "dtm_device.hpp"]
 
 HIPCC_FLAGS = [
