@@ -12,8 +12,11 @@ same steps (the GPU simulator) can be compared count for count:
   (draw block, period c, run, pixel); each block gives four 32-bit words,
   consumed in order; a uniform is (w + 0.5) / 2^32.  Periods draw from
   streams of their own, so a simulator may generate them in any order;
-* per period: Knuth's product-of-uniforms Poisson draw for the pulse count
-  (threshold exp(-S)), then for the background count (threshold exp(-B));
+* per period: the pulse count, then the background count, each a Poisson
+  draw by inversion of one uniform u: the count is the first k with
+  u <= C_k, where C_0 = p_0 = exp(-S) (resp. exp(-B)), p_k = p_{k-1} * S / k,
+  C_k = C_{k-1} + p_k, summed in that order in float64 (k < 128; a u beyond
+  C_127 counts as 127);
   pulse photons come in Box-Muller pairs: two uniforms u1, u2 give
   r = sqrt(-2 ln u1), theta = 2 pi u2 and the times tau + sigma r cos(theta)
   and (when the count is not yet reached) tau + sigma r sin(theta), each kept
@@ -66,25 +69,37 @@ class Stream:
         return (self.buf.pop(0) + 0.5) / 4294967296.0
 
 
-def poisson(st, threshold):
+KMAX = 128
+
+
+def poisson_cdf(mean, p0):
+    """C_0..C_{KMAX-1} of a Poisson law with p_0 = exp(-mean) given."""
+    p, c, out = p0, p0, [p0]
+    for k in range(1, KMAX):
+        p = p * mean / k
+        c = c + p
+        out.append(c)
+    return out
+
+
+def poisson(st, cdf):
+    u = st.uniform()
     k = 0
-    p = st.uniform()
-    while p > threshold:
+    while k < KMAX - 1 and u > cdf[k]:
         k += 1
-        p *= st.uniform()
     return k
 
 
 def simulate_run(scene_fields, cycles, burn, seed, run, pixel, hist):
     """Adds the registrations of one run to ``hist`` (n_b integer counts)."""
     t_r, t_d, tau, sigma, S, B, n = scene_fields
-    e_s, e_b = math.exp(-S), math.exp(-B)
+    cdf_s, cdf_b = poisson_cdf(S, math.exp(-S)), poisson_cdf(B, math.exp(-B))
     delta = t_r / n
     a = 0.0
     for c in range(cycles):
         st = Stream(seed, c, run, pixel)
-        ns = poisson(st, e_s)
-        nb = poisson(st, e_b)
+        ns = poisson(st, cdf_s)
+        nb = poisson(st, cdf_b)
         ts = []
         for i in range(0, ns, 2):
             u1 = st.uniform()

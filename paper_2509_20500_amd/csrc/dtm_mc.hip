@@ -7,8 +7,9 @@
 // Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011), one
 // stream per period: key = seed, counter = (draw block, period, run, pixel).
 // Each block yields four 32-bit words, consumed in order; u = (w + 1/2) / 2^32.
-// Per period: Knuth's product-of-uniforms Poisson draws (pulse, then
-// background; thresholds exp(-S), exp(-B) computed on the host), pulse
+// Per period: Poisson counts (pulse, then background) by inversion of one
+// uniform against cumulative probabilities built from exp(-S), exp(-B)
+// (host libm) by the recurrence p_k = p_{k-1} mean / k, pulse
 // photons in Box-Muller pairs tau + sigma sqrt(-2 ln u1) (cos, sin)(2 pi u2)
 // (the second only while the count is not reached) kept inside [0, t_r),
 // background photons t_r u.  The detector state is the rearm time a relative
@@ -79,13 +80,25 @@ struct Stream {
   }
 };
 
-__device__ inline int poisson(Stream& st, double threshold) {
-  int k = 0;
-  double p = st.uniform();
-  while (p > threshold) {
-    ++k;
-    p *= st.uniform();
+constexpr int KMAX = 128;  // Poisson table length (counts above 127 read as 127)
+
+// C_0 = p_0, p_k = p_{k-1} mean / k, C_k = C_{k-1} + p_k: the cumulative
+// Poisson probabilities, summed in this order (one thread).
+__device__ inline void poisson_cdf(double mean, double p0, double* cdf) {
+  double p = p0, c = p0;
+  cdf[0] = p0;
+  for (int k = 1; k < KMAX; ++k) {
+    p = p * mean / static_cast<double>(k);
+    c = c + p;
+    cdf[k] = c;
   }
+}
+
+// Poisson draw by inversion of one uniform: the first k with u <= C_k.
+__device__ inline int poisson(Stream& st, const double* cdf) {
+  const double u = st.uniform();
+  int k = 0;
+  while (k < KMAX - 1 && u > cdf[k]) ++k;
   return k;
 }
 
@@ -115,6 +128,7 @@ __global__ __launch_bounds__(BT) void k_mc(const PixelMeta* __restrict__ metas, 
                                            int64_t burn, uint64_t seed, int L, int cap,
                                            uint32_t* __restrict__ hist, uint32_t* __restrict__ overflow) {
   extern __shared__ double lds_d[];
+  __shared__ double cdf_s[KMAX], cdf_b[KMAX];
   double* pool = lds_d;
   uint16_t* jend = reinterpret_cast<uint16_t*>(lds_d + cap);
   uint32_t* h = reinterpret_cast<uint32_t*>(lds_d + cap) + (cap + 1) / 2;
@@ -122,6 +136,8 @@ __global__ __launch_bounds__(BT) void k_mc(const PixelMeta* __restrict__ metas, 
   const int n = m.n;
   const int lane = threadIdx.x;
   for (int j = lane; j < n; j += BT) h[j] = 0u;
+  if (lane == 0) poisson_cdf(m.S, m.e_s, cdf_s);
+  if (lane == 1) poisson_cdf(m.B, m.e_b, cdf_b);
   __syncthreads();
   const int k_in = lane % L, base_lane = lane - k_in;
   const int run = blockIdx.y * (BT / L) + lane / L;
@@ -143,29 +159,38 @@ __global__ __launch_bounds__(BT) void k_mc(const PixelMeta* __restrict__ metas, 
     st.pos = 4;
     int ns = 0, nb = 0;
     if (mine) {
-      ns = poisson(st, m.e_s);
-      nb = poisson(st, m.e_b);
+      ns = poisson(st, cdf_s);
+      nb = poisson(st, cdf_b);
     }
     const int off = wave_exclusive_sum(ns + nb, lane);
     const int room = min(ns + nb, max(cap - off, 0));
     double* seg = pool + off;
     int cnt = 0;
     if (mine) {
-      for (int i = 0; i < ns; i += 2) {  // Box-Muller pairs
+      // Box-Muller pairs, two pairs per round so that their transcendental
+      // chains overlap (the second pair's uniforms are drawn only when it
+      // exists, so the stream is consumed exactly as pair by pair)
+      for (int i = 0; i < ns; i += 4) {
         const double u1 = st.uniform();
         const double u2 = st.uniform();
-        const double r = sqrt(-2.0 * log(u1));
-        double sn, cs;
-        sincos(two_pi * u2, &sn, &cs);
-        const double t1 = m.tau + m.sigma * (r * cs);
-        if (t1 >= 0.0 && t1 < m.t_r) {
-          if (cnt < room) seg[cnt++] = t1;
-          else over = true;
+        const bool second = i + 2 < ns;
+        double u3 = 0.5, u4 = 0.25;
+        if (second) {
+          u3 = st.uniform();
+          u4 = st.uniform();
         }
-        const double t2 = m.tau + m.sigma * (r * sn);
-        if (i + 1 < ns && t2 >= 0.0 && t2 < m.t_r) {
-          if (cnt < room) seg[cnt++] = t2;
-          else over = true;
+        const double ra = sqrt(-2.0 * log(u1)), rb = sqrt(-2.0 * log(u3));
+        double sna, csa, snb, csb;
+        sincos(two_pi * u2, &sna, &csa);
+        sincos(two_pi * u4, &snb, &csb);
+        const double t[4] = {m.tau + m.sigma * (ra * csa), m.tau + m.sigma * (ra * sna),
+                             m.tau + m.sigma * (rb * csb), m.tau + m.sigma * (rb * snb)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (i + q < ns && t[q] >= 0.0 && t[q] < m.t_r) {
+            if (cnt < room) seg[cnt++] = t[q];
+            else over = true;
+          }
         }
       }
       for (int i = 0; i < nb; ++i) {
