@@ -308,8 +308,9 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
  * n_b bins of X = T mod t_r (bin ceil(X / Delta) - 1).
  *
  * Random numbers: Philox4x32-10 with key = seed and counter = (draw block,
- * period, run, pixel index); the sampling steps (Poisson counts by inversion
- * of one uniform, Box-Muller pairs of pulse times, time-ordered visit with the rearm time carried from
+ * period, run, pixel index); the sampling steps (block 0: Poisson counts by
+ * inversion of one uniform each; then a block per four pulse photons, two
+ * Box-Muller pairs, and a block per four background photons; time-ordered visit with the rearm time carried from
  * period to period) are fixed, so another implementation of the same steps
  * reproduces the counts exactly.
  *

@@ -9,18 +9,18 @@ the sampling steps are spelled out so that another implementation of the
 same steps (the GPU simulator) can be compared count for count:
 
 * stream of a period: key = (seed low word, seed high word), counter =
-  (draw block, period c, run, pixel); each block gives four 32-bit words,
-  consumed in order; a uniform is (w + 0.5) / 2^32.  Periods draw from
-  streams of their own, so a simulator may generate them in any order;
-* per period: the pulse count, then the background count, each a Poisson
-  draw by inversion of one uniform u: the count is the first k with
-  u <= C_k, where C_0 = p_0 = exp(-S) (resp. exp(-B)), p_k = p_{k-1} * S / k,
-  C_k = C_{k-1} + p_k, summed in that order in float64 (k < 128; a u beyond
-  C_127 counts as 127);
-  pulse photons come in Box-Muller pairs: two uniforms u1, u2 give
-  r = sqrt(-2 ln u1), theta = 2 pi u2 and the times tau + sigma r cos(theta)
-  and (when the count is not yet reached) tau + sigma r sin(theta), each kept
-  when 0 <= t < t_r; each background photon: t = t_r u;
+  (draw block, period c, run, pixel); a block gives four 32-bit words w,
+  each read as the uniform (w + 0.5) / 2^32.  Periods draw from streams of
+  their own, so a simulator may generate them in any order.  Block 0: the
+  pulse count and the background count (words 0 and 1), each a Poisson draw
+  by inversion: the first k with u <= C_k, where C_0 = p_0 = exp(-S) (resp.
+  exp(-B)), p_k = p_{k-1} * S / k, C_k = C_{k-1} + p_k, summed in that order
+  in float64 (k < 128; a u beyond C_127 counts as 127).  Then one block per
+  four pulse photons: words (0, 1) and (2, 3) are two Box-Muller pairs,
+  r = sqrt(-2 ln u1), theta = 2 pi u2, giving tau + sigma r cos(theta) and
+  tau + sigma r sin(theta) in that order, as far as the count goes; a time is
+  kept when 0 <= t < t_r.  Then one block per four background photons,
+  t = t_r u per word, as far as the count goes;
 * the detector state is the rearm time a, measured from the start of the
   current period (0 at the start of a run: armed).  The period's photons are
   sorted by time and visited in order; a photon at t >= a is registered and
@@ -55,18 +55,10 @@ def philox4x32_10(ctr, key):
     return c0, c1, c2, c3
 
 
-class Stream:
-    def __init__(self, seed, cycle, run, pixel):
-        self.key = (seed & MASK, (seed >> 32) & MASK)
-        self.ctr = (cycle & MASK, run & MASK, pixel & MASK)
-        self.block = 0
-        self.buf = []
-
-    def uniform(self):
-        if not self.buf:
-            self.buf = list(philox4x32_10((self.block,) + self.ctr, self.key))
-            self.block += 1
-        return (self.buf.pop(0) + 0.5) / 4294967296.0
+def uniforms(seed, block, cycle, run, pixel):
+    """The four uniforms of one draw block of a period's stream."""
+    w = philox4x32_10((block & MASK, cycle & MASK, run & MASK, pixel & MASK), (seed & MASK, (seed >> 32) & MASK))
+    return [(x + 0.5) / 4294967296.0 for x in w]
 
 
 KMAX = 128
@@ -82,8 +74,7 @@ def poisson_cdf(mean, p0):
     return out
 
 
-def poisson(st, cdf):
-    u = st.uniform()
+def poisson(u, cdf):
     k = 0
     while k < KMAX - 1 and u > cdf[k]:
         k += 1
@@ -97,21 +88,26 @@ def simulate_run(scene_fields, cycles, burn, seed, run, pixel, hist):
     delta = t_r / n
     a = 0.0
     for c in range(cycles):
-        st = Stream(seed, c, run, pixel)
-        ns = poisson(st, cdf_s)
-        nb = poisson(st, cdf_b)
+        u = uniforms(seed, 0, c, run, pixel)
+        ns = poisson(u[0], cdf_s)
+        nb = poisson(u[1], cdf_b)
         ts = []
-        for i in range(0, ns, 2):
-            u1 = st.uniform()
-            u2 = st.uniform()
-            r = math.sqrt(-2.0 * math.log(u1))
-            theta = 2.0 * math.pi * u2
-            pair = (tau + sigma * (r * math.cos(theta)), tau + sigma * (r * math.sin(theta)))
-            for t in pair[:min(2, ns - i)]:
+        block = 1
+        for i in range(0, ns, 4):
+            u = uniforms(seed, block, c, run, pixel)
+            block += 1
+            pulse = []
+            for u1, u2 in ((u[0], u[1]), (u[2], u[3])):
+                r = math.sqrt(-2.0 * math.log(u1))
+                theta = 2.0 * math.pi * u2
+                pulse += [tau + sigma * (r * math.cos(theta)), tau + sigma * (r * math.sin(theta))]
+            for t in pulse[:min(4, ns - i)]:
                 if 0.0 <= t < t_r:
                     ts.append(t)
-        for _ in range(nb):
-            ts.append(t_r * st.uniform())
+        for i in range(0, nb, 4):
+            u = uniforms(seed, block, c, run, pixel)
+            block += 1
+            ts += [t_r * x for x in u[:min(4, nb - i)]]
         ts.sort()
         for t in ts:
             if t >= a:

@@ -5,14 +5,14 @@
 // physics it approximates (Section 3.5 compares with Monte Carlo the same way).
 //
 // Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011), one
-// stream per period: key = seed, counter = (draw block, period, run, pixel).
-// Each block yields four 32-bit words, consumed in order; u = (w + 1/2) / 2^32.
-// Per period: Poisson counts (pulse, then background) by inversion of one
-// uniform against cumulative probabilities built from exp(-S), exp(-B)
-// (host libm) by the recurrence p_k = p_{k-1} mean / k, pulse
-// photons in Box-Muller pairs tau + sigma sqrt(-2 ln u1) (cos, sin)(2 pi u2)
-// (the second only while the count is not reached) kept inside [0, t_r),
-// background photons t_r u.  The detector state is the rearm time a relative
+// stream per period: key = seed, counter = (draw block, period, run, pixel);
+// a block gives four words w, read as u = (w + 1/2) / 2^32.  Block 0: the
+// pulse and background counts (words 0, 1), Poisson draws by inversion of
+// one uniform against cumulative probabilities built from exp(-S), exp(-B)
+// (host libm) by the recurrence p_k = p_{k-1} mean / k.  Then one block per
+// four pulse photons, two Box-Muller pairs tau + sigma sqrt(-2 ln u1)
+// (cos, sin)(2 pi u2) as far as the count goes, kept inside [0, t_r); then
+// one block per four background photons t_r u.  The detector state is the rearm time a relative
 // to the period start (0 = armed): photons are visited in time order, one at
 // t >= a is registered and sets a = t + t_d; the period ends with
 // a = max(a - t_r, 0).
@@ -60,23 +60,16 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
   }
 }
 
-struct Stream {
-  uint32_t k0, k1, cycle, run, pixel, block;
-  uint32_t buf[4];
-  int pos;
+// The four uniforms (w + 1/2) / 2^32 of draw block `block` of a period's
+// stream: Philox4x32-10 of the counter (block, period, run, pixel).
+struct Draws {
+  uint32_t k0, k1, cycle, run, pixel;
 
-  __device__ double uniform() {
-    if (pos == 4) {
-      buf[0] = block++;
-      buf[1] = cycle;
-      buf[2] = run;
-      buf[3] = pixel;
-      philox4x32_10(buf, k0, k1);
-      pos = 0;
-    }
-    const uint32_t w = pos == 0 ? buf[0] : pos == 1 ? buf[1] : pos == 2 ? buf[2] : buf[3];
-    ++pos;
-    return (static_cast<double>(w) + 0.5) * (1.0 / 4294967296.0);
+  __device__ inline void block(uint32_t b, double u[4]) const {
+    uint32_t w[4] = {b, cycle, run, pixel};
+    philox4x32_10(w, k0, k1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = (static_cast<double>(w[q]) + 0.5) * (1.0 / 4294967296.0);
   }
 };
 
@@ -95,8 +88,7 @@ __device__ inline void poisson_cdf(double mean, double p0, double* cdf) {
 }
 
 // Poisson draw by inversion of one uniform: the first k with u <= C_k.
-__device__ inline int poisson(Stream& st, const double* cdf) {
-  const double u = st.uniform();
+__device__ inline int poisson(double u, const double* cdf) {
   int k = 0;
   while (k < KMAX - 1 && u > cdf[k]) ++k;
   return k;
@@ -149,40 +141,34 @@ __global__ __launch_bounds__(BT) void k_mc(const PixelMeta* __restrict__ metas, 
   for (int64_t c0 = 0; c0 < cycles; c0 += L) {
     const int64_t c = c0 + k_in;
     const bool mine = run_ok && c < cycles;
-    Stream st;
+    Draws st;
     st.k0 = static_cast<uint32_t>(seed);
     st.k1 = static_cast<uint32_t>(seed >> 32);
     st.cycle = static_cast<uint32_t>(c);
     st.run = static_cast<uint32_t>(run);
     st.pixel = static_cast<uint32_t>(m.index);
-    st.block = 0u;
-    st.pos = 4;
     int ns = 0, nb = 0;
     if (mine) {
-      ns = poisson(st, cdf_s);
-      nb = poisson(st, cdf_b);
+      double u[4];
+      st.block(0u, u);  // block 0: the two counts
+      ns = poisson(u[0], cdf_s);
+      nb = poisson(u[1], cdf_b);
     }
     const int off = wave_exclusive_sum(ns + nb, lane);
     const int room = min(ns + nb, max(cap - off, 0));
     double* seg = pool + off;
     int cnt = 0;
     if (mine) {
-      // Box-Muller pairs, two pairs per round so that their transcendental
-      // chains overlap (the second pair's uniforms are drawn only when it
-      // exists, so the stream is consumed exactly as pair by pair)
+      // one block per four pulse photons (two Box-Muller pairs, whose
+      // transcendental chains overlap), then one per four background photons
+      uint32_t blk = 1u;
       for (int i = 0; i < ns; i += 4) {
-        const double u1 = st.uniform();
-        const double u2 = st.uniform();
-        const bool second = i + 2 < ns;
-        double u3 = 0.5, u4 = 0.25;
-        if (second) {
-          u3 = st.uniform();
-          u4 = st.uniform();
-        }
-        const double ra = sqrt(-2.0 * log(u1)), rb = sqrt(-2.0 * log(u3));
+        double u[4];
+        st.block(blk++, u);
+        const double ra = sqrt(-2.0 * log(u[0])), rb = sqrt(-2.0 * log(u[2]));
         double sna, csa, snb, csb;
-        sincos(two_pi * u2, &sna, &csa);
-        sincos(two_pi * u4, &snb, &csb);
+        sincos(two_pi * u[1], &sna, &csa);
+        sincos(two_pi * u[3], &snb, &csb);
         const double t[4] = {m.tau + m.sigma * (ra * csa), m.tau + m.sigma * (ra * sna),
                              m.tau + m.sigma * (rb * csb), m.tau + m.sigma * (rb * snb)};
 #pragma unroll
@@ -193,10 +179,16 @@ __global__ __launch_bounds__(BT) void k_mc(const PixelMeta* __restrict__ metas, 
           }
         }
       }
-      for (int i = 0; i < nb; ++i) {
-        const double t = m.t_r * st.uniform();
-        if (cnt < room) seg[cnt++] = t;
-        else over = true;
+      for (int i = 0; i < nb; i += 4) {
+        double u[4];
+        st.block(blk++, u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (i + q < nb) {
+            if (cnt < room) seg[cnt++] = m.t_r * u[q];
+            else over = true;
+          }
+        }
       }
       for (int x = 1; x < cnt; ++x) {  // insertion sort of this lane's segment
         const double v = seg[x];
