@@ -63,10 +63,12 @@ typedef enum dtm_dtype { DTM_F64 = 0, DTM_F32 = 1 } dtm_dtype;
 
 /* One pixel: the problem statement theta = (t_r, t_d, sigma_t, tau, S, B, n_b)
  * of Section 2.2 with the flux model of Eq. (arrival_flux):
- *   lambda(t) = S * N(t - tau; 0, sigma^2) + B / t_r,  t in [0, t_r).
- * Valid: t_r > 0, t_d >= 0 (only t_d mod t_r matters), 0 <= tau < t_r,
- * sigma > 0, S >= 0, B >= 0, S + B > 0, B > 0 or S > 0 with a reachable chain,
- * 2 <= n_b <= DTM_MAX_BINS, reserved == 0, every field finite. */
+ *   lambda(t) = S * N(t - tau; 0, sigma^2) + B / t_r,  t in [0, t_r)
+ * (the Gaussian is cut to the period, so tau may lie anywhere).
+ * Valid: t_r > 0, t_d >= 0 (the chain depends on t_d mod t_r only; the Monte
+ * Carlo simulator uses t_d itself), sigma > 0, S >= 0, B >= 0, S + B > 0,
+ * 2 <= n_b <= DTM_MAX_BINS, reserved == 0, every field finite; otherwise
+ * DTM_EINVAL. */
 typedef struct dtm_scene {
   double period_ns;       /* t_r */
   double dead_time_ns;    /* t_d */
@@ -169,15 +171,18 @@ size_t dtm_workspace_bytes(int32_t n, dtm_dtype dt);
 
 /* Bin tables (Eq. arrival_flux, Theorem 1): writes lambda_dev[j] = lambda(s_j)
  * in dt (n elements) and F_dev[j] = F(s_j) in float64 (n + 1 elements; the
- * last one is Lambda = F(t_r)).  F comes from per-bin flux integrals (erf /
- * erfc differences) and a float64 exclusive prefix scan, plus the half-bin
- * integral up to the centre.  Either output may be NULL. */
+ * last one is Lambda = F(t_r)).  F comes from normal tail probabilities
+ * (erfc) at the bin edges and centres: a float64 exclusive prefix scan of
+ * per-chunk flux integrals, then per-bin integrals and the half-bin integral
+ * up to the centre.  Either output may be NULL. */
 int dtm_bin_tables(const dtm_scene* s, dtm_dtype dt, void* lambda_dev, double* F_dev,
                    void* workspace_dev, size_t workspace_bytes, dtm_stream_t stream);
 
 /* Base matrix (Section 3.4): P_base_dev[k*ld + j] =
  *   lambda_j exp(-Lambda [k > j] - F_j + F_k) / R_k,
- * R_k the row sum (wavefront reduction; compensated in float32).  n x n. */
+ * R_k the row sum, for every row at once from one prefix and one suffix
+ * float64 scan of g_j = lambda_j e^{-F_j} (the factor e^{F_k} cancels).
+ * n x n. */
 int dtm_build_base(const dtm_scene* s, dtm_dtype dt, void* P_base_dev, int64_t ld,
                    void* workspace_dev, size_t workspace_bytes, dtm_stream_t stream);
 
@@ -286,8 +291,12 @@ int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, 
  * v_{t+2} = a v_{t+1} + b v_t, whose roots are the dominant eigenvalue (or
  * complex pair); the fit is reliable when |lambda_3| is clearly below
  * |lambda_2|.  Uses the factored operator (O(n) per step per vector).  The
- * mixing search keeps all n start states (n^2 float64 per pixel of scratch).
- * Launch only. */
+ * mixing search keeps all n start states (2 n^2 float64 per pixel of
+ * scratch).  Without the mixing search the call only launches; with it, it
+ * copies the per-pixel scratch offsets from the host and synchronises
+ * `stream` before returning.  scratch_bytes below
+ * dtm_spectral_scratch_bytes gives DTM_ENOSPACE; max_steps outside
+ * [1, 2^30] or an unbound plan DTM_EINVAL. */
 typedef struct dtm_spectral_info {
   double lambda2_re, lambda2_im;  /* lambda_2 (one of a conjugate pair: im >= 0) */
   double lambda2_abs, lambda2_arg;/* |lambda_2| and its phase in [0, pi]          */
