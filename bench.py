@@ -819,7 +819,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": alg_flops / (ms_step * 1e-3) / 1e12 / 78.6,
             "traffic": None,
-            "kernel": "k_solve_factored",
+            "kernel": "k_solve_factored_wave" if int(scenes["n_bins"].max()) <= 1024 else "k_solve_factored",
             "alg_flops_per_launch": alg_flops,
         } if factored else {
             "bound": "hbm",

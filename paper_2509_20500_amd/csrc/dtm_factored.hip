@@ -178,6 +178,230 @@ __global__ __launch_bounds__(BT) void k_solve_factored(const PixelMeta* __restri
   if (threadIdx.x == 0) infos[m.index] = make_info(st);
 }
 
+// ============================================================================
+// One wavefront per pixel (n <= 64 E): lane t owns bins [t E, t E + E); its
+// tables, the last difference and the product stay in registers, and the
+// iterate lives in LDS, for the shifted reads of the next product.  The LDS
+// copy pads one slot after every E bins, so the lanes' strided accesses fall
+// in distinct banks.  Scans and sums are wavefront shuffles, so no block
+// barrier is ever needed and the four pixels of a block run independently.
+// Same steps and stop rule as k_solve_factored.
+// ============================================================================
+
+namespace wave {
+
+// Exclusive prefix over the lanes of v; *total gets the sum of all lanes.
+// The exclusive value is the previous lane's inclusive one, not the
+// inclusive one minus v: a small prefix next to a large v keeps its digits.
+__device__ inline double excl_scan(double v, int lane, double* total) {
+  double s = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const double u = __shfl_up(s, d, kWave);
+    if (lane >= d) s += u;
+  }
+  *total = __shfl(s, kWave - 1, kWave);
+  const double prev = __shfl_up(s, 1, kWave);
+  return lane == 0 ? 0.0 : prev;
+}
+
+// Exclusive suffix over the lanes of v (sum over the lanes after this one),
+// taken from the next lane's inclusive suffix.
+__device__ inline double excl_scan_rev(double v, int lane) {
+  double s = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const double u = __shfl_down(s, d, kWave);
+    if (lane + d < kWave) s += u;
+  }
+  const double next = __shfl_down(s, 1, kWave);
+  return lane == kWave - 1 ? 0.0 : next;
+}
+
+__device__ inline void sync_wave() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// LDS slot of bin i: one pad slot after every E bins.
+template <int E>
+__device__ inline int slot(int i) {
+  return i + i / E;
+}
+
+template <int E>
+constexpr size_t lds_doubles() {
+  return static_cast<size_t>(kWave) * (E + 1);
+}
+
+template <typename T, int E>
+__global__ __launch_bounds__(BT) void k_solve_factored_wave(const PixelMeta* __restrict__ metas, int n_pixels,
+                                                            const T* __restrict__ x0_packed,
+                                                            T* __restrict__ pi_packed,
+                                                            dtm_solve_info* __restrict__ infos, KOpts o) {
+  extern __shared__ double lds_x[];
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int p = blockIdx.x * (BT / kWave) + wid;
+  if (p >= n_pixels) return;  // whole wavefronts only; nothing below waits for another wavefront
+  const PixelMeta m = metas[p];
+  const int n = m.n;
+  double* xs = lds_x + wid * lds_doubles<E>();
+  const int j0 = lane * E;
+  double* xo = xs + slot<E>(j0);  // this lane's own bins (E consecutive slots)
+
+  // ---- bin tables (as pixel_tables and row_normalisers, per wavefront) ----
+  const double delta = m.t_r / n, is = 1.0 / m.sigma, bq = m.B / m.t_r;
+  const int jb = min(j0, n), je = min(j0 + E, n);
+  const double zb = (jb * delta - m.tau) * is, ze = (je * delta - m.tau) * is;
+  double part = 0.0;
+  if (je > jb) part = m.S * mass_from_tails(zb, gauss_tail(zb), ze, gauss_tail(ze)) + bq * ((je - jb) * delta);
+  double Lam;
+  double acc = excl_scan(part, lane, &Lam);
+  double g[E], inv[E];
+  double zl = zb, tl = gauss_tail(zb);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = j0 + e;
+    g[e] = 0.0;
+    if (j < n) {
+      const double lo = j * delta;
+      const double zm = (lo + 0.5 * delta - m.tau) * is, zh = ((j + 1) * delta - m.tau) * is;
+      const double tm = gauss_tail(zm), th = gauss_tail(zh);
+      const double F = acc + m.S * mass_from_tails(zl, tl, zm, tm) + bq * (0.5 * delta);
+      const double dF = m.S * mass_from_tails(zl, tl, zh, th) + bq * delta;
+      if (m.lam_mode == 0) g[e] = flux_at(m, lo + 0.5 * delta) * exp(-F);
+      else if (m.lam_mode == 1) g[e] = dF / delta * exp(-F);
+      else g[e] = exp(-acc) * -expm1(-dF) / delta;
+      acc += dF;
+      zl = zh;
+      tl = th;
+    }
+  }
+  const double c = exp(-Lam);
+  {
+    double cs = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) cs += g[e];
+    double tot;
+    double P = excl_scan(cs, lane, &tot);
+    double Tk = excl_scan_rev(cs, lane);
+    // inv[] first holds the exclusive prefixes p_k, then 1 / (T_k + c p_k)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      inv[e] = P;
+      P += g[e];
+    }
+#pragma unroll
+    for (int e = E - 1; e >= 0; --e) {
+      Tk += g[e];
+      inv[e] = (j0 + e < n) ? 1.0 / (Tk + c * inv[e]) : 0.0;
+    }
+  }
+
+  // ---- start vector ---------------------------------------------------------
+  StopState st;
+  stop_init(st, 0, 0);
+  const T* x0 = x0_packed ? x0_packed + m.pi_off : nullptr;
+  double sum = 0.0, bad = 0.0;
+  if (x0) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (j0 + e < n) {
+        const double v = static_cast<double>(x0[j0 + e]);
+        if (!(v >= 0.0) || !isfinite(v)) bad += 1.0;
+        else sum += v;
+      }
+    sum = wave_sum(sum);
+    bad = wave_sum(bad);
+  }
+  const bool warm = x0 && bad == 0.0 && sum > 0.0 && isfinite(sum);
+  if (x0 && !warm) st.flags |= DTM_INFO_WARM_REJECTED;
+  st.warm = warm ? 1 : 0;
+  double dp[E], y[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = j0 + e;
+    if (j < n) xo[e] = warm ? static_cast<double>(x0[j]) / sum : 1.0 / n;
+    dp[e] = 0.0;
+  }
+  sync_wave();
+
+  // ---- power iteration --------------------------------------------------------
+  // bin k reads x_{k - l} (and x_{k - l - 1} for an interpolated shift); the
+  // lane's first read index, the rest follow with one wrap at most
+  int i0 = j0 - m.l;
+  if (i0 < 0) i0 += n;
+  const double f = m.frac;
+  for (;;) {
+    // u_k = x_{k - l} / S_k into y[]
+    double cs = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      y[e] = 0.0;
+      if (j0 + e < n) {
+        int i = i0 + e;
+        if (i >= n) i -= n;
+        double xv = xs[slot<E>(i)];
+        if (f != 0.0) {
+          const int i2 = i == 0 ? n - 1 : i - 1;
+          xv = (1.0 - f) * xv + f * xs[slot<E>(i2)];
+        }
+        y[e] = xv * inv[e];
+        cs += y[e];
+      }
+    }
+    double tot;
+    double U = excl_scan(cs, lane, &tot);
+    // y_j = g_j (c U_{n-1} + (1 - c) U_j), in place of u
+    double sy = 0.0, rs = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (j0 + e < n) {
+        U += y[e];
+        y[e] = g[e] * (c * tot + (1.0 - c) * U);
+        sy += y[e];
+        rs += fabs(y[e] - xo[e]);
+      }
+    }
+    sy = wave_sum(sy);
+    rs = wave_sum(rs);
+    sync_wave();  // every shifted read of xs is done before the writes below
+    const double isy = 1.0 / sy;
+    double ch = 0.0, dd = 0.0, ddp = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (j0 + e < n) {
+        const double xn = y[e] * isy;
+        const double d = xn - xo[e];
+        ch += fabs(d);
+        dd += d * d;
+        ddp += d * dp[e];
+        dp[e] = d;
+        xo[e] = xn;
+      }
+    }
+    ch = wave_sum(ch);
+    dd = wave_sum(dd);
+    ddp = wave_sum(ddp);
+    const bool restart = stop_update(st, o, ch, dd, ddp, rs, true, 1.1102230246251565e-16);
+    if (restart) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (j0 + e < n) xo[e] = 1.0 / n;
+        dp[e] = 0.0;
+      }
+    }
+    sync_wave();  // the new iterate is in xs before the next shifted reads
+    if (st.done) break;
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    if (j0 + e < n) pi_packed[m.pi_off + j0 + e] = static_cast<T>(xo[e]);
+  if (lane == 0) infos[m.index] = make_info(st);
+}
+
+}  // namespace wave
+
 // Deflated operator A v = v P~ - (v . 1) pi (removes the Perron pair: left
 // eigenvectors of the other eigenvalues are orthogonal to the right Perron
 // vector 1).  out may alias V.u.
@@ -400,6 +624,26 @@ int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, 
   double* fact = reinterpret_cast<double*>(w + plan->off_fact);
   KOpts o = plan->kopts;
   o.pad = 0;
+  if (plan->max_n <= 1024) {
+    // one wavefront per pixel, four per block; E bins per lane
+    const int E = plan->max_n <= 256 ? 4 : plan->max_n <= 512 ? 8 : 16;
+    const dim3 grid((plan->n_pixels + 3) / 4), block(fact::BT);
+    const size_t lds = sizeof(double) * 4 * kWave * (E + 1);
+    if (plan->dt == DTM_F32) {
+      const float* x0 = static_cast<const float*>(x0_packed_dev);
+      float* pi = static_cast<float*>(pi_packed_dev);
+      if (E == 4) hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<float, 4>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o);
+      else if (E == 8) hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<float, 8>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o);
+      else hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<float, 16>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o);
+    } else {
+      const double* x0 = static_cast<const double*>(x0_packed_dev);
+      double* pi = static_cast<double*>(pi_packed_dev);
+      if (E == 4) hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<double, 4>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o);
+      else if (E == 8) hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<double, 8>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o);
+      else hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<double, 16>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o);
+    }
+    return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP;
+  }
   const bool in_lds = plan->max_n <= fact::kLdsMaxN;
   const size_t lds = in_lds ? 5 * sizeof(double) * static_cast<size_t>(plan->max_n) : 0;
   const dim3 grid(plan->n_pixels), block(fact::BT);
