@@ -599,6 +599,89 @@ __global__ __launch_bounds__(BT) void k_mixing(const PixelMeta* __restrict__ met
   if (threadIdx.x == 0) atomicMax(&out[m.index].mixing_steps, steps);
 }
 
+// The same empirical mixing steps with one wavefront per start state (n <= 64
+// E): the state's distribution stays on chip, its bins [t E, t E + E) in
+// lane t's registers and in a padded LDS copy for the shifted reads, with
+// g, 1/S and pi of the pixel in registers; each wavefront stops at its own
+// first step within eps and merges it by atomicMax.  Block y of a pixel owns
+// states [4 y, 4 y + 4).  No n x n scratch is touched.
+template <int E>
+__global__ __launch_bounds__(BT) void k_mixing_wave(const PixelMeta* __restrict__ metas,
+                                                    const double* __restrict__ fact, int64_t vec_elems,
+                                                    const double* __restrict__ scal,
+                                                    dtm_spectral_info* __restrict__ out, double eps,
+                                                    int max_steps) {
+  extern __shared__ double lds_x[];
+  const PixelMeta m = metas[blockIdx.x];
+  const int n = m.n;
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int s = blockIdx.y * (BT / kWave) + wid;
+  if (s >= n) return;  // whole wavefronts only; nothing below waits for another wavefront
+  const double* base = fact + m.vec_off;
+  const double* gv = base;
+  const double* iv = base + vec_elems;
+  const double* pv = base + 2 * vec_elems;
+  const double c = scal[blockIdx.x];
+  double* xs = lds_x + wid * wave::lds_doubles<E>();
+  const int j0 = lane * E;
+  double* xo = xs + wave::slot<E>(j0);
+  double g[E], inv[E], pi[E], y[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = j0 + e;
+    const bool in = j < n;
+    g[e] = in ? gv[j] : 0.0;
+    inv[e] = in ? iv[j] : 0.0;
+    pi[e] = in ? pv[j] : 0.0;
+    if (in) xo[e] = (j == s) ? 1.0 : 0.0;
+  }
+  wave::sync_wave();
+  int i0 = j0 - m.l;
+  if (i0 < 0) i0 += n;
+  const double f = m.frac;
+  int steps = max_steps + 1;
+  for (int t = 1; t <= max_steps; ++t) {
+    double cs = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      y[e] = 0.0;
+      if (j0 + e < n) {
+        int i = i0 + e;
+        if (i >= n) i -= n;
+        double xv = xs[wave::slot<E>(i)];
+        if (f != 0.0) {
+          const int i2 = i == 0 ? n - 1 : i - 1;
+          xv = (1.0 - f) * xv + f * xs[wave::slot<E>(i2)];
+        }
+        y[e] = xv * inv[e];
+        cs += y[e];
+      }
+    }
+    double tot;
+    double U = wave::excl_scan(cs, lane, &tot);
+    double tv = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (j0 + e < n) {
+        U += y[e];
+        y[e] = g[e] * (c * tot + (1.0 - c) * U);
+        tv += fabs(y[e] - pi[e]);
+      }
+    }
+    tv = 0.5 * wave_sum(tv);
+    wave::sync_wave();  // every shifted read of xs is done before the writes below
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (j0 + e < n) xo[e] = y[e];
+    wave::sync_wave();
+    if (tv <= eps) {
+      steps = t;
+      break;
+    }
+  }
+  if (lane == 0) atomicMax(&out[m.index].mixing_steps, steps);
+}
+
 // Pixels some of whose start states did not mix within max_steps: -1.
 __global__ __launch_bounds__(BT) void k_mixing_final(const PixelMeta* __restrict__ metas, int n_pixels,
                                                      dtm_spectral_info* __restrict__ out, int max_steps) {
@@ -737,9 +820,25 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
   if (hipMemcpyAsync(mix_off, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice, st) !=
       hipSuccess)
     return DTM_EHIP;
-  const unsigned state_blocks = static_cast<unsigned>((plan->max_n + fact::BT - 1) / fact::BT);
-  hipLaunchKernelGGL(fact::k_mixing, dim3(plan->n_pixels, state_blocks), dim3(fact::BT), 0, st, metas, fact,
-                     plan->vec_elems, mixbuf, mix_off, scal, out_dev, mixing_eps, max_steps);
+  if (plan->max_n <= 1024) {
+    // one wavefront per start state, four per block; E bins per lane
+    const int E = plan->max_n <= 256 ? 4 : plan->max_n <= 512 ? 8 : 16;
+    const dim3 grid(plan->n_pixels, static_cast<unsigned>((plan->max_n + 3) / 4));
+    const size_t lds = sizeof(double) * 4 * kWave * (E + 1);
+    if (E == 4)
+      hipLaunchKernelGGL(fact::k_mixing_wave<4>, grid, dim3(fact::BT), lds, st, metas, fact, plan->vec_elems, scal,
+                         out_dev, mixing_eps, max_steps);
+    else if (E == 8)
+      hipLaunchKernelGGL(fact::k_mixing_wave<8>, grid, dim3(fact::BT), lds, st, metas, fact, plan->vec_elems, scal,
+                         out_dev, mixing_eps, max_steps);
+    else
+      hipLaunchKernelGGL(fact::k_mixing_wave<16>, grid, dim3(fact::BT), lds, st, metas, fact, plan->vec_elems,
+                         scal, out_dev, mixing_eps, max_steps);
+  } else {
+    const unsigned state_blocks = static_cast<unsigned>((plan->max_n + fact::BT - 1) / fact::BT);
+    hipLaunchKernelGGL(fact::k_mixing, dim3(plan->n_pixels, state_blocks), dim3(fact::BT), 0, st, metas, fact,
+                       plan->vec_elems, mixbuf, mix_off, scal, out_dev, mixing_eps, max_steps);
+  }
   if (hipGetLastError() != hipSuccess) return DTM_EHIP;
   hipLaunchKernelGGL(fact::k_mixing_final, dim3((plan->n_pixels + fact::BT - 1) / fact::BT), dim3(fact::BT), 0, st,
                      metas, plan->n_pixels, out_dev, max_steps);

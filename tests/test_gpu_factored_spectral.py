@@ -44,6 +44,51 @@ def test_factored_solver_matches_oracle(dt, tol, bar):
     plan.close()
 
 
+def _ragged(n_max, seed):
+    """Five scenes of varied physics whose largest has n_max bins."""
+    scenes = sc.random_small(5, seed=seed).copy()
+    scenes["n_bins"] = [n_max, n_max - 37, 3, 64, n_max // 2 + 1]
+    return scenes
+
+
+@pytest.mark.parametrize("n_max", [200, 500, 1000, 1500])
+def test_factored_solver_each_launch_shape(n_max):
+    """The largest pixel of a plan picks the launch: one wavefront per pixel
+    with 4, 8 or 16 bins per lane up to 1024 bins, a block per pixel with its
+    vectors in LDS above; smaller ragged pixels share the launch."""
+    scenes = _ragged(n_max, seed=140 + n_max)
+    d, plan, ws = _plan(scenes, "f64", lib().opts(tol=1e-12))
+    pi = torch.full((plan.pi_elems,), float("nan"), dtype=torch.float64, device="cuda")
+    infos = torch.zeros(plan.n_pixels * 40, dtype=torch.uint8, device="cuda")
+    plan.solve_factored(pi, infos)
+    torch.cuda.synchronize()
+    info = d.infos_to_numpy(infos)
+    assert np.all(info["status"] == 0), info
+    got = pi.cpu().numpy()
+    for p, (s, v) in enumerate(zip(scenes, split(got, plan.pi_offsets))):
+        assert np.abs(v - oracle_pi(s)).sum() <= 1e-10, (p, s)
+    plan.close()
+
+
+@pytest.mark.parametrize("n_max", [200, 500, 1000, 1100])
+def test_mixing_steps_each_launch_shape(n_max):
+    """Mixing steps with one wavefront per start state (up to 1024 bins) and
+    one thread per start state above, against powers of the dense matrix."""
+    scenes = sc.paper_grid((3.0, 9.0), dead_time=75.0, n_bins=n_max).copy()
+    scenes["n_bins"][1] = n_max - 37
+    d, plan, ws = _plan(scenes, "f64", lib().opts(tol=1e-12))
+    scratch = torch.empty(plan.spectral_scratch_bytes(True), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(plan.n_pixels * 48, dtype=torch.uint8, device="cuda")
+    plan.spectral(out, scratch, 0.25, 5000)
+    torch.cuda.synchronize()
+    res = d.spectral_to_numpy(out)
+    for p, s in enumerate(scenes):
+        Pt = odtm.transition_matrix(s)
+        ref = ospec.mixing_steps(Pt, odtm.stationary_solve(Pt), 0.25)
+        assert res["mixing_steps"][p] == ref, (p, s, res[p], ref)
+    plan.close()
+
+
 def test_factored_solver_at_large_n():
     """n = 65536 (a 16 GiB float32 matrix if formed): check pi by the residual
     of the factorised left product, written out independently in NumPy."""
