@@ -264,7 +264,7 @@ def mc_sweep_workload(args):
             "bound": "alu", "unit": "G VALU wave-instructions/s", "peak": VALU_PEAK_G,
             "achieved": (valu / (k2 * 1e-3) / 1e9) if valu else None,
             "frac": (valu / (k2 * 1e-3) / 1e9 / VALU_PEAK_G) if valu else None,
-            "traffic": None, "kernel": "k_mc (S,B in {0.1,3,6,9} launch)",
+            "traffic": None, "kernel": "k_mc + repair passes (S,B in {0.1,3,6,9} call)",
             "valu_insts_per_launch": valu,
         },
         "k_mc_ms": {"grid_4x4_n1024": k2, "grid_11x11_n256": k3},

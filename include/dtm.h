@@ -319,23 +319,41 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
  * Random numbers: Philox4x32-10 with key = seed and counter = (draw block,
  * period, run, pixel index); the sampling steps (block 0: Poisson counts by
  * inversion of one uniform each; then a block per four pulse photons, two
- * Box-Muller pairs, and a block per four background photons; time-ordered visit with the rearm time carried from
- * period to period) are fixed, so another implementation of the same steps
- * reproduces the counts exactly.
+ * Box-Muller pairs, and a block per four background photons; time-ordered
+ * visit with the rearm time carried from period to period) are fixed, so
+ * another implementation of the same steps reproduces the counts exactly.
+ *
+ * A run may be cut into segments of consecutive periods that are simulated
+ * side by side from the armed state and then repaired where a segment's true
+ * start differed (the repair walks each such segment from its true start
+ * until the two trajectories meet); the counts are those of one sequential
+ * walk of the run whatever the segmentation.
  *
  * hist_packed_dev: uint32 counts packed like pi (runs summed), overwritten.
  * overflow_dev: one uint32 per pixel (input order), zeroed by the caller; set
  * when the 64 periods a wave draws at once held more photons than its pool
  * (their mean plus ten standard deviations; the excess is dropped).
  * lanes_per_run: 0 = automatic, else a power of two <= 64 (lanes that share
- * one run; the counts do not depend on it).  Requires S + B <= 24,
- * n_b <= 16384, 1 <= runs_per_pixel <= 65535, 0 <= burn_cycles < cycles <
- * 2^32 and runs_per_pixel * (cycles - burn_cycles) < 2^26 (so no bin can pass
- * 2^32); else DTM_EINVAL or DTM_ENOTSUP and nothing is launched.  The plan
- * must be bound; launch only. */
+ * one segment; the counts do not depend on it).
+ * segments_per_run: 0 = automatic (about 2^17 segments in all, none shorter
+ * than 256 periods), else 1 .. cycles (1 = no cut; the counts do not depend
+ * on it).
+ * scratch_dev / scratch_bytes: segment states, at least
+ * dtm_mc_scratch_bytes(plan, runs_per_pixel, cycles, segments_per_run) bytes,
+ * 256-byte aligned (may be NULL when that is 0; DTM_ENOSPACE when short).
+ * Requires S + B <= 24, n_b <= 16384, 1 <= runs_per_pixel <= 65535,
+ * 0 <= burn_cycles < cycles < 2^32 and runs_per_pixel * (cycles -
+ * burn_cycles) < 2^26 (so no bin can pass 2^32), at most 2^27 segments in
+ * all and at most 65535 launch blocks per pixel; else DTM_EINVAL or
+ * DTM_ENOTSUP and nothing is launched.  The plan must be bound; launch only
+ * (four kernels on `stream`; the scratch must stay untouched until they
+ * finish). */
+size_t dtm_mc_scratch_bytes(const dtm_plan* plan, int32_t runs_per_pixel, int64_t cycles,
+                            int32_t segments_per_run);
 int dtm_mc_histograms(const dtm_plan* plan, int32_t runs_per_pixel, int64_t cycles,
                       int64_t burn_cycles, uint64_t seed, int32_t lanes_per_run,
-                      uint32_t* hist_packed_dev, uint32_t* overflow_dev, dtm_stream_t stream);
+                      int32_t segments_per_run, uint32_t* hist_packed_dev, uint32_t* overflow_dev,
+                      void* scratch_dev, size_t scratch_bytes, dtm_stream_t stream);
 
 /* Calibration probe, not part of the method: the dense solver's memory
  * access pattern without its arithmetic.  Each of n_chunks workgroups writes

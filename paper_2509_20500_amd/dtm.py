@@ -57,7 +57,7 @@ SYMBOLS = [
     "dtm_mlp_workspace_layout", "dtm_mlp_features", "dtm_mlp_sync_bf16", "dtm_mlp_forward",
     "dtm_mlp_backward", "dtm_mlp_adam", "dtm_mlp_gemm_bf16",
     "dtm_solve_factored_batched", "dtm_spectral_scratch_bytes", "dtm_spectral_batched",
-    "dtm_mc_histograms", "dtm_stream_probe",
+    "dtm_mc_scratch_bytes", "dtm_mc_histograms", "dtm_stream_probe",
 ]
 
 
@@ -168,7 +168,9 @@ def lib() -> ctypes.CDLL:
         "dtm_solve_factored_batched": (ctypes.c_int, [_P, _P, _P, _P, _P]),
         "dtm_spectral_scratch_bytes": (_SZ, [_P, _I32]),
         "dtm_spectral_batched": (ctypes.c_int, [_P, _D, _I32, _P, _P, _SZ, _P]),
-        "dtm_mc_histograms": (ctypes.c_int, [_P, _I32, _I64, _I64, ctypes.c_uint64, _I32, _P, _P, _P]),
+        "dtm_mc_scratch_bytes": (_SZ, [_P, _I32, _I64, _I32]),
+        "dtm_mc_histograms": (ctypes.c_int, [_P, _I32, _I64, _I64, ctypes.c_uint64, _I32, _I32, _P, _P, _P,
+                                             _SZ, _P]),
         "dtm_stream_probe": (ctypes.c_int, [_P, _SZ, _I32, _I32, _P, _P]),
     }
     for name, (res, args) in sig.items():
@@ -394,11 +396,17 @@ class Plan:
                                          _ptr(scratch), scratch.numel(), _stream(stream)),
               "dtm_spectral_batched")
 
-    def mc_histograms(self, runs, cycles, burn, seed, lanes_per_run=0, stream=None, hist=None, over=None):
+    def mc_scratch_bytes(self, runs, cycles, segments_per_run=0):
+        return int(lib().dtm_mc_scratch_bytes(self.handle, int(runs), int(cycles), int(segments_per_run)))
+
+    def mc_histograms(self, runs, cycles, burn, seed, lanes_per_run=0, stream=None, hist=None, over=None,
+                      segments_per_run=0, scratch=None):
         """Monte Carlo registration counts (packed like pi, uint32 held in an
         int32 tensor) and per-pixel overflow flags.  hist/over may be given
         (int32 CUDA tensors of pi_elems and n_pixels elements); over is
-        cleared here."""
+        cleared here.  scratch (a uint8 CUDA tensor of at least
+        mc_scratch_bytes bytes) is allocated here when not given; it must
+        outlive the launches."""
         import torch
         if hist is None:
             hist = torch.empty(self.pi_elems, dtype=torch.int32, device="cuda")
@@ -408,8 +416,14 @@ class Plan:
             over.zero_()
         if hist.numel() < self.pi_elems or over.numel() < self.n_pixels:
             raise ValueError("mc_histograms: output tensors too small")
+        need = self.mc_scratch_bytes(runs, cycles, segments_per_run) if int(runs) >= 1 and int(cycles) >= 1 else 0
+        if scratch is None and need > 0:
+            scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
+        self._mc_scratch = scratch  # kept alive until the next call
         check(lib().dtm_mc_histograms(self.handle, int(runs), int(cycles), int(burn), int(seed),
-                                      int(lanes_per_run), _ptr(hist), _ptr(over), _stream(stream)),
+                                      int(lanes_per_run), int(segments_per_run), _ptr(hist), _ptr(over),
+                                      _ptr(scratch) if scratch is not None else None,
+                                      scratch.numel() if scratch is not None else 0, _stream(stream)),
               "dtm_mc_histograms")
         return hist, over
 

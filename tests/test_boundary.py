@@ -197,8 +197,25 @@ def test_monte_carlo_arguments_before_any_launch(d):
     lib = d.lib()
     plan = d.Plan(sc.random_small(3, seed=44), "f64")
     fake = 1 << 20
-    assert lib.dtm_mc_histograms(plan.handle, 4, 100, 0, 1, 0, fake, fake, None) == d.DTM_EINVAL  # unbound
-    assert lib.dtm_mc_histograms(None, 4, 100, 0, 1, 0, fake, fake, None) == d.DTM_EINVAL
+    assert lib.dtm_mc_histograms(plan.handle, 4, 100, 0, 1, 0, 0, fake, fake, None, 0, None) == d.DTM_EINVAL
+    assert lib.dtm_mc_histograms(None, 4, 100, 0, 1, 0, 0, fake, fake, None, 0, None) == d.DTM_EINVAL
+    plan.close()
+
+
+def test_monte_carlo_segment_scratch_sizes(d):
+    """Host-side segment layout: about 2^17 segments in all, none shorter
+    than 256 periods, empty tail segments dropped; 20 bytes per segment
+    (speculative end, repaired end, coupled flag), none without a cut."""
+    plan = d.Plan(sc.paper_grid(dead_time=75.0, n_bins=64), "f64")  # 16 pixels
+    per = 2 * 8 + 4
+    assert plan.mc_scratch_bytes(100, 50_000) == 16 * 100 * 82 * per  # K = ceil(2^17 / 1600) = 82
+    assert plan.mc_scratch_bytes(100, 10_000) == 16 * 100 * 39 * per  # capped at 10000 // 256 = 39
+    assert plan.mc_scratch_bytes(100, 300) == 0  # one segment: no scratch
+    assert plan.mc_scratch_bytes(3, 400, 1) == 0
+    assert plan.mc_scratch_bytes(3, 400, 400) == 16 * 3 * 400 * per  # one period per segment
+    assert plan.mc_scratch_bytes(3, 10, 4) == 16 * 3 * 4 * per  # segments of 3, 3, 3, 1 periods
+    assert plan.mc_scratch_bytes(3, 10, 6) == 16 * 3 * 5 * per  # segments of 2: the sixth would be empty
+    assert plan.mc_scratch_bytes(3, 10, 11) == 0  # more segments than periods: invalid
     plan.close()
 
 

@@ -19,12 +19,12 @@ from gpu_helpers import lib, split
 pytestmark = pytest.mark.gpu
 
 
-def _mc(scenes, runs, cycles, burn, seed, lanes=0):
+def _mc(scenes, runs, cycles, burn, seed, lanes=0, segments=1):
     d = lib()
     plan = d.Plan(scenes, "f64", d.opts(tol=1e-10))
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     plan.bind(ws)
-    hist, over = plan.mc_histograms(runs, cycles, burn, seed, lanes)
+    hist, over = plan.mc_histograms(runs, cycles, burn, seed, lanes, segments_per_run=segments)
     torch.cuda.synchronize()
     out = split(hist.cpu().numpy().view(np.uint32).astype(np.int64), plan.pi_offsets), over.cpu().numpy()
     plan.close()
@@ -43,23 +43,40 @@ def _edge_scenes():
     ])
 
 
-@pytest.mark.parametrize("runs,cycles,burn,seed,lanes", [
-    (3, 400, 40, 2024, 0), (3, 400, 40, 2024, 1), (3, 397, 40, 2024, 64), (3, 401, 5, 2024, 8),
-    (70, 30, 0, (7 << 32) | 99, 1), (70, 30, 0, (7 << 32) | 99, 2), (70, 30, 29, (7 << 32) | 99, 16)])
-def test_histograms_match_oracle_count_for_count(runs, cycles, burn, seed, lanes):
+@pytest.mark.parametrize("runs,cycles,burn,seed,lanes,segments", [
+    (3, 400, 40, 2024, 0, 1), (3, 400, 40, 2024, 1, 1), (3, 397, 40, 2024, 64, 1), (3, 401, 5, 2024, 8, 1),
+    (70, 30, 0, (7 << 32) | 99, 1, 1), (70, 30, 0, (7 << 32) | 99, 2, 1), (70, 30, 29, (7 << 32) | 99, 16, 1),
+    (3, 400, 40, 2024, 0, 7), (3, 400, 40, 2024, 8, 400), (3, 401, 5, 2024, 64, 13), (3, 397, 40, 2024, 16, 2),
+    (70, 30, 0, (7 << 32) | 99, 1, 30), (70, 30, 29, (7 << 32) | 99, 2, 3), (3, 2000, 100, 5, 0, 0)])
+def test_histograms_match_oracle_count_for_count(runs, cycles, burn, seed, lanes, segments):
     """Edge cases: no dead time, dead time over two periods, pulses cut at
     t = 0, many photons per period (sorting), no signal, no background, two
     bins, ragged bin counts, run blocks that are not full (70 runs), period
     counts that are not a multiple of the lanes per run, one counted period,
     and a key that uses both seed words; every lane grouping gives the same
-    counts."""
+    counts.  Cut runs (segments > 1, 0 = automatic) give them too: from
+    one-period segments, where most segment starts must be repaired and many
+    repairs never meet the speculative walk (dead time over two periods, 18
+    photons a period), to a ragged last segment and the burn-in inside it."""
     scenes = _edge_scenes()
-    got, over = _mc(scenes, runs, cycles, burn, seed, lanes)
+    got, over = _mc(scenes, runs, cycles, burn, seed, lanes, segments)
     ref = mc_philox.histograms(scenes, runs, cycles, burn, seed)
     assert not over.any()
     for p, (g, r) in enumerate(zip(got, ref)):
         assert g.sum() > 0, p
         np.testing.assert_array_equal(g, r, err_msg=f"pixel {p}")
+
+
+def test_segmented_runs_give_the_sequential_counts():
+    """The Section 3.5 grid (S, B in {0.1, 3, 6, 9}) at 2^10 bins, 100 runs of
+    5000 periods: the counts do not depend on how the runs are cut."""
+    scenes = sc.paper_grid(dead_time=75.0, n_bins=1024)
+    ref, _ = _mc(scenes, 100, 5000, 50, 11, 0, 1)
+    for segments in (0, 2, 50, 777, 5000):
+        got, over = _mc(scenes, 100, 5000, 50, 11, 0, segments)
+        assert not over.any()
+        for p, (g, r) in enumerate(zip(got, ref)):
+            np.testing.assert_array_equal(g, r, err_msg=f"segments {segments} pixel {p}")
 
 
 def test_pixel_and_run_streams_are_distinct():
@@ -84,11 +101,17 @@ def test_rejects_unsupported_arguments():
     plan = d.Plan(s, "f64", d.opts(tol=1e-10))
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     plan.bind(ws)
-    for runs, cycles, burn, lanes in ((0, 100, 0, 0), (4, 100, 100, 0), (4, 0, 0, 0), (4, 100, -1, 0),
-                                      (65536, 10, 0, 0), (4, 1 << 32, 0, 0), (1024, 65537, 1, 0),
-                                      (4, 100, 0, 3), (4, 100, 0, 128), (4, 100, 0, -1)):
+    for runs, cycles, burn, lanes, segs in ((0, 100, 0, 0, 0), (4, 100, 100, 0, 0), (4, 0, 0, 0, 0),
+                                            (4, 100, -1, 0, 0), (65536, 10, 0, 0, 0), (4, 1 << 32, 0, 0, 0),
+                                            (1024, 65537, 1, 0, 0), (4, 100, 0, 3, 0), (4, 100, 0, 128, 0),
+                                            (4, 100, 0, -1, 0), (4, 100, 0, 0, 101), (4, 100, 0, 0, -1)):
         with pytest.raises(d.DtmError):
-            plan.mc_histograms(runs, cycles, burn, 1, lanes)
+            plan.mc_histograms(runs, cycles, burn, 1, lanes, segments_per_run=segs)
+    # a scratch buffer shorter than the segment states
+    short = torch.empty(plan.mc_scratch_bytes(4, 100, 10) - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(d.DtmError) as e:
+        plan.mc_histograms(4, 100, 0, 1, 0, segments_per_run=10, scratch=short)
+    assert e.value.status == d.DTM_ENOSPACE
     plan.close()
 
 
@@ -100,7 +123,7 @@ def test_markov_model_approaches_monte_carlo_as_bins_grow():
     discretisation error of this scene at 2.8/N for N = 32 and below 2/N
     from N = 64 on; the bar here is 4/N.)"""
     base = dict(period=100.0, dead_time=75.0, center=30.0, sigma=2.0, signal=2.0, background=0.5)
-    got, _ = _mc(sc.scene(n_bins=1024, **base), 1024, 20000, 100, 77)
+    got, _ = _mc(sc.scene(n_bins=1024, **base), 1024, 20000, 100, 77, 0, 0)
     h = got[0].astype(np.float64)
     m = h.sum()
     errs = {}
