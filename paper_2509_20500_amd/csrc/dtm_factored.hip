@@ -536,7 +536,8 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
 
 // Empirical mixing steps: every start state e_s advanced on its own, one
 // thread per start state (each thread runs its own prefix scan over the n
-// bins); block y of a pixel owns states [y BT, (y + 1) BT).  X and Y are
+// bins); flat pixel-major grid, block y of a pixel owns states
+// [y BT, (y + 1) BT).  X and Y are
 // n x n, stored state-minor (X[k * n + s]) so that a wavefront reads
 // consecutive states.  The distance of each start state from pi does not
 // grow from one step to the next (P~ is stochastic), so the pixel mixes at
@@ -549,15 +550,16 @@ __global__ __launch_bounds__(BT) void k_mixing(const PixelMeta* __restrict__ met
                                                double* __restrict__ mix, const int64_t* __restrict__ mix_off,
                                                const double* __restrict__ scal,
                                                dtm_spectral_info* __restrict__ out, double eps,
-                                               int max_steps) {
+                                               int max_steps, int state_blocks) {
   __shared__ double red[BT / kWave];
-  const PixelMeta m = metas[blockIdx.x];
+  const int pix = static_cast<int>(blockIdx.x / state_blocks);
+  const PixelMeta m = metas[pix];
   const int n = m.n;
-  const int s0 = blockIdx.y * BT;
+  const int s0 = static_cast<int>(blockIdx.x % state_blocks) * BT;
   if (s0 >= n) return;
   const Vecs V = vecs(fact, vec_elems, m);
-  const double c = scal[blockIdx.x];
-  double* X = mix + mix_off[blockIdx.x];
+  const double c = scal[pix];
+  double* X = mix + mix_off[pix];
   double* Y = X + static_cast<int64_t>(n) * n;
   const int s = s0 + static_cast<int>(threadIdx.x);
   const bool mine = s < n;
@@ -603,25 +605,27 @@ __global__ __launch_bounds__(BT) void k_mixing(const PixelMeta* __restrict__ met
 // E): the state's distribution stays on chip, its bins [t E, t E + E) in
 // lane t's registers and in a padded LDS copy for the shifted reads, with
 // g, 1/S and pi of the pixel in registers; each wavefront stops at its own
-// first step within eps and merges it by atomicMax.  Block y of a pixel owns
-// states [4 y, 4 y + 4).  No n x n scratch is touched.
+// first step within eps and merges it by atomicMax.  Flat pixel-major grid
+// (so that each pixel's blocks are dealt to all XCDs): block y of a pixel
+// owns states [4 y, 4 y + 4).  No n x n scratch is touched.
 template <int E>
 __global__ __launch_bounds__(BT) void k_mixing_wave(const PixelMeta* __restrict__ metas,
                                                     const double* __restrict__ fact, int64_t vec_elems,
                                                     const double* __restrict__ scal,
                                                     dtm_spectral_info* __restrict__ out, double eps,
-                                                    int max_steps) {
+                                                    int max_steps, int state_blocks) {
   extern __shared__ double lds_x[];
-  const PixelMeta m = metas[blockIdx.x];
+  const int pix = static_cast<int>(blockIdx.x / state_blocks);
+  const PixelMeta m = metas[pix];
   const int n = m.n;
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int s = blockIdx.y * (BT / kWave) + wid;
+  const int s = static_cast<int>(blockIdx.x % state_blocks) * (BT / kWave) + wid;
   if (s >= n) return;  // whole wavefronts only; nothing below waits for another wavefront
   const double* base = fact + m.vec_off;
   const double* gv = base;
   const double* iv = base + vec_elems;
   const double* pv = base + 2 * vec_elems;
-  const double c = scal[blockIdx.x];
+  const double c = scal[pix];
   double* xs = lds_x + wid * wave::lds_doubles<E>();
   const int j0 = lane * E;
   double* xo = xs + wave::slot<E>(j0);
@@ -820,24 +824,27 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
   if (hipMemcpyAsync(mix_off, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice, st) !=
       hipSuccess)
     return DTM_EHIP;
+  if (static_cast<double>(plan->n_pixels) * ((plan->max_n + 3) / 4) >= 2147483647.0) return DTM_EINVAL;
   if (plan->max_n <= 1024) {
     // one wavefront per start state, four per block; E bins per lane
     const int E = plan->max_n <= 256 ? 4 : plan->max_n <= 512 ? 8 : 16;
-    const dim3 grid(plan->n_pixels, static_cast<unsigned>((plan->max_n + 3) / 4));
+    const int sb = (plan->max_n + 3) / 4;
+    const dim3 grid(static_cast<unsigned>(plan->n_pixels) * static_cast<unsigned>(sb));
     const size_t lds = sizeof(double) * 4 * kWave * (E + 1);
     if (E == 4)
       hipLaunchKernelGGL(fact::k_mixing_wave<4>, grid, dim3(fact::BT), lds, st, metas, fact, plan->vec_elems, scal,
-                         out_dev, mixing_eps, max_steps);
+                         out_dev, mixing_eps, max_steps, sb);
     else if (E == 8)
       hipLaunchKernelGGL(fact::k_mixing_wave<8>, grid, dim3(fact::BT), lds, st, metas, fact, plan->vec_elems, scal,
-                         out_dev, mixing_eps, max_steps);
+                         out_dev, mixing_eps, max_steps, sb);
     else
       hipLaunchKernelGGL(fact::k_mixing_wave<16>, grid, dim3(fact::BT), lds, st, metas, fact, plan->vec_elems,
-                         scal, out_dev, mixing_eps, max_steps);
+                         scal, out_dev, mixing_eps, max_steps, sb);
   } else {
-    const unsigned state_blocks = static_cast<unsigned>((plan->max_n + fact::BT - 1) / fact::BT);
-    hipLaunchKernelGGL(fact::k_mixing, dim3(plan->n_pixels, state_blocks), dim3(fact::BT), 0, st, metas, fact,
-                       plan->vec_elems, mixbuf, mix_off, scal, out_dev, mixing_eps, max_steps);
+    const int sb = (plan->max_n + fact::BT - 1) / fact::BT;
+    hipLaunchKernelGGL(fact::k_mixing, dim3(static_cast<unsigned>(plan->n_pixels) * static_cast<unsigned>(sb)),
+                       dim3(fact::BT), 0, st, metas, fact, plan->vec_elems, mixbuf, mix_off, scal, out_dev,
+                       mixing_eps, max_steps, sb);
   }
   if (hipGetLastError() != hipSuccess) return DTM_EHIP;
   hipLaunchKernelGGL(fact::k_mixing_final, dim3((plan->n_pixels + fact::BT - 1) / fact::BT), dim3(fact::BT), 0, st,
