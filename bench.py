@@ -536,9 +536,9 @@ def copy_calibration(nbytes=1 << 30, reps=10):
 
 def pattern_ceiling(n_chunks, chunk_bytes, passes, reps=3):
     """GB/s of the dense solver's access pattern without its arithmetic
-    (dtm_stream_probe): each workgroup writes its chunk once and reads it
-    back; the time for `passes` (fractional) reads is interpolated between
-    the whole numbers around it."""
+    (dtm_stream_probe): every chunk written once in one launch, then read
+    back in a second; the time for `passes` (fractional) reads is
+    interpolated between the whole numbers around it."""
     import math
 
     import torch
@@ -657,7 +657,7 @@ def warm_start_workload(args):
                    "pixels": plan.n_pixels, "epochs": args.epochs},
         "roofline": {"bound": "hbm", "achieved": alg_w / (ms_w * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": alg_w / (ms_w * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_solve_fused", "alg_bytes_per_launch": alg_w},
+                     "kernel": "k_solve_build + k_solve_sweeps", "alg_bytes_per_launch": alg_w},
         "uniform_start": {"pixels_per_s": plan.n_pixels / (ms_u * 1e-3), "ms_per_step": ms_u,
                           "mean_sweeps": float(iu["iterations"].mean())},
         "warm_start": {"pixels_per_s": plan.n_pixels / (ms_w * 1e-3), "ms_per_step": ms_w,
@@ -829,9 +829,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (measured_traffic("k_solve_fused", f"batched_uniform_n1024_{args.dtype}")
+            "traffic": (measured_traffic("k_solve_build+k_solve_sweeps", f"batched_uniform_n1024_{args.dtype}")
                         if not uneven and plan.n_pixels == 4096 and not graph and not tiles else None),
-            "kernel": "k_solve_fused" if not uneven else "k_solve_fused + k_band_sweep",
+            "kernel": ("k_solve_build + k_solve_sweeps" if not uneven
+                       else "k_solve_build + k_solve_sweeps + k_band_sweep"),
             "alg_bytes_per_launch": alg_bytes,
         },
         "iterations": {"mean": float(info["iterations"].mean()), "max": int(info["iterations"].max()),

@@ -356,10 +356,11 @@ int dtm_mc_histograms(const dtm_plan* plan, int32_t runs_per_pixel, int64_t cycl
                       void* scratch_dev, size_t scratch_bytes, dtm_stream_t stream);
 
 /* Calibration probe, not part of the method: the dense solver's memory
- * access pattern without its arithmetic.  Each of n_chunks workgroups writes
- * its own chunk_bytes of buf_dev (nontemporal stores), then reads it back
- * `reads` times (nontemporal loads), as the fused kernel writes one pixel's
- * matrix and sweeps it.  buf_dev holds n_chunks * chunk_bytes bytes (caller
+ * access pattern without its arithmetic.  A first launch of n_chunks
+ * workgroups writes every chunk_bytes chunk of buf_dev (nontemporal stores),
+ * a second one reads each chunk back `reads` times (nontemporal loads), as
+ * the batched solve writes every matrix in its build launch and then sweeps
+ * them in its sweep launch.  buf_dev holds n_chunks * chunk_bytes bytes (caller
  * owned, contents overwritten); sink_dev is one float that is never written
  * for these values.  chunk_bytes a positive multiple of 16, n_chunks >= 1,
  * reads >= 0, else DTM_EINVAL.  Launch only. */

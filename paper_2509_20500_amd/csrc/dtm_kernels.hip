@@ -140,11 +140,11 @@ __global__ __launch_bounds__(BT) void k_shift(const PixelMeta* metas, PixelMeta 
 }
 
 // ============================================================================
-// Batched fused solver: one block per pixel does the row sums, the shifted
-// build fused with the first power-iteration sweep, the remaining sweeps,
-// the float64 check sweep and the stop rule.  The bin tables g_j and
-// c = exp(-Lambda) come from k_tables (run just before, so that its erf code
-// does not set this kernel's register budget).  Thread t owns columns
+// Batched solver for pixels that fit one block: per pixel, the shifted build
+// with the first power-iteration sweep taken on the way, the remaining
+// sweeps, the float64 check sweep and the stop rule.  The bin tables g_j,
+// 1/S_k and c = exp(-Lambda) come from k_tables (run just before, so that its
+// erf code does not set these kernels' register budgets).  Thread t owns columns
 // (t + BT q) * VN .. + VN - 1 for q < CPT in every row: each row is one
 // coalesced pass of the block and x P~ needs no cross-thread reduction.
 // ============================================================================
@@ -225,42 +225,22 @@ __device__ inline void sweep_rows(const T* __restrict__ mat, int64_t ld, int n, 
   }
 }
 
-template <typename T, int BT, int CPT, int U>
-__global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict__ metas,
-                                                    const T* __restrict__ colf,
-                                                    const T* __restrict__ invs_g,
-                                                    const double* __restrict__ scal,
-                                                    T* __restrict__ pool,
-                                                    const T* __restrict__ x0_packed,
-                                                    T* __restrict__ pi_packed,
-                                                    dtm_solve_info* __restrict__ infos,
-                                                    const int32_t* __restrict__ sel,
-                                                    KOpts o, int lds_ld) {
-  using V = typename Vec<T>::type;
-  constexpr int VN = Vec<T>::n;
-  constexpr int UE = (U * CPT <= 8) ? U : (8 / CPT > 0 ? 8 / CPT : 1);
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* g = reinterpret_cast<T*>(smem);
-  T* xs = g + lds_ld;
-  T* invs = xs + lds_ld;
-  double* red = reinterpret_cast<double*>(invs + lds_ld);
+// The dense solve of a batch runs in two launches over the same pixels (one
+// block each, same order): k_solve_build writes every matrix while it takes
+// the first sweep, then k_solve_sweeps runs the remaining sweeps, which only
+// read.  Measured on this part, HBM gives a stream of writes followed by a
+// stream of reads about 1.3 times the bandwidth it gives the same traffic
+// mixed (each block writing its matrix and then reading it back while others
+// write theirs).  The first sweep's float64 sums y = x0 P~ pass between the
+// launches through the workspace; the start vector is derived again, the
+// same way, so the iterates are those of one fused kernel, bit for bit.
 
-  const int pq = sel[blockIdx.x];
-  const PixelMeta m = metas[pq];
-  const int n = m.n;
-  const int64_t ld = m.ld;
-  const int tid = threadIdx.x;
-  T* mat = pool + m.mat_off;
-  const T c = static_cast<T>(scal[pq]);
-
-  // ---- a1/a2 tables into LDS: g (zero-padded to ld) and 1/S_k -------------
-  for (int j = tid; j < m.ld; j += BT) g[j] = colf[m.vec_off + j];
-  for (int j = tid; j < n; j += BT) invs[j] = invs_g[m.vec_off + j];
-  __syncthreads();
-
-  // ---- start vector: caller's (validated) or uniform ---------------------
-  StopState st;
-  stop_init(st, 0, 0);
+// Start vector into xs (LDS): the caller's, validated and normalised, or the
+// uniform one; records the warm start in st.  Ends with a block barrier.
+template <typename T, int BT>
+__device__ inline void start_vector(const PixelMeta& m, const T* __restrict__ x0_packed, T* xs, StopState& st,
+                                    double* red) {
+  const int n = m.n, tid = threadIdx.x;
   if (x0_packed) {
     double sum = 0.0, bad = 0.0;
     for (int j = tid; j < n; j += BT) {
@@ -281,31 +261,54 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
     for (int j = tid; j < n; j += BT) xs[j] = static_cast<T>(1.0 / n);
   }
   __syncthreads();
+}
 
-  // This thread's columns (clamped to 0 past n) and their g values.
-  int jc[CPT];
+// Phase 1: tables into LDS, then every row written once (a2 + a3: row i from
+// base row k = (i + l) mod n) while x0 P~ accumulates in compensated sums;
+// the sums go to y1 (float64, the pixel's ld slots at vec_off).
+template <typename T, int BT, int CPT>
+__global__ __launch_bounds__(BT) void k_solve_build(const PixelMeta* __restrict__ metas,
+                                                    const T* __restrict__ colf,
+                                                    const T* __restrict__ invs_g,
+                                                    const double* __restrict__ scal,
+                                                    T* __restrict__ pool,
+                                                    const T* __restrict__ x0_packed,
+                                                    double* __restrict__ y1,
+                                                    const int32_t* __restrict__ sel, int lds_ld) {
+  using V = typename Vec<T>::type;
+  constexpr int VN = Vec<T>::n;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* g = reinterpret_cast<T*>(smem);
+  T* xs = g + lds_ld;
+  T* invs = xs + lds_ld;
+  double* red = reinterpret_cast<double*>(invs + lds_ld);
+
+  const int pq = sel[blockIdx.x];
+  const PixelMeta m = metas[pq];
+  const int n = m.n;
+  const int64_t ld = m.ld;
+  const int tid = threadIdx.x;
+  T* mat = pool + m.mat_off;
+  const T c = static_cast<T>(scal[pq]);
+
+  for (int j = tid; j < m.ld; j += BT) g[j] = colf[m.vec_off + j];
+  for (int j = tid; j < n; j += BT) invs[j] = invs_g[m.vec_off + j];
+  __syncthreads();
+  StopState st;
+  stop_init(st, 0, 0);
+  start_vector<T, BT>(m, x0_packed, xs, st, red);
+
   T gr[CPT][VN];
+  T acc[CPT][VN], cmp[CPT][VN];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int j0 = (tid + BT * q) * VN;
-    jc[q] = j0 < n ? j0 : 0;
-#pragma unroll
-    for (int e = 0; e < VN; ++e) gr[q][e] = (j0 < n) ? g[j0 + e] : T(0);
-  }
-
-  T acc[CPT][VN], cmp[CPT][VN];
-  double accd[CPT][VN], dd0[CPT][VN];
-  double dprev[CPT][VN];  // previous difference vector on this thread's columns
-#pragma unroll
-  for (int q = 0; q < CPT; ++q)
 #pragma unroll
     for (int e = 0; e < VN; ++e) {
-      dprev[q][e] = 0.0;
+      gr[q][e] = (j0 < n) ? g[j0 + e] : T(0);
       acc[q][e] = cmp[q][e] = T(0);
     }
-
-  // ---- a2+a3 fused with the first sweep: write row i from base row
-  //      k = (i + l) mod n and accumulate x_i P~[i, :] ----------------------
+  }
   for (int i = 0; i < n; ++i) {
     int k = i + m.l;
     if (k >= n) k -= n;
@@ -324,6 +327,63 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
       if (j0 < n) __builtin_nontemporal_store(v, reinterpret_cast<V*>(row + j0));
     }
   }
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int j0 = (tid + BT * q) * VN;
+#pragma unroll
+    for (int e = 0; e < VN; ++e)
+      if (j0 + e < n) y1[m.vec_off + j0 + e] = static_cast<double>(acc[q][e]) - static_cast<double>(cmp[q][e]);
+  }
+}
+
+// Phase 2: from y1, the stop rule and the remaining sweeps (a4, with the
+// float64 check sweep of a5 when due), reading each matrix as many times as
+// its pixel needs.
+template <typename T, int BT, int CPT, int U>
+__global__ __launch_bounds__(BT) void k_solve_sweeps(const PixelMeta* __restrict__ metas,
+                                                     const T* __restrict__ pool,
+                                                     const T* __restrict__ x0_packed,
+                                                     const double* __restrict__ y1,
+                                                     T* __restrict__ pi_packed,
+                                                     dtm_solve_info* __restrict__ infos,
+                                                     const int32_t* __restrict__ sel,
+                                                     KOpts o, int lds_ld) {
+  constexpr int VN = Vec<T>::n;
+  constexpr int UE = (U * CPT <= 8) ? U : (8 / CPT > 0 ? 8 / CPT : 1);
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* xs = reinterpret_cast<T*>(smem);
+  double* red = reinterpret_cast<double*>(xs + lds_ld);
+
+  const int pq = sel[blockIdx.x];
+  const PixelMeta m = metas[pq];
+  const int n = m.n;
+  const int64_t ld = m.ld;
+  const int tid = threadIdx.x;
+  const T* mat = pool + m.mat_off;
+
+  StopState st;
+  stop_init(st, 0, 0);
+  start_vector<T, BT>(m, x0_packed, xs, st, red);
+
+  // This thread's columns (clamped to 0 past n: those sums are never used).
+  int jc[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int j0 = (tid + BT * q) * VN;
+    jc[q] = j0 < n ? j0 : 0;
+  }
+
+  T acc[CPT][VN], cmp[CPT][VN];
+  double accd[CPT][VN], dd0[CPT][VN];
+  double dprev[CPT][VN];  // previous difference vector on this thread's columns
+#pragma unroll
+  for (int q = 0; q < CPT; ++q)
+#pragma unroll
+    for (int e = 0; e < VN; ++e) {
+      dprev[q][e] = 0.0;
+      acc[q][e] = cmp[q][e] = T(0);
+    }
+  bool first = true;        // y is the first sweep's, from phase 1
   bool have_check = false;  // the accumulators hold a float64 check sweep
 
   for (;;) {
@@ -336,14 +396,17 @@ __global__ __launch_bounds__(BT) void k_solve_fused(const PixelMeta* __restrict_
       const int j0 = (tid + BT * q) * VN;
 #pragma unroll
       for (int e = 0; e < VN; ++e) {
-        y[q][e] = have_check ? accd[q][e]
-                             : static_cast<double>(acc[q][e]) - static_cast<double>(cmp[q][e]);
+        if (first) y[q][e] = (j0 + e < n) ? y1[m.vec_off + j0 + e] : 0.0;
+        else
+          y[q][e] = have_check ? accd[q][e]
+                               : static_cast<double>(acc[q][e]) - static_cast<double>(cmp[q][e]);
         if (j0 + e < n) {
           sy += y[q][e];
           rs += fabs(y[q][e] - static_cast<double>(xs[j0 + e]));
         }
       }
     }
+    first = false;
     block_sum2<BT>(sy, rs, red);
     const double inv = 1.0 / sy;
     T xn[CPT][VN];
@@ -1017,23 +1080,35 @@ template <typename T, int BT, int CPT>
 int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, const int32_t* sel,
                      int count, const T* colf, const double* scal, T* pool, const T* x0, T* pi,
                      dtm_solve_info* infos, int lds_ld, hipStream_t st) {
-  const size_t lds = 3 * sizeof(T) * static_cast<size_t>(lds_ld) + 3 * BT / kWave * sizeof(double);
-  void (*kern)(const PixelMeta*, const T*, const T*, const double*, T*, const T*, T*,
-               dtm_solve_info*, const int32_t*, KOpts, int) = nullptr;
+  const size_t red = 3 * BT / kWave * sizeof(double);
+  const size_t lds_build = 3 * sizeof(T) * static_cast<size_t>(lds_ld) + red;
+  const size_t lds_sweeps = sizeof(T) * static_cast<size_t>(lds_ld) + red;
+  auto build = k_solve_build<T, BT, CPT>;
+  void (*sweeps)(const PixelMeta*, const T*, const T*, const double*, T*, dtm_solve_info*, const int32_t*,
+                 KOpts, int) = nullptr;
   switch (unroll) {
-    case 2: kern = k_solve_fused<T, BT, CPT, 2>; break;
-    case 4: kern = k_solve_fused<T, BT, CPT, 4>; break;
-    default: kern = k_solve_fused<T, BT, CPT, 8>; break;
+    case 2: sweeps = k_solve_sweeps<T, BT, CPT, 2>; break;
+    case 4: sweeps = k_solve_sweeps<T, BT, CPT, 4>; break;
+    default: sweeps = k_solve_sweeps<T, BT, CPT, 8>; break;
   }
-  if (lds > 64 * 1024) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            static_cast<int>(lds)) != hipSuccess)
-      return DTM_EHIP;
-  }
-  const T* invs = reinterpret_cast<const T*>(static_cast<char*>(plan->ws) + plan->off_invs);
-  hipLaunchKernelGGL(kern, dim3(count), dim3(BT), lds, st, metas, colf, invs, scal, pool, x0, pi,
-                     infos, sel, plan->kopts, lds_ld);
+  if (lds_build > 64 * 1024 &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(build), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          static_cast<int>(lds_build)) != hipSuccess)
+    return DTM_EHIP;
+  if (lds_sweeps > 64 * 1024 &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(sweeps), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          static_cast<int>(lds_sweeps)) != hipSuccess)
+    return DTM_EHIP;
+  char* w = static_cast<char*>(plan->ws);
+  const T* invs = reinterpret_cast<const T*>(w + plan->off_invs);
+  // the first sweep's sums: the float64 slots the banded path uses for its
+  // previous differences (disjoint pixels) and the tables kernel as scratch
+  // (finished before this launch)
+  double* y1 = reinterpret_cast<double*>(w + plan->off_dprev);
+  hipLaunchKernelGGL(build, dim3(count), dim3(BT), lds_build, st, metas, colf, invs, scal, pool, x0, y1, sel,
+                     lds_ld);
+  hipLaunchKernelGGL(sweeps, dim3(count), dim3(BT), lds_sweeps, st, metas, pool, x0, y1, pi, infos, sel,
+                     plan->kopts, lds_ld);
   return last_launch();
 }
 
@@ -1077,8 +1152,8 @@ int launch_refine(const dtm_plan* plan, const PixelMeta* metas, T* pi, dtm_solve
   return last_launch();
 }
 
-// Banded path: k_band_init (launched by the caller before the fused kernel
-// is forked off, so that it does not queue behind the fused kernel's
+// Banded path: k_band_init (launched by the caller before the one-block
+// solver is forked off, so that it does not queue behind that solver's
 // long-running blocks), then band_sweeps x (sweep over all items, combine).
 template <typename T>
 int launch_band_init(const dtm_plan* plan, const PixelMeta* metas, const T* x0, hipStream_t st) {
@@ -1149,7 +1224,7 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
   if (rc) return rc;
   const int nsmall = static_cast<int>(plan->small_sel.size());
   const int nbig = static_cast<int>(plan->big_sel.size());
-  // With both kinds of pixels, the fused kernel runs on the plan's second
+  // With both kinds of pixels, the one-block solver runs on the plan's second
   // stream alongside the banded launches, which leave most of the GPU idle
   // while a sweep's last bands and the combines finish.
   const bool fork = nsmall > 0 && nbig > 0;

@@ -1,7 +1,8 @@
 // Bandwidth of the dense solver's memory access pattern without its
-// arithmetic, for the benchmark's calibration: every block writes one chunk
-// (as the fused kernel writes one pixel's matrix while it builds it) and then
-// streams it back `reads` times with nontemporal loads (the sweeps).
+// arithmetic, for the benchmark's calibration: one launch in which every
+// block writes its chunk (as the build launch writes one pixel's matrix),
+// then one in which every block streams its chunk back `reads` times with
+// nontemporal loads (the sweep launch).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -15,12 +16,15 @@ constexpr int BT = 256;
 constexpr int UNROLL = 8;
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(BT) void k_stream_probe(f4* __restrict__ buf, size_t chunk4, int reads,
-                                                     float* __restrict__ sink) {
+__global__ __launch_bounds__(BT) void k_probe_write(f4* __restrict__ buf, size_t chunk4) {
   f4* p = buf + static_cast<size_t>(blockIdx.x) * chunk4;
   for (size_t i = threadIdx.x; i < chunk4; i += BT)
     __builtin_nontemporal_store(f4{1.0f, 2.0f, 3.0f, static_cast<float>(i)}, p + i);
-  __syncthreads();
+}
+
+__global__ __launch_bounds__(BT) void k_probe_read(const f4* __restrict__ buf, size_t chunk4, int reads,
+                                                   float* __restrict__ sink) {
+  const f4* p = buf + static_cast<size_t>(blockIdx.x) * chunk4;
   float s = 0.0f;
   for (int r = 0; r < reads; ++r) {
     size_t i = threadIdx.x;
@@ -46,8 +50,10 @@ extern "C" int dtm_stream_probe(void* buf_dev, size_t chunk_bytes, int32_t n_chu
                                 float* sink_dev, dtm_stream_t stream) {
   if (!buf_dev || !sink_dev || n_chunks < 1 || reads < 0 || chunk_bytes < 16 || chunk_bytes % 16 != 0)
     return DTM_EINVAL;
-  hipLaunchKernelGGL(dtm::probe::k_stream_probe, dim3(n_chunks), dim3(dtm::probe::BT), 0,
-                     static_cast<hipStream_t>(stream), static_cast<dtm::probe::f4*>(buf_dev), chunk_bytes / 16, reads,
-                     sink_dev);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  dtm::probe::f4* buf = static_cast<dtm::probe::f4*>(buf_dev);
+  hipLaunchKernelGGL(dtm::probe::k_probe_write, dim3(n_chunks), dim3(dtm::probe::BT), 0, st, buf, chunk_bytes / 16);
+  hipLaunchKernelGGL(dtm::probe::k_probe_read, dim3(n_chunks), dim3(dtm::probe::BT), 0, st, buf, chunk_bytes / 16,
+                     reads, sink_dev);
   return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP;
 }
