@@ -692,9 +692,9 @@ def main():
     ap.add_argument("--single-sample", type=int, default=256,
                     help="pixels timed on the plain single-pixel GPU path (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--threads", type=int, default=0, help="fused block size (0 = default)")
+    ap.add_argument("--threads", type=int, default=0, help="one-block solver block size (0 = default)")
     ap.add_argument("--unroll", type=int, default=0, help="rows in flight per thread (0 = default)")
-    ap.add_argument("--fused-max-bins", type=int, default=0, help="largest n of the fused kernel (0 = default)")
+    ap.add_argument("--fused-max-bins", type=int, default=0, help="largest n of the one-block solver (0 = default)")
     ap.add_argument("--band-rows", type=int, default=0, help="rows per banded work item (0 = default)")
     ap.add_argument("--band-cpt", type=int, default=0, help="column vectors per thread, banded (0 = default)")
     ap.add_argument("--calibrate", action="store_true",
@@ -766,7 +766,7 @@ def main():
     n = scenes["n_bins"].astype(np.float64)
     es = 4 if args.dtype == "f32" else 8
     # algorithmic bytes: each matrix written once; every sweep after the
-    # first (which is fused with the build) reads it once
+    # first (taken while the matrix is built) reads it once
     alg_bytes = float(np.sum(es * n * n * info["iterations"]))
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     value = plan.n_pixels / (ms_step * 1e-3)

@@ -214,7 +214,7 @@ int dtm_stationary_pdf(const void* P_dev, int32_t n, int64_t ld, dtm_dtype dt,
 /* Launch shape of the batched kernels.  Zero fields take the built-in or
  * autotuned defaults. */
 typedef struct dtm_tile_config {
-  int32_t fused_threads;   /* threads per workgroup of the fused kernel: 256 or 512     */
+  int32_t fused_threads;   /* threads per workgroup of the one-block solver: 256 or 512 */
   int32_t fused_unroll;    /* rows in flight per thread in a sweep: 2, 4 or 8           */
   int32_t fused_max_bins;  /* pixels with n_b above this take the banded path (>= 2)    */
   int32_t band_rows;       /* rows per workgroup in the banded sweep, multiple of 16,
@@ -257,7 +257,10 @@ int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes,
                   dtm_stream_t stream);
 
 /* Solves every pixel: bin tables, transition matrix (shift fused), power
- * iteration with the plan's stop rule, float64 residual check.  Writes pi
+ * iteration with the plan's stop rule, float64 residual check.  Pixels up to
+ * fused_max_bins take one workgroup each in two launches: every matrix is
+ * written (with the first sweep taken on the way), then the remaining sweeps
+ * read them; larger pixels take the banded launches.  Writes pi
  * packed by pi_offsets (dtype of the plan) and one dtm_solve_info per pixel
  * to infos_dev (device memory, plan order = input order).  x0_packed_dev
  * (packed like pi, dtype of the plan) seeds the iteration; NULL = uniform.

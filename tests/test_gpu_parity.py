@@ -309,7 +309,7 @@ def test_float32_paper_grid_with_refinement():
 def test_banded_path_ragged(dt):
     """Pixels above fused_max_bins take the banded multi-block path: ragged
     row bands (64 rows) and, past 4096 (float32) or 2048 (float64) columns,
-    several column blocks; mixed with fused pixels in one plan."""
+    several column blocks; mixed with one-block pixels in one plan."""
     d = lib()
     rng = np.random.default_rng(81)
     ns = [300, 1000, 2500, 257, 64, 5000 if dt == "f32" else 3000, 777]
@@ -338,8 +338,8 @@ def test_banded_sweep_cap_is_soft():
     assert np.all(np.isfinite(pi)) and abs(pi.sum() - 1) < 1e-5
 
 
-def test_banded_matches_fused_bitwise_pattern():
-    """The banded and fused paths solve the same pixels to the same
+def test_banded_matches_one_block_path():
+    """The banded and one-block paths solve the same pixels to the same
     tolerance (they differ only in summation order)."""
     d = lib()
     scenes = sc.batched_uniform(24, seed=91)
