@@ -1075,9 +1075,10 @@ int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_e
   return DTM_OK;
 }
 
-// Fused batched solve: kernel instance by (dtype, block, columns per thread).
+// One-block batched solve, kernel instance by (dtype, block, columns per
+// thread); phase 0 launches the build, phase 1 the sweeps.
 template <typename T, int BT, int CPT>
-int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, const int32_t* sel,
+int launch_fused_cpt(const dtm_plan* plan, int phase, int unroll, const PixelMeta* metas, const int32_t* sel,
                      int count, const T* colf, const double* scal, T* pool, const T* x0, T* pi,
                      dtm_solve_info* infos, int lds_ld, hipStream_t st) {
   const size_t red = 3 * BT / kWave * sizeof(double);
@@ -1105,27 +1106,29 @@ int launch_fused_cpt(const dtm_plan* plan, int unroll, const PixelMeta* metas, c
   // previous differences (disjoint pixels) and the tables kernel as scratch
   // (finished before this launch)
   double* y1 = reinterpret_cast<double*>(w + plan->off_dprev);
-  hipLaunchKernelGGL(build, dim3(count), dim3(BT), lds_build, st, metas, colf, invs, scal, pool, x0, y1, sel,
-                     lds_ld);
-  hipLaunchKernelGGL(sweeps, dim3(count), dim3(BT), lds_sweeps, st, metas, pool, x0, y1, pi, infos, sel,
-                     plan->kopts, lds_ld);
+  if (phase == 0)
+    hipLaunchKernelGGL(build, dim3(count), dim3(BT), lds_build, st, metas, colf, invs, scal, pool, x0, y1, sel,
+                       lds_ld);
+  else
+    hipLaunchKernelGGL(sweeps, dim3(count), dim3(BT), lds_sweeps, st, metas, pool, x0, y1, pi, infos, sel,
+                       plan->kopts, lds_ld);
   return last_launch();
 }
 
 template <typename T, int BT>
-int launch_fused_bt(const dtm_plan* plan, int cpt, const PixelMeta* metas, const int32_t* sel,
+int launch_fused_bt(const dtm_plan* plan, int phase, int cpt, const PixelMeta* metas, const int32_t* sel,
                     int count, const T* colf, const double* scal, T* pool, const T* x0, T* pi,
                     dtm_solve_info* infos, int lds_ld, hipStream_t st) {
   const int u = plan->tiles.fused_unroll;
   switch (cpt) {
     case 1:
-      return launch_fused_cpt<T, BT, 1>(plan, u, metas, sel, count, colf, scal, pool, x0, pi, infos,
+      return launch_fused_cpt<T, BT, 1>(plan, phase, u, metas, sel, count, colf, scal, pool, x0, pi, infos,
                                         lds_ld, st);
     case 2:
-      return launch_fused_cpt<T, BT, 2>(plan, u, metas, sel, count, colf, scal, pool, x0, pi, infos,
+      return launch_fused_cpt<T, BT, 2>(plan, phase, u, metas, sel, count, colf, scal, pool, x0, pi, infos,
                                         lds_ld, st);
     case 4:
-      return launch_fused_cpt<T, BT, 4>(plan, u, metas, sel, count, colf, scal, pool, x0, pi, infos,
+      return launch_fused_cpt<T, BT, 4>(plan, phase, u, metas, sel, count, colf, scal, pool, x0, pi, infos,
                                         lds_ld, st);
     default:
       return DTM_ENOTSUP;
@@ -1169,9 +1172,11 @@ int launch_band_init(const dtm_plan* plan, const PixelMeta* metas, const T* x0, 
   return last_launch();
 }
 
+// Sweeps [t0, t1) of the banded path (sweep 0 builds the matrices).
 template <typename T>
-int launch_banded(const dtm_plan* plan, const PixelMeta* metas, const T* colf, const double* scal,
-                  const T* invs, T* pool, const T* x0, T* pi, dtm_solve_info* infos, hipStream_t st) {
+int launch_banded(const dtm_plan* plan, int t0, int t1, const PixelMeta* metas, const T* colf,
+                  const double* scal, const T* invs, T* pool, const T* x0, T* pi, dtm_solve_info* infos,
+                  hipStream_t st) {
   constexpr int BT = 256;
   char* w = static_cast<char*>(plan->ws);
   const int32_t* big = reinterpret_cast<const int32_t*>(w + plan->off_big);
@@ -1192,7 +1197,7 @@ int launch_banded(const dtm_plan* plan, const PixelMeta* metas, const T* colf, c
     case 2: sweep = u == 2 ? k_band_sweep<T, BT, 2, 2> : u == 4 ? k_band_sweep<T, BT, 2, 4> : k_band_sweep<T, BT, 2, 8>; break;
     default: sweep = u == 2 ? k_band_sweep<T, BT, 4, 2> : u == 4 ? k_band_sweep<T, BT, 4, 4> : k_band_sweep<T, BT, 4, 8>; break;
   }
-  for (int t = 0; t < plan->tiles.band_sweeps; ++t) {
+  for (int t = t0; t < t1; ++t) {
     hipLaunchKernelGGL(sweep, dim3(nitems), dim3(BT), lds, st, metas, items, colf, scal, invs, pool,
                        xbuf, states, part, plan->tiles.band_rows, t == 0 ? 1 : 0);
     hipLaunchKernelGGL((k_band_combine<T, BT>), dim3(nbig), dim3(BT), 0, st, metas, big, part, xbuf,
@@ -1238,28 +1243,53 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
     if (hipEventRecord(static_cast<hipEvent_t>(plan->ev_fork), st) != hipSuccess) return DTM_EHIP;
     if (hipStreamWaitEvent(fst, static_cast<hipEvent_t>(plan->ev_fork), 0) != hipSuccess) return DTM_EHIP;
   }
+  // columns per thread covering the largest one-block pixel; at most 4
+  // vectors of columns per thread (more would spill), so wide pixels take
+  // 512 threads
+  int bt = plan->tiles.fused_threads, cpt = 1;
   if (nsmall > 0) {
-    // columns per thread covering the largest fused pixel; at most 4 vectors
-    // of columns per thread (more would spill), so wide pixels take 512 threads
-    int bt = plan->tiles.fused_threads;
-    int cpt = (plan->max_ld_small + bt * VN - 1) / (bt * VN);
+    cpt = (plan->max_ld_small + bt * VN - 1) / (bt * VN);
     if (cpt > 4 && bt == 256) {
       bt = 512;
       cpt = (plan->max_ld_small + bt * VN - 1) / (bt * VN);
     }
     cpt = cpt <= 1 ? 1 : cpt <= 2 ? 2 : 4;
     if (cpt * bt * VN < plan->max_ld_small) return DTM_ENOTSUP;
-    const int lds_ld = plan->max_ld_small;
-    if (bt == 512)
-      rc = launch_fused_bt<T, 512>(plan, cpt, metas, small, nsmall, colf, scal, pool, x0t, pit, infos,
-                                   lds_ld, fst);
-    else
-      rc = launch_fused_bt<T, 256>(plan, cpt, metas, small, nsmall, colf, scal, pool, x0t, pit, infos,
-                                   lds_ld, fst);
+  }
+  const int lds_ld = plan->max_ld_small;
+  const auto one_block = [&](int phase) {
+    return bt == 512 ? launch_fused_bt<T, 512>(plan, phase, cpt, metas, small, nsmall, colf, scal, pool, x0t, pit,
+                                               infos, lds_ld, fst)
+                     : launch_fused_bt<T, 256>(plan, phase, cpt, metas, small, nsmall, colf, scal, pool, x0t, pit,
+                                               infos, lds_ld, fst);
+  };
+  // Every matrix is written before any is swept (HBM serves a stream of
+  // writes and then a stream of reads better than the two mixed): the
+  // one-block builds and the banded first sweep (which builds), then the
+  // one-block sweeps and the remaining banded sweeps; with both kinds of
+  // pixels each stream waits for the other's builds before it sweeps.
+  if (nsmall > 0) {
+    rc = one_block(0);
     if (rc) return rc;
   }
   if (nbig > 0) {
-    rc = launch_banded<T>(plan, metas, colf, scal, invs, pool, x0t, pit, infos, st);
+    rc = launch_banded<T>(plan, 0, std::min(1, plan->tiles.band_sweeps), metas, colf, scal, invs, pool, x0t, pit,
+                          infos, st);
+    if (rc) return rc;
+  }
+  if (fork) {
+    hipEvent_t small_built = static_cast<hipEvent_t>(plan->ev_join);
+    hipEvent_t big_built = static_cast<hipEvent_t>(plan->ev_fork);
+    if (hipEventRecord(small_built, fst) != hipSuccess || hipEventRecord(big_built, st) != hipSuccess ||
+        hipStreamWaitEvent(fst, big_built, 0) != hipSuccess || hipStreamWaitEvent(st, small_built, 0) != hipSuccess)
+      return DTM_EHIP;
+  }
+  if (nsmall > 0) {
+    rc = one_block(1);
+    if (rc) return rc;
+  }
+  if (nbig > 0) {
+    rc = launch_banded<T>(plan, 1, plan->tiles.band_sweeps, metas, colf, scal, invs, pool, x0t, pit, infos, st);
     if (rc) return rc;
   }
   if (fork) {
