@@ -404,17 +404,38 @@ __global__ __launch_bounds__(BT) void k_solve_factored_wave(const PixelMeta* __r
 
 // Deflated operator A v = v P~ - (v . 1) pi (removes the Perron pair: left
 // eigenvectors of the other eigenvalues are orthogonal to the right Perron
-// vector 1).  out may alias V.u.
-__device__ void deflated(const PixelMeta& m, const Vecs& V, double c, const double* v, double* out,
+// vector 1), given s = v . 1.  out may alias V.u.
+__device__ void deflated(const PixelMeta& m, const Vecs& V, double c, const double* v, double s, double* out,
                          double* red) {
   int j0, j1;
   chunk_of(m.n, j0, j1);
-  double s = 0.0;
-  for (int j = j0; j < j1; ++j) s += v[j];
-  s = block_sum<BT>(s, red);
   apply(m.n, m.l, m.frac, v, V.g, V.invs, c, V.u, out, red);
-  for (int j = j0; j < j1; ++j) out[j] -= s * V.x[j];
+  if (s != 0.0)
+    for (int j = j0; j < j1; ++j) out[j] -= s * V.x[j];
   __syncthreads();
+}
+
+// Sums of N values over the block (every thread gets all of them), one
+// barrier round for all; red holds N * BT / 64 doubles.
+template <int N>
+__device__ inline void block_sum_n(double (&v)[N], double* red) {
+  constexpr int NW = BT / kWave;
+  const int w = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = wave_sum(v[q]);
+  __syncthreads();
+  if ((threadIdx.x % kWave) == 0) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) red[q * NW + w] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) t += red[q * NW + i];
+    v[q] = t;
+  }
 }
 
 // IN_LDS: the eight vectors live in LDS (8 n doubles, n <= kLdsMaxN); g, 1/S
@@ -425,7 +446,7 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
                                                  double* __restrict__ scal_out,
                                                  dtm_spectral_info* __restrict__ out, KOpts o,
                                                  int max_iter) {
-  __shared__ double red[3 * BT / kWave];
+  __shared__ double red[8 * BT / kWave];
   extern __shared__ double lds_vec[];
   const PixelMeta m = metas[blockIdx.x];
   const int n = m.n;
@@ -446,73 +467,85 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
   power<double>(m, V, c, static_cast<const double*>(nullptr), o, red);  // pi -> V.x
   int j0, j1;
   chunk_of(n, j0, j1);
-  // start: a fixed non-symmetric pattern, deflated
+  // start: a fixed non-symmetric pattern, deflated and normalised
   for (int j = j0; j < j1; ++j) V.v2[j] = 1.0 + 0.5 * sin(0.7 * j + 0.3) + ((j * 7919) % 13) * 0.01;
-  __syncthreads();
-  deflated(m, V, c, V.v2, V.v0, red);
+  double s2 = 0.0;
+  for (int j = j0; j < j1; ++j) s2 += V.v2[j];
+  s2 = block_sum<BT>(s2, red);
+  deflated(m, V, c, V.v2, s2, V.v0, red);
+  double nv = 0.0, s0 = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    nv += V.v0[j] * V.v0[j];
+    s0 += V.v0[j];
+  }
+  block_sum2<BT>(nv, s0, red);
   double re = 0.0, im = 0.0, fit = 1.0, prev_re = 2.0, prev_im = 2.0;
   int it = 0;
-  for (; it < max_iter; ++it) {
-    // normalise v0
-    double nv = 0.0;
-    for (int j = j0; j < j1; ++j) nv += V.v0[j] * V.v0[j];
-    nv = block_sum<BT>(nv, red);
-    if (!(nv > 0.0)) {  // the deflated operator is nil on the start vector
-      re = im = 0.0;
-      fit = 0.0;
-      break;
-    }
+  if (!(nv > 0.0)) {  // the deflated operator is nil on the start vector
+    re = im = 0.0;
+    fit = 0.0;
+  } else {
     const double sc = 1.0 / sqrt(nv);
     for (int j = j0; j < j1; ++j) V.v0[j] *= sc;
+    s0 *= sc;
     __syncthreads();
-    deflated(m, V, c, V.v0, V.v1, red);
-    deflated(m, V, c, V.v1, V.v2, red);
-    // least squares v2 ~ a v1 + b v0
-    double g11 = 0.0, g10 = 0.0, g00 = 0.0;
-    double r1 = 0.0, r0 = 0.0, w22 = 0.0;
-    for (int j = j0; j < j1; ++j) {
-      g11 += V.v1[j] * V.v1[j];
-      g10 += V.v1[j] * V.v0[j];
-      g00 += V.v0[j] * V.v0[j];
-      r1 += V.v2[j] * V.v1[j];
-      r0 += V.v2[j] * V.v0[j];
-      w22 += V.v2[j] * V.v2[j];
-    }
-    block_sum3<BT>(g11, g10, g00, red);
-    block_sum3<BT>(r1, r0, w22, red);
-    const double det = g11 * g00 - g10 * g10;
-    double a, b;
-    if (det > 1e-12 * g11 * g00) {
-      a = (r1 * g00 - r0 * g10) / det;
-      b = (g11 * r0 - g10 * r1) / det;
-      const double disc = a * a + 4.0 * b;
-      if (disc < 0.0) {
-        re = 0.5 * a;
-        im = 0.5 * sqrt(-disc);
-      } else {
-        const double s = sqrt(disc);
-        const double z1 = 0.5 * (a + s), z2 = 0.5 * (a - s);
-        re = fabs(z1) >= fabs(z2) ? z1 : z2;
-        im = 0.0;
+    // Every deflated vector sums to zero (P~ is stochastic and pi sums to
+    // one), so v1 = A v0 is taken with s = 0; the rounding-level sum that v0
+    // carries is removed each step (s0, from the fused sums below).  One
+    // block reduction per step gives the Gram entries, v2 . 1 and ||v2||,
+    // with which v2 becomes the next normalised v0.
+    for (; it < max_iter; ++it) {
+      deflated(m, V, c, V.v0, s0, V.v1, red);
+      deflated(m, V, c, V.v1, 0.0, V.v2, red);
+      // least squares v2 ~ a v1 + b v0
+      double q[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int j = j0; j < j1; ++j) {
+        q[0] += V.v1[j] * V.v1[j];
+        q[1] += V.v1[j] * V.v0[j];
+        q[2] += V.v0[j] * V.v0[j];
+        q[3] += V.v2[j] * V.v1[j];
+        q[4] += V.v2[j] * V.v0[j];
+        q[5] += V.v2[j] * V.v2[j];
+        q[6] += V.v2[j];
       }
-      // residual ||v2 - a v1 - b v0||^2 / ||v2||^2 from the Gram entries
-      const double res2 = w22 - 2.0 * (a * r1 + b * r0) + a * a * g11 + 2.0 * a * b * g10 + b * b * g00;
-      fit = w22 > 0.0 ? sqrt(fmax(res2, 0.0) / w22) : 0.0;
-    } else {  // v1 parallel to v0: one real dominant eigenvalue
-      a = g00 > 0.0 ? g10 / g00 : 0.0;
-      re = a;
-      im = 0.0;
-      const double res2 = g11 - 2.0 * a * g10 + a * a * g00;
-      fit = g11 > 0.0 ? sqrt(fmax(res2, 0.0) / g11) : 0.0;
+      block_sum_n<7>(q, red);
+      const double g11 = q[0], g10 = q[1], g00 = q[2], r1 = q[3], r0 = q[4], w22 = q[5];
+      const double det = g11 * g00 - g10 * g10;
+      double a, b;
+      if (det > 1e-12 * g11 * g00) {
+        a = (r1 * g00 - r0 * g10) / det;
+        b = (g11 * r0 - g10 * r1) / det;
+        const double disc = a * a + 4.0 * b;
+        if (disc < 0.0) {
+          re = 0.5 * a;
+          im = 0.5 * sqrt(-disc);
+        } else {
+          const double sq = sqrt(disc);
+          const double z1 = 0.5 * (a + sq), z2 = 0.5 * (a - sq);
+          re = fabs(z1) >= fabs(z2) ? z1 : z2;
+          im = 0.0;
+        }
+        // residual ||v2 - a v1 - b v0||^2 / ||v2||^2 from the Gram entries
+        const double res2 = w22 - 2.0 * (a * r1 + b * r0) + a * a * g11 + 2.0 * a * b * g10 + b * b * g00;
+        fit = w22 > 0.0 ? sqrt(fmax(res2, 0.0) / w22) : 0.0;
+      } else {  // v1 parallel to v0: one real dominant eigenvalue
+        a = g00 > 0.0 ? g10 / g00 : 0.0;
+        re = a;
+        im = 0.0;
+        const double res2 = g11 - 2.0 * a * g10 + a * a * g00;
+        fit = g11 > 0.0 ? sqrt(fmax(res2, 0.0) / g11) : 0.0;
+      }
+      const bool settled = fabs(re - prev_re) <= 1e-12 * (1.0 + fabs(re)) &&
+                           fabs(im - prev_im) <= 1e-12 * (1.0 + fabs(im));
+      prev_re = re;
+      prev_im = im;
+      if ((settled && it >= 4) || !(w22 > 0.0)) break;
+      // next start: v2 (two steps further along), normalised
+      const double sc2 = 1.0 / sqrt(w22);
+      for (int j = j0; j < j1; ++j) V.v0[j] = V.v2[j] * sc2;
+      s0 = q[6] * sc2;
+      __syncthreads();
     }
-    // next start: v2 (two steps further along)
-    for (int j = j0; j < j1; ++j) V.v0[j] = V.v2[j];
-    __syncthreads();
-    const bool settled = fabs(re - prev_re) <= 1e-12 * (1.0 + fabs(re)) &&
-                         fabs(im - prev_im) <= 1e-12 * (1.0 + fabs(im));
-    prev_re = re;
-    prev_im = im;
-    if (settled && it >= 4) break;
   }
   if constexpr (IN_LDS) {
     for (int j = j0; j < j1; ++j) {
