@@ -104,10 +104,11 @@ inline size_t dtype_size(dtm_dtype dt) { return dt == DTM_F32 ? 4 : 8; }
 inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Workspace layout of the single-pixel entry points (byte offsets).  The
-// band count caps the float64 partial sums at 256 rows of length ld.
+// band count caps the float64 partial sums at 256 rows of length ld; y and
+// the per-block sums (sum y, sum |y - x|) serve the two-stage combine.
 struct SingleLayout {
-  int32_t ld, bands, band_rows;
-  size_t off_colf, off_invs, off_x, off_scal, off_state, off_dprev, off_part, total;
+  int32_t ld, bands, band_rows, cblocks;
+  size_t off_colf, off_invs, off_x, off_scal, off_state, off_dprev, off_part, off_y, off_bsum, total;
 };
 inline SingleLayout single_layout(int32_t n, dtm_dtype dt) {
   SingleLayout L;
@@ -125,6 +126,9 @@ inline SingleLayout single_layout(int32_t n, dtm_dtype dt) {
   L.off_state = off; off = align256(off + sizeof(SolveState));
   L.off_dprev = off; off = align256(off + 8 * static_cast<size_t>(L.ld));
   L.off_part = off; off = align256(off + 8 * static_cast<size_t>(L.bands) * L.ld);
+  L.cblocks = (n + 255) / 256;
+  L.off_y = off;    off = align256(off + 8 * static_cast<size_t>(L.ld));
+  L.off_bsum = off; off = align256(off + 16 * static_cast<size_t>(L.cblocks));
   L.total = off;
   return L;
 }

@@ -860,30 +860,53 @@ __global__ __launch_bounds__(BT) void k_sweep_band(const T* __restrict__ P, int 
     out[e] = check ? accd[e] : static_cast<double>(acc[e]) - static_cast<double>(cmp[e]);
 }
 
+// Single-pixel combine, stage 1 (one block per 256 columns): y_j = the band
+// partial sums of column j added in band order, and the block's sums of y
+// and |y - x| (a fixed order), for stage 2.
 template <typename T, int BT>
-__global__ __launch_bounds__(BT) void k_combine(const double* __restrict__ part, int64_t part_ld,
-                                                int bands, int n, T* __restrict__ x,
-                                                double* __restrict__ dprev,
-                                                SolveState* __restrict__ state,
-                                                T* __restrict__ pi, KOpts o) {
+__global__ __launch_bounds__(BT) void k_combine_cols(const double* __restrict__ part, int64_t part_ld,
+                                                     int bands, int n, const T* __restrict__ x,
+                                                     const SolveState* __restrict__ state,
+                                                     double* __restrict__ y, double* __restrict__ bsum) {
+  __shared__ double red[3 * BT / kWave];
+  if (state->s.done) return;  // the same for every block
+  const int j = blockIdx.x * BT + threadIdx.x;
+  double sy = 0.0, rs = 0.0;
+  if (j < n) {
+    double yj = 0.0;
+    for (int b = 0; b < bands; ++b) yj += part[static_cast<int64_t>(b) * part_ld + j];
+    y[j] = yj;
+    sy = yj;
+    rs = fabs(yj - static_cast<double>(x[j]));
+  }
+  block_sum2<BT>(sy, rs, red);
+  if (threadIdx.x == 0) {
+    bsum[2 * blockIdx.x] = sy;
+    bsum[2 * blockIdx.x + 1] = rs;
+  }
+}
+
+// Stage 2 (one block): sum y and the residual from the blocks' sums, then
+// the new iterate y / sum y, its change, and the stop rule.
+template <typename T, int BT>
+__global__ __launch_bounds__(BT) void k_combine_finish(const double* __restrict__ y,
+                                                       const double* __restrict__ bsum, int cblocks, int n,
+                                                       T* __restrict__ x, double* __restrict__ dprev,
+                                                       SolveState* __restrict__ state, T* __restrict__ pi,
+                                                       KOpts o) {
   __shared__ double red[3 * BT / kWave];
   StopState s = state->s;
   if (s.done) return;
   const bool was_check = s.check_next != 0;
   double sy = 0.0, rs = 0.0;
-  for (int j = threadIdx.x; j < n; j += BT) {
-    double y = 0.0;
-    for (int b = 0; b < bands; ++b) y += part[static_cast<int64_t>(b) * part_ld + j];
-    sy += y;
-    rs += fabs(y - static_cast<double>(x[j]));
+  for (int i = 0; i < cblocks; ++i) {
+    sy += bsum[2 * i];
+    rs += bsum[2 * i + 1];
   }
-  block_sum2<BT>(sy, rs, red);
   const double inv = 1.0 / sy;
   double ch = 0.0, dd = 0.0, ddp = 0.0;
   for (int j = threadIdx.x; j < n; j += BT) {
-    double y = 0.0;
-    for (int b = 0; b < bands; ++b) y += part[static_cast<int64_t>(b) * part_ld + j];
-    const T xn = static_cast<T>(y * inv);
+    const T xn = static_cast<T>(y[j] * inv);
     const double dj = static_cast<double>(xn) - static_cast<double>(x[j]);
     ch += fabs(dj);
     dd += dj * dj;
@@ -1028,6 +1051,8 @@ int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_e
   SolveState* state = reinterpret_cast<SolveState*>(w + L.off_state);
   double* dprev = reinterpret_cast<double*>(w + L.off_dprev);
   double* part = reinterpret_cast<double*>(w + L.off_part);
+  double* y = reinterpret_cast<double*>(w + L.off_y);
+  double* bsum = reinterpret_cast<double*>(w + L.off_bsum);
   constexpr int VN = Vec<T>::n;
   const bool vec = (ld % VN == 0) && (reinterpret_cast<uintptr_t>(P) % 16 == 0);
   hipLaunchKernelGGL((k_solver_init<T, kBT>), dim3(1), dim3(kBT), 0, st, x0, x, dprev, state, n);
@@ -1037,7 +1062,7 @@ int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_e
   const int cols_per_block = kBT * vn;
   dim3 grid((n + cols_per_block - 1) / cols_per_block, L.bands);
   SolveState hs;
-  // Each pair of launches is one sweep; after `done` they return at once.
+  // Each three launches are one sweep; after `done` they return at once.
   // The stop rule ends every solve within 2 * max_iter sweeps (one restart).
   const int max_sweeps = 2 * ko.max_iter + 2;
   int launched = 0;
@@ -1049,8 +1074,10 @@ int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_e
       else
         hipLaunchKernelGGL((k_sweep_band<T, kBT, 1>), grid, dim3(kBT), 0, st, P, n, ld, x, state,
                            part, static_cast<int64_t>(L.ld), L.band_rows);
-      hipLaunchKernelGGL((k_combine<T, kBT>), dim3(1), dim3(kBT), 0, st, part,
-                         static_cast<int64_t>(L.ld), L.bands, n, x, dprev, state, pi, ko);
+      hipLaunchKernelGGL((k_combine_cols<T, kBT>), dim3(L.cblocks), dim3(kBT), 0, st, part,
+                         static_cast<int64_t>(L.ld), L.bands, n, x, state, y, bsum);
+      hipLaunchKernelGGL((k_combine_finish<T, kBT>), dim3(1), dim3(kBT), 0, st, y, bsum, L.cblocks, n, x, dprev,
+                         state, pi, ko);
     }
     rc = last_launch();
     if (rc) return rc;
