@@ -338,7 +338,7 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
  * (their mean plus ten standard deviations; the excess is dropped).
  * lanes_per_run: 0 = automatic, else a power of two <= 64 (lanes that share
  * one segment; the counts do not depend on it).
- * segments_per_run: 0 = automatic (about 2^17 segments in all, none shorter
+ * segments_per_run: 0 = automatic (about 2^18 segments in all, none shorter
  * than 256 periods), else 1 .. cycles (1 = no cut; the counts do not depend
  * on it).
  * scratch_dev / scratch_bytes: segment states, at least

@@ -51,7 +51,8 @@
 namespace dtm {
 namespace mc {
 
-constexpr int BT = 64;        // one wave per block
+constexpr int BT = 64;        // wavefront size (one wavefront per block in the repair passes)
+constexpr int WPB = 2;        // wavefronts per block of k_mc (they share the pixel's histogram)
 constexpr int kCoopMin = 16;  // lanes per run from which the hand-over search is shared
 
 __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
@@ -210,35 +211,36 @@ __device__ inline double* pool_segment(double* pool, int cap, int want, int lane
 // the XCDs in turn, spread every pixel over all of them (a 2D grid with the
 // pixel as its x would pin pixel x to XCD x mod 8 whenever the pixel count is
 // a multiple of 8, and the XCD with the brightest pixels would set the time).
-// Block = one wave = 64 / L chains of one pixel.
+// Block = WPB wavefronts of 64 / L chains each, all of one pixel.
 // Chain q of a pixel is segment q mod K of run q / K: periods
 // [seg len (q mod K), min(seg len (q mod K + 1), cycles)), started armed; with
 // K > 1 its last rearm time goes to spec_end.
-// LDS: a pool of `cap` photon times shared by the wave's 64 periods of a
-// chunk (each lane owns a contiguous segment, placed by a prefix sum of its
-// Poisson counts, sorted), for each photon the last registration of the
-// chain that starts with it (uint16, same offsets), then the pixel's
-// histogram (n uint32), added atomically to HBM at the end.
-__global__ __launch_bounds__(BT) void k_mc(const PixelMeta* __restrict__ metas, int runs, int64_t cycles,
+// LDS: per wavefront, a pool of `cap` photon times shared by its 64 periods
+// of a chunk (each lane owns a contiguous segment, placed by a prefix sum of
+// its Poisson counts, sorted); per wavefront, for groups that share the
+// search, for each photon the last registration of the chain that starts
+// with it (uint16, same offsets); then the pixel's histogram (n uint32),
+// shared by the block's wavefronts and added atomically to HBM at the end.
+__global__ __launch_bounds__(BT * WPB) void k_mc(const PixelMeta* __restrict__ metas, int runs, int64_t cycles,
                                            int64_t burn, uint64_t seed, int L, int cap, int K, int64_t seg_len,
                                            int chain_blocks, uint32_t* __restrict__ hist,
                                            uint32_t* __restrict__ overflow, double* __restrict__ spec_end) {
   extern __shared__ double lds_d[];
   __shared__ double cdf_s[KMAX], cdf_b[KMAX];
-  double* pool = lds_d;
+  const int wid = static_cast<int>(threadIdx.x) / BT, lane = static_cast<int>(threadIdx.x) % BT;
+  double* pool = lds_d + wid * cap;
   // jend (uint16 per pool slot) only for groups that share the search
-  uint16_t* jend = reinterpret_cast<uint16_t*>(lds_d + cap);
-  uint32_t* h = reinterpret_cast<uint32_t*>(lds_d + cap) + (L >= kCoopMin ? (cap + 1) / 2 : 0);
+  uint16_t* jend = reinterpret_cast<uint16_t*>(lds_d + WPB * cap) + wid * cap;
+  uint32_t* h = reinterpret_cast<uint32_t*>(lds_d + WPB * cap) + (L >= kCoopMin ? (WPB * cap + 1) / 2 : 0);
   const int pix = static_cast<int>(blockIdx.x / chain_blocks), cb = static_cast<int>(blockIdx.x % chain_blocks);
   const PixelMeta m = metas[pix];
   const int n = m.n;
-  const int lane = threadIdx.x;
-  for (int j = lane; j < n; j += BT) h[j] = 0u;
-  if (lane == 0) poisson_cdf(m.S, m.e_s, cdf_s);
-  if (lane == 1) poisson_cdf(m.B, m.e_b, cdf_b);
+  for (int j = threadIdx.x; j < n; j += BT * WPB) h[j] = 0u;
+  if (threadIdx.x == 0) poisson_cdf(m.S, m.e_s, cdf_s);
+  if (threadIdx.x == 1) poisson_cdf(m.B, m.e_b, cdf_b);
   __syncthreads();
   const int k_in = lane % L, base_lane = lane - k_in;
-  const int64_t chain = static_cast<int64_t>(cb) * (BT / L) + lane / L;
+  const int64_t chain = (static_cast<int64_t>(cb) * WPB + wid) * (BT / L) + lane / L;
   const int run = static_cast<int>(chain / K), sgm = static_cast<int>(chain % K);
   const bool run_ok = run < runs;
   const int64_t seg_begin = sgm * seg_len, seg_end = min(seg_begin + seg_len, cycles);
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(BT) void k_mc(const PixelMeta* __restrict__ metas, 
   if (K > 1 && run_ok && k_in == 0) spec_end[(static_cast<int64_t>(pix) * runs + run) * K + sgm] = a;
   if (over) atomicOr(&overflow[m.index], 1u);
   __syncthreads();
-  for (int j = lane; j < n; j += BT)
+  for (int j = threadIdx.x; j < n; j += BT * WPB)
     if (h[j]) atomicAdd(&hist[m.pi_off + j], h[j]);
 }
 
@@ -482,15 +484,16 @@ using namespace dtm;
 namespace {
 
 // Segments per run (K, after dropping empty ones) and periods per segment.
-// segments_per_run 0 picks about 2^17 chains in all (the rate of a chip full
-// of them, measured) with segments of at least 256 periods (their repair
-// walks, a few periods each, stay a small share).
+// segments_per_run 0 picks about 2^18 chains in all (measured on the paper's
+// sweeps: 2^17 to 2^19 chains run within 5 % of each other) with segments of
+// at least 256 periods (their repair walks, a few periods each, stay a small
+// share).
 void mc_segments(const dtm_plan* plan, int32_t runs_per_pixel, int64_t cycles, int32_t segments_per_run,
                  int64_t* K_out, int64_t* seg_len_out) {
   const double runs_total = static_cast<double>(plan->n_pixels) * runs_per_pixel;
   int64_t K = segments_per_run;
   if (K == 0) {
-    K = static_cast<int64_t>(std::ceil(131072.0 / runs_total));
+    K = static_cast<int64_t>(std::ceil(262144.0 / runs_total));
     K = std::max<int64_t>(1, std::min<int64_t>(K, cycles / 256));
   }
   const int64_t seg_len = (cycles + K - 1) / K;
@@ -540,14 +543,14 @@ extern "C" int dtm_mc_histograms(const dtm_plan* plan, int32_t runs_per_pixel, i
   if (scratch_bytes < state_bytes) return DTM_ENOSPACE;
   int L = lanes_per_run;
   if (L == 0) {
-    // At least 8 lanes per chain, more until the chains give about one and a
+    // At least 4 lanes per chain, more until the chains give about one and a
     // half waves to each SIMD of the 256 CUs (measured: the longer hand-over
     // chain of a larger group costs less than an idle SIMD).
     const double chains = runs_total * static_cast<double>(K);
-    L = 8;
+    L = 4;
     while (L < mc::BT && chains * L < 256.0 * 4 * 64 * 1.5) L *= 2;
   }
-  const int per_block = mc::BT / L;
+  const int per_block = mc::WPB * (mc::BT / L);
   const int64_t chain_blocks = (static_cast<int64_t>(runs_per_pixel) * K + per_block - 1) / per_block;
   const int64_t fix_blocks = (static_cast<int64_t>(runs_per_pixel) * (K - 1) + mc::BT - 1) / mc::BT;
   const int64_t chain_blocks_b = (static_cast<int64_t>(runs_per_pixel) + mc::BT - 1) / mc::BT;
@@ -565,8 +568,8 @@ extern "C" int dtm_mc_histograms(const dtm_plan* plan, int32_t runs_per_pixel, i
   for (const PixelMeta& m : plan->meta) lam = std::max(lam, m.S + m.B);
   const double mean = mc::BT * lam;
   const int cap = static_cast<int>(std::ceil(mean + 10.0 * std::sqrt(mean) + 64.0));
-  const size_t lds = sizeof(double) * static_cast<size_t>(cap) +
-                    (L >= mc::kCoopMin ? sizeof(uint32_t) * static_cast<size_t>((cap + 1) / 2) : 0) +
+  const size_t lds = sizeof(double) * static_cast<size_t>(mc::WPB * cap) +
+                    (L >= mc::kCoopMin ? sizeof(uint32_t) * static_cast<size_t>((mc::WPB * cap + 1) / 2) : 0) +
                     sizeof(uint32_t) * static_cast<size_t>(plan->max_n);
   if (lds > 160 * 1024) return DTM_ENOTSUP;
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(mc::k_mc), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -580,7 +583,7 @@ extern "C" int dtm_mc_histograms(const dtm_plan* plan, int32_t runs_per_pixel, i
   const size_t total = plan->pi_elems;
   hipLaunchKernelGGL(mc::k_zero, dim3(static_cast<unsigned>((total + mc::BT - 1) / mc::BT)), dim3(mc::BT), 0, st,
                      hist_packed_dev, total);
-  hipLaunchKernelGGL(mc::k_mc, dim3(static_cast<unsigned>(plan->n_pixels * chain_blocks)), dim3(mc::BT), lds, st,
+  hipLaunchKernelGGL(mc::k_mc, dim3(static_cast<unsigned>(plan->n_pixels * chain_blocks)), dim3(mc::BT * mc::WPB), lds, st,
                      metas, runs_per_pixel, cycles, burn_cycles, seed, L, cap, static_cast<int>(K), seg_len,
                      static_cast<int>(chain_blocks), hist_packed_dev, overflow_dev, spec_end);
   if (K > 1) {

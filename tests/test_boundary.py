@@ -203,12 +203,13 @@ def test_monte_carlo_arguments_before_any_launch(d):
 
 
 def test_monte_carlo_segment_scratch_sizes(d):
-    """Host-side segment layout: about 2^17 segments in all, none shorter
+    """Host-side segment layout: about 2^18 segments in all, none shorter
     than 256 periods, empty tail segments dropped; 20 bytes per segment
     (speculative end, repaired end, coupled flag), none without a cut."""
     plan = d.Plan(sc.paper_grid(dead_time=75.0, n_bins=64), "f64")  # 16 pixels
     per = 2 * 8 + 4
-    assert plan.mc_scratch_bytes(100, 50_000) == 16 * 100 * 82 * per  # K = ceil(2^17 / 1600) = 82
+    # K = ceil(2^18 / 1600) = 164 -> 305 periods a segment -> 164 segments
+    assert plan.mc_scratch_bytes(100, 50_000) == 16 * 100 * 164 * per
     assert plan.mc_scratch_bytes(100, 10_000) == 16 * 100 * 39 * per  # capped at 10000 // 256 = 39
     assert plan.mc_scratch_bytes(100, 300) == 0  # one segment: no scratch
     assert plan.mc_scratch_bytes(3, 400, 1) == 0
