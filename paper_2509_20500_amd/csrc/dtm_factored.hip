@@ -235,7 +235,7 @@ constexpr size_t lds_doubles() {
 }
 
 template <typename T, int E>
-__global__ __launch_bounds__(BT) void k_solve_factored_wave(const PixelMeta* __restrict__ metas, int n_pixels,
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void k_solve_factored_wave(const PixelMeta* __restrict__ metas, int n_pixels,
                                                             const T* __restrict__ x0_packed,
                                                             T* __restrict__ pi_packed,
                                                             dtm_solve_info* __restrict__ infos, KOpts o) {
@@ -245,36 +245,78 @@ __global__ __launch_bounds__(BT) void k_solve_factored_wave(const PixelMeta* __r
   if (p >= n_pixels) return;  // whole wavefronts only; nothing below waits for another wavefront
   const PixelMeta m = metas[p];
   const int n = m.n;
-  double* xs = lds_x + wid * lds_doubles<E>();
+  double* xs = lds_x + wid * 2 * lds_doubles<E>();
   const int j0 = lane * E;
   double* xo = xs + slot<E>(j0);  // this lane's own bins (E consecutive slots)
 
   // ---- bin tables (as pixel_tables and row_normalisers, per wavefront) ----
+  // The flux integrals of the bins are taken with bin j = 64 q + lane (q < E)
+  // so that the bins near the pulse, the only ones whose normal tails are not
+  // exactly zero (erfc(40 / sqrt 2) / 2 underflows, and so does the pulse
+  // term of lambda there), are spread over all lanes; a far bin takes those
+  // exact zeros without calling erfc or exp.  The integrals then pass through
+  // LDS to the lane that owns the bin, which sums them in bin order as
+  // pixel_tables does.  The second LDS copy per wavefront serves only this
+  // transposition; the kernel is held to two wavefronts per SIMD so that the
+  // tables' registers do not halve its residency.
+  constexpr double kFar = 40.0;
   const double delta = m.t_r / n, is = 1.0 / m.sigma, bq = m.B / m.t_r;
+  double* ts = xs + lds_doubles<E>();  // second LDS copy, used by the tables only
+  double dF[E], sh[E], lam[E];  // integral over the bin, S x normal mass up to its centre, lambda at the centre
+#pragma unroll 2
+  for (int q = 0; q < E; ++q) {
+    const int j = q * kWave + lane;
+    if (j < n) {
+      const double zl = (j * delta - m.tau) * is;
+      const double zm = (j * delta + 0.5 * delta - m.tau) * is, zh = ((j + 1) * delta - m.tau) * is;
+      double mh = 0.0, mf = 0.0;
+      if (zh >= -kFar && zl <= kFar) {
+        const double tl = gauss_tail(zl), tm = gauss_tail(zm), th = gauss_tail(zh);
+        mh = mass_from_tails(zl, tl, zm, tm);
+        mf = mass_from_tails(zl, tl, zh, th);
+      }
+      xs[slot<E>(j)] = m.S * mf + bq * delta;
+      ts[slot<E>(j)] = m.S * mh;
+    }
+  }
+  sync_wave();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    dF[e] = (j0 + e < n) ? xo[e] : 0.0;
+    sh[e] = (j0 + e < n) ? ts[slot<E>(j0 + e)] : 0.0;
+  }
+  sync_wave();
+#pragma unroll 2
+  for (int q = 0; q < E; ++q) {
+    const int j = q * kWave + lane;
+    if (j < n) {
+      const double zl = (j * delta - m.tau) * is, zh = ((j + 1) * delta - m.tau) * is;
+      xs[slot<E>(j)] = (m.lam_mode == 0 && zh >= -kFar && zl <= kFar) ? flux_at(m, j * delta + 0.5 * delta) : bq;
+    }
+  }
+  sync_wave();
+#pragma unroll
+  for (int e = 0; e < E; ++e) lam[e] = (j0 + e < n) ? xo[e] : 0.0;
+  sync_wave();
   const int jb = min(j0, n), je = min(j0 + E, n);
   const double zb = (jb * delta - m.tau) * is, ze = (je * delta - m.tau) * is;
   double part = 0.0;
-  if (je > jb) part = m.S * mass_from_tails(zb, gauss_tail(zb), ze, gauss_tail(ze)) + bq * ((je - jb) * delta);
+  if (je > jb) {
+    const double mass = (ze >= -kFar && zb <= kFar) ? mass_from_tails(zb, gauss_tail(zb), ze, gauss_tail(ze)) : 0.0;
+    part = m.S * mass + bq * ((je - jb) * delta);
+  }
   double Lam;
   double acc = excl_scan(part, lane, &Lam);
   double g[E], inv[E];
-  double zl = zb, tl = gauss_tail(zb);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int j = j0 + e;
     g[e] = 0.0;
-    if (j < n) {
-      const double lo = j * delta;
-      const double zm = (lo + 0.5 * delta - m.tau) * is, zh = ((j + 1) * delta - m.tau) * is;
-      const double tm = gauss_tail(zm), th = gauss_tail(zh);
-      const double F = acc + m.S * mass_from_tails(zl, tl, zm, tm) + bq * (0.5 * delta);
-      const double dF = m.S * mass_from_tails(zl, tl, zh, th) + bq * delta;
-      if (m.lam_mode == 0) g[e] = flux_at(m, lo + 0.5 * delta) * exp(-F);
-      else if (m.lam_mode == 1) g[e] = dF / delta * exp(-F);
-      else g[e] = exp(-acc) * -expm1(-dF) / delta;
-      acc += dF;
-      zl = zh;
-      tl = th;
+    if (j0 + e < n) {
+      const double F = acc + sh[e] + bq * (0.5 * delta);
+      if (m.lam_mode == 0) g[e] = lam[e] * exp(-F);
+      else if (m.lam_mode == 1) g[e] = dF[e] / delta * exp(-F);
+      else g[e] = exp(-acc) * -expm1(-dF[e]) / delta;
+      acc += dF[e];
     }
   }
   const double c = exp(-Lam);
@@ -745,10 +787,24 @@ int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, 
   KOpts o = plan->kopts;
   o.pad = 0;
   if (plan->max_n <= 1024) {
-    // one wavefront per pixel, four per block; E bins per lane
+    // one wavefront per pixel, four per block; E bins per lane; two LDS
+    // copies of a pixel's bins per wavefront (the iterate, and the tables'
+    // second transposition buffer)
     const int E = plan->max_n <= 256 ? 4 : plan->max_n <= 512 ? 8 : 16;
     const dim3 grid((plan->n_pixels + 3) / 4), block(fact::BT);
-    const size_t lds = sizeof(double) * 4 * kWave * (E + 1);
+    const size_t lds = sizeof(double) * 4 * 2 * kWave * (E + 1);
+    const void* kern = nullptr;
+    if (plan->dt == DTM_F32)
+      kern = E == 4 ? reinterpret_cast<const void*>(fact::wave::k_solve_factored_wave<float, 4>)
+             : E == 8 ? reinterpret_cast<const void*>(fact::wave::k_solve_factored_wave<float, 8>)
+                      : reinterpret_cast<const void*>(fact::wave::k_solve_factored_wave<float, 16>);
+    else
+      kern = E == 4 ? reinterpret_cast<const void*>(fact::wave::k_solve_factored_wave<double, 4>)
+             : E == 8 ? reinterpret_cast<const void*>(fact::wave::k_solve_factored_wave<double, 8>)
+                      : reinterpret_cast<const void*>(fact::wave::k_solve_factored_wave<double, 16>);
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+      return DTM_EHIP;
     if (plan->dt == DTM_F32) {
       const float* x0 = static_cast<const float*>(x0_packed_dev);
       float* pi = static_cast<float*>(pi_packed_dev);
