@@ -294,10 +294,11 @@ int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, 
  * v_{t+2} = a v_{t+1} + b v_t, whose roots are the dominant eigenvalue (or
  * complex pair); the fit is reliable when |lambda_3| is clearly below
  * |lambda_2|.  Uses the factored operator (O(n) per step per vector).  The
- * mixing search keeps all n start states (2 n^2 float64 per pixel of
- * scratch).  Without the mixing search the call only launches; with it, it
- * copies the per-pixel scratch offsets from the host and synchronises
- * `stream` before returning.  scratch_bytes below
+ * mixing search advances every start state: for plans whose pixels have at
+ * most 1024 bins on chip (the call then only launches); above that in the
+ * scratch (2 n^2 float64 per pixel), and the call then copies the per-pixel
+ * scratch offsets from the host and synchronises `stream` before
+ * returning.  scratch_bytes below
  * dtm_spectral_scratch_bytes gives DTM_ENOSPACE; max_steps outside
  * [1, 2^30] or an unbound plan DTM_EINVAL. */
 typedef struct dtm_spectral_info {

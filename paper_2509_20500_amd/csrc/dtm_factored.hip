@@ -856,10 +856,12 @@ int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, 
 size_t dtm_spectral_scratch_bytes(const dtm_plan* plan, int32_t with_mixing) {
   if (!plan) return 0;
   // 8 float64 vectors per pixel for the deflated iteration, c per pixel, and
-  // optionally two n x n float64 blocks per pixel plus their offsets
+  // for the mixing search of plans with n above 1024 (one thread per start
+  // state) two n x n float64 blocks per pixel plus their offsets; up to
+  // 1024 bins the search keeps every start state on chip
   size_t b = align256(8 * fact::NVEC * static_cast<size_t>(plan->vec_elems));
   b += align256(8 * static_cast<size_t>(plan->n_pixels));
-  if (with_mixing) {
+  if (with_mixing && plan->max_n > 1024) {
     size_t mix = 0;
     for (const PixelMeta& m : plan->meta) mix += 2 * static_cast<size_t>(m.n) * m.n;
     b += align256(8 * mix) + align256(8 * static_cast<size_t>(plan->n_pixels));
@@ -901,18 +903,6 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
   if (hipGetLastError() != hipSuccess) return DTM_EHIP;
   if (!with_mix) return DTM_OK;
   // k_spectral left g, 1/S, pi and c in the scratch
-  std::vector<int64_t> offs(plan->n_pixels);
-  size_t mix = 0;
-  for (int32_t q = 0; q < plan->n_pixels; ++q) {
-    offs[q] = static_cast<int64_t>(mix);
-    mix += 2 * static_cast<size_t>(plan->meta[q].n) * plan->meta[q].n;
-  }
-  double* mixbuf = reinterpret_cast<double*>(s + off);
-  off += align256(8 * mix);
-  int64_t* mix_off = reinterpret_cast<int64_t*>(s + off);
-  if (hipMemcpyAsync(mix_off, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice, st) !=
-      hipSuccess)
-    return DTM_EHIP;
   if (static_cast<double>(plan->n_pixels) * ((plan->max_n + 3) / 4) >= 2147483647.0) return DTM_EINVAL;
   if (plan->max_n <= 1024) {
     // one wavefront per start state, four per block; E bins per lane
@@ -929,7 +919,26 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
     else
       hipLaunchKernelGGL(fact::k_mixing_wave<16>, grid, dim3(fact::BT), lds, st, metas, fact, plan->vec_elems,
                          scal, out_dev, mixing_eps, max_steps, sb);
-  } else {
+    if (hipGetLastError() != hipSuccess) return DTM_EHIP;
+    hipLaunchKernelGGL(fact::k_mixing_final, dim3((plan->n_pixels + fact::BT - 1) / fact::BT), dim3(fact::BT), 0, st,
+                       metas, plan->n_pixels, out_dev, max_steps);
+    return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP;
+  }
+  // larger pixels: the n x n blocks of start-state distributions live in the
+  // scratch, at per-pixel offsets copied from the host
+  std::vector<int64_t> offs(plan->n_pixels);
+  size_t mix = 0;
+  for (int32_t q = 0; q < plan->n_pixels; ++q) {
+    offs[q] = static_cast<int64_t>(mix);
+    mix += 2 * static_cast<size_t>(plan->meta[q].n) * plan->meta[q].n;
+  }
+  double* mixbuf = reinterpret_cast<double*>(s + off);
+  off += align256(8 * mix);
+  int64_t* mix_off = reinterpret_cast<int64_t*>(s + off);
+  if (hipMemcpyAsync(mix_off, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice, st) !=
+      hipSuccess)
+    return DTM_EHIP;
+  {
     const int sb = (plan->max_n + fact::BT - 1) / fact::BT;
     hipLaunchKernelGGL(fact::k_mixing, dim3(static_cast<unsigned>(plan->n_pixels) * static_cast<unsigned>(sb)),
                        dim3(fact::BT), 0, st, metas, fact, plan->vec_elems, mixbuf, mix_off, scal, out_dev,

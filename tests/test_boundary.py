@@ -227,3 +227,17 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_spectral_scratch_sizes(d):
+    """Up to 1024 bins the mixing search needs no n x n scratch (its start
+    states stay on chip); above, two n x n float64 blocks per pixel and their
+    offsets are added."""
+    small = d.Plan(sc.paper_grid(dead_time=75.0, n_bins=1024), "f64", d.opts(flags=d.DTM_FLAG_NO_DENSE))
+    assert small.spectral_scratch_bytes(True) == small.spectral_scratch_bytes(False) > 0
+    small.close()
+    big = d.Plan(sc.paper_grid(dead_time=75.0, n_bins=1100), "f64", d.opts(flags=d.DTM_FLAG_NO_DENSE))
+    extra = big.spectral_scratch_bytes(True) - big.spectral_scratch_bytes(False)
+    mix = 16 * 2 * 8 * 1100 * 1100
+    assert mix <= extra < mix + 2 * 256 + 8 * 16
+    big.close()
