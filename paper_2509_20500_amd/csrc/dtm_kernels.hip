@@ -1202,8 +1202,7 @@ int launch_band_init(const dtm_plan* plan, const PixelMeta* metas, const T* x0, 
 // Sweeps [t0, t1) of the banded path (sweep 0 builds the matrices).
 template <typename T>
 int launch_banded(const dtm_plan* plan, int t0, int t1, const PixelMeta* metas, const T* colf,
-                  const double* scal, const T* invs, T* pool, const T* x0, T* pi, dtm_solve_info* infos,
-                  hipStream_t st) {
+                  const double* scal, const T* invs, T* pool, T* pi, dtm_solve_info* infos, hipStream_t st) {
   constexpr int BT = 256;
   char* w = static_cast<char*>(plan->ws);
   const int32_t* big = reinterpret_cast<const int32_t*>(w + plan->off_big);
@@ -1241,7 +1240,6 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
   char* w = static_cast<char*>(plan->ws);
   const PixelMeta* metas = reinterpret_cast<const PixelMeta*>(w + plan->off_meta);
   const int32_t* small = reinterpret_cast<const int32_t*>(w + plan->off_small);
-  const int32_t* big = reinterpret_cast<const int32_t*>(w + plan->off_big);
   T* pool = reinterpret_cast<T*>(w + plan->off_pool);
   T* colf = reinterpret_cast<T*>(w + plan->off_colf);
   T* invs = reinterpret_cast<T*>(w + plan->off_invs);
@@ -1300,8 +1298,8 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
     if (rc) return rc;
   }
   if (nbig > 0) {
-    rc = launch_banded<T>(plan, 0, std::min(1, plan->tiles.band_sweeps), metas, colf, scal, invs, pool, x0t, pit,
-                          infos, st);
+    rc = launch_banded<T>(plan, 0, std::min(1, plan->tiles.band_sweeps), metas, colf, scal, invs, pool, pit, infos,
+                          st);
     if (rc) return rc;
   }
   if (fork) {
@@ -1316,7 +1314,7 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
     if (rc) return rc;
   }
   if (nbig > 0) {
-    rc = launch_banded<T>(plan, 1, plan->tiles.band_sweeps, metas, colf, scal, invs, pool, x0t, pit, infos, st);
+    rc = launch_banded<T>(plan, 1, plan->tiles.band_sweeps, metas, colf, scal, invs, pool, pit, infos, st);
     if (rc) return rc;
   }
   if (fork) {
@@ -1477,12 +1475,12 @@ int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes, d
     hipEvent_t a, b;
     if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) return DTM_EHIP;
     if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess) {
-      hipStreamDestroy(aux);
+      (void)hipStreamDestroy(aux);
       return DTM_EHIP;
     }
     if (hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
-      hipEventDestroy(a);
-      hipStreamDestroy(aux);
+      (void)hipEventDestroy(a);
+      (void)hipStreamDestroy(aux);
       return DTM_EHIP;
     }
     plan->aux_stream = aux;
@@ -1497,10 +1495,10 @@ int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes, d
 void dtm_plan_destroy(dtm_plan* plan) {
   if (!plan) return;
   if (plan->aux_stream) {
-    hipStreamSynchronize(static_cast<hipStream_t>(plan->aux_stream));
-    hipStreamDestroy(static_cast<hipStream_t>(plan->aux_stream));
-    hipEventDestroy(static_cast<hipEvent_t>(plan->ev_fork));
-    hipEventDestroy(static_cast<hipEvent_t>(plan->ev_join));
+    (void)hipStreamSynchronize(static_cast<hipStream_t>(plan->aux_stream));
+    (void)hipStreamDestroy(static_cast<hipStream_t>(plan->aux_stream));
+    (void)hipEventDestroy(static_cast<hipEvent_t>(plan->ev_fork));
+    (void)hipEventDestroy(static_cast<hipEvent_t>(plan->ev_join));
   }
   delete plan;
 }
@@ -1536,26 +1534,26 @@ int dtm_graph_create(const dtm_plan* plan, const void* x0_packed_dev, void* pi_p
   int rc = DTM_OK;
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     return DTM_EHIP;
   }
   rc = plan->dt == DTM_F32 ? batched_solve<float>(plan, x0_packed_dev, pi_packed_dev, infos_dev, cs)
                            : batched_solve<double>(plan, x0_packed_dev, pi_packed_dev, infos_dev, cs);
   const hipError_t ec = hipStreamEndCapture(cs, &g);
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   if (rc != DTM_OK || ec != hipSuccess || !g) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc != DTM_OK ? rc : DTM_EHIP;
   }
   hipGraphExec_t ex = nullptr;
   if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return DTM_EHIP;
   }
   dtm_graph* out = new (std::nothrow) dtm_graph{g, ex};
   if (!out) {
-    hipGraphExecDestroy(ex);
-    hipGraphDestroy(g);
+    (void)hipGraphExecDestroy(ex);
+    (void)hipGraphDestroy(g);
     return DTM_EINVAL;
   }
   *graph_out = out;
@@ -1569,8 +1567,8 @@ int dtm_graph_launch(dtm_graph* graph, dtm_stream_t stream) {
 
 void dtm_graph_destroy(dtm_graph* graph) {
   if (!graph) return;
-  hipGraphExecDestroy(graph->exec);
-  hipGraphDestroy(graph->graph);
+  (void)hipGraphExecDestroy(graph->exec);
+  (void)hipGraphDestroy(graph->graph);
   delete graph;
 }
 
