@@ -697,6 +697,9 @@ def main():
     ap.add_argument("--fused-max-bins", type=int, default=0, help="largest n of the one-block solver (0 = default)")
     ap.add_argument("--band-rows", type=int, default=0, help="rows per banded work item (0 = default)")
     ap.add_argument("--band-cpt", type=int, default=0, help="column vectors per thread, banded (0 = default)")
+    ap.add_argument("--variant", default="paper",
+                    choices=["paper", "nearest", "bin_mean", "bin_integral", "interp"],
+                    help="discretisation of the model (interp needs --solver factored)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also time a plain 1 GiB device copy (the reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -736,6 +739,13 @@ def main():
     factored = args.solver == "factored"
     if factored:
         sopts.flags |= dtm.DTM_FLAG_NO_DENSE
+    variant_flags = {"paper": 0, "nearest": dtm.DTM_FLAG_SHIFT_NEAREST, "bin_mean": dtm.DTM_FLAG_LAMBDA_BIN_MEAN,
+                     "bin_integral": dtm.DTM_FLAG_BIN_INTEGRAL, "interp": dtm.DTM_FLAG_SHIFT_INTERP}
+    if args.variant == "interp" and not factored:
+        print("bench.py: the interpolated shift runs on the factored solver only (--solver factored)",
+              file=sys.stderr)
+        sys.exit(2)
+    sopts.flags |= variant_flags[args.variant]
     plan = dtm.Plan(scenes, args.dtype, sopts, tiles)
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     plan.bind(ws)
@@ -780,8 +790,13 @@ def main():
     rng = np.random.default_rng(0)
     small = np.flatnonzero(scenes["n_bins"] <= 2048)
     l1 = 0.0
+    from oracle import variants as ovar
+    shift_lam = {"paper": ("ceil", "point"), "nearest": ("nearest", "point"), "bin_mean": ("ceil", "bin_mean"),
+                 "bin_integral": ("ceil", "bin_integral"), "interp": ("interp", "point")}[args.variant]
     for p in rng.choice(small, min(args.check, small.size), replace=False):
-        ref = odtm.stationary_solve(odtm.transition_matrix(scenes[p]))
+        mat = (odtm.transition_matrix(scenes[p]) if args.variant == "paper"
+               else ovar.transition_matrix_variant(scenes[p], *shift_lam))
+        ref = odtm.stationary_solve(mat)
         l1 = max(l1, float(np.abs(got[off[p]:off[p + 1]] - ref).sum()))
 
     if uneven:
@@ -794,6 +809,7 @@ def main():
     desc += (f"{args.dtype} build+sweeps, float64 check, L1<=1e-6" if not factored else
              f"factored solver (no matrix, O(n) float64 sweeps), {args.dtype} output, L1<=1e-6")
     desc += "; HIP graph" if graph else ""
+    desc += f"; model variant {args.variant}" if args.variant != "paper" else ""
     out = {
         "metric": "stationary-PDF pixels/s at N=1024, L1<=1e-6 vs FP64 oracle; % HBM roofline",
         "value": value,
@@ -830,7 +846,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": (measured_traffic("k_solve_build+k_solve_sweeps", f"batched_uniform_n1024_{args.dtype}")
-                        if not uneven and plan.n_pixels == 4096 and not graph and not tiles else None),
+                        if (not uneven and plan.n_pixels == 4096 and not graph and not tiles
+                            and args.variant == "paper") else None),
             "kernel": ("k_solve_build + k_solve_sweeps" if not uneven
                        else "k_solve_build + k_solve_sweeps + k_band_sweep"),
             "alg_bytes_per_launch": alg_bytes,
