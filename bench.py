@@ -477,10 +477,17 @@ def cpu_baseline(scenes, sample):
         t0 = time.perf_counter()
         pool.map(_oracle_one, recs, chunksize=max(1, len(recs) // (4 * workers)))
         dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": len(recs) / dt, "unit": "pixels/s", "cores": workers, "kind": "oracle",
         "sample": f"first {len(recs)} pixels of the workload; float64 dense build + LAPACK solve; "
                   f"{workers} processes x 1 BLAS thread; {dt:.2f} s wall",
+        "host": {"cpu_count": os.cpu_count(), "cpu_model": model},
     }
 
 
