@@ -85,8 +85,13 @@ typedef struct dtm_scene {
 /* Stop rules of the power iteration (Section 4: the convergence rate is set
  * by |lambda_2|, which the bound rule estimates from successive changes). */
 #define DTM_STOP_CHANGE 0 /* stop when ||x_{t+1} - x_t||_1 < tol_l1              */
-#define DTM_STOP_BOUND  1 /* stop when c_t * rho/(1-rho) <= safety * tol_l1, then
-                             confirm with a float64 residual sweep              */
+#define DTM_STOP_BOUND  1 /* with c_t the L1 change and rho the contraction
+                             estimated from successive changes: once the next
+                             change is predicted to meet c rho/(1-rho) <=
+                             safety * tol_l1, the next sweep is a float64
+                             check; stop when its residual r = ||x P~ - x||_1
+                             meets r rho/(1-rho) <= safety * tol_l1 (the check
+                             sweep's output is returned)                        */
 
 /* Option flags */
 #define DTM_FLAG_NO_FINAL_CHECK 0x1 /* skip the float64 residual sweep            */
