@@ -350,10 +350,12 @@ __device__ inline bool stop_update(StopState& s, const KOpts& o, double change, 
     // The check sweep's residual will be about the next change, contr times
     // this one: fire when that one is predicted to pass.  A check that fails
     // costs nothing extra (its output is the next iterate), and the check
-    // never comes later than when this change itself passes.
+    // never comes later than when this change itself passes.  Without a
+    // check the iterate at hand is the answer, so this change must pass.
+    const double ahead = o.final_check ? s.contr : 1.0;
     const bool fire = (o.stop_rule == DTM_STOP_CHANGE)
                           ? (change < o.tol)
-                          : (change == 0.0 || (s.iter >= 2 && change * gain * s.contr <= o.safety * o.tol));
+                          : (change == 0.0 || (s.iter >= 2 && change * gain * ahead <= o.safety * o.tol));
     if (fire || s.stalled) {
       if (o.final_check) {
         s.check_next = 1;

@@ -348,3 +348,28 @@ def test_banded_matches_one_block_path():
     assert np.all(ia["status"] == 0) and np.all(ib["status"] == 0)
     for p in range(len(scenes)):
         assert np.abs(a[off[p]:off[p + 1]] - b[off[p]:off[p + 1]]).sum() < 1e-6
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_batched_stop_rules_and_no_final_check(dt):
+    """The batched solve (one-block and banded pixels in one plan) under the
+    change rule (config 1's rule) and with the float64 check switched off:
+    the change rule at 1e-12 reaches the oracle to 1e-9 in float64; without
+    the check, no pixel reports a check sweep and the iterate still sits
+    within the float32 floor of the oracle."""
+    d = lib()
+    scenes = np.concatenate([sc.random_small(20, seed=171), sc.batched_uniform(4, seed=172)])
+    tiles = d.tiles(fused_max_bins=128, band_rows=64)
+    if dt == "f64":
+        pi, info, off = run_batched(scenes, dt, solve_opts=d.opts(tol=1e-12, stop_rule=d.DTM_STOP_CHANGE),
+                                    tiles=tiles)
+        assert np.all(info["status"] == 0)
+        for p, (s, v) in enumerate(zip(scenes, split(pi, off))):
+            assert np.abs(v - oracle_pi(s)).sum() <= 1e-9, (p, s)
+    else:
+        pi, info, off = run_batched(scenes, dt, solve_opts=d.opts(tol=1e-6, flags=d.DTM_FLAG_NO_FINAL_CHECK),
+                                    tiles=tiles)
+        assert np.all(info["status"] == 0)
+        assert not np.any(info["flags"] & d.DTM_INFO_CHECKED)
+        for p, (s, v) in enumerate(zip(scenes, split(pi, off))):
+            assert np.abs(v - oracle_pi(s)).sum() <= 1e-5, (p, s)
