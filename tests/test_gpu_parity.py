@@ -373,3 +373,38 @@ def test_batched_stop_rules_and_no_final_check(dt):
         assert not np.any(info["flags"] & d.DTM_INFO_CHECKED)
         for p, (s, v) in enumerate(zip(scenes, split(pi, off))):
             assert np.abs(v - oracle_pi(s)).sum() <= 1e-5, (p, s)
+
+
+def test_banded_warm_start_and_fallbacks():
+    """Warm starts on a plan that mixes one-block and banded pixels: a close
+    start saves sweeps on both paths; a rejected start (negative, NaN, all
+    zero) falls back to uniform and is flagged on the pixel it belongs to."""
+    d = lib()
+    scenes = np.concatenate([sc.random_small(6, seed=181), sc.batched_uniform(4, seed=182)])
+    tiles = d.tiles(fused_max_bins=128, band_rows=64)
+    ref = [oracle_pi(s) for s in scenes]
+    big = np.array([int(s["n_bins"]) > 128 for s in scenes])
+    assert big.any() and (~big).any()
+    rng = np.random.default_rng(2)
+    x0 = np.concatenate([r * (1 + 0.01 * rng.standard_normal(r.size)) for r in ref])
+    _, info_u, off = run_batched(scenes, "f32", tiles=tiles)
+    pi_w, info_w, _ = run_batched(scenes, "f32", tiles=tiles,
+                                  x0=torch.tensor(x0, dtype=torch.float32, device="cuda"))
+    assert np.all(info_w["status"] == 0)
+    assert not np.any(info_w["flags"] & d.DTM_INFO_WARM_REJECTED)
+    for sel in (big, ~big):
+        assert info_w["iterations"][sel].sum() < info_u["iterations"][sel].sum()
+    for r, v in zip(ref, split(pi_w, off)):
+        assert np.abs(v - r).sum() <= TOL_F32
+    bad = x0.copy()
+    rejected = [int(np.flatnonzero(~big)[0]), int(np.flatnonzero(big)[0]), int(np.flatnonzero(big)[-1])]
+    bad[off[rejected[0]] + 1] = -1.0
+    bad[off[rejected[1]] + 5] = np.nan
+    bad[off[rejected[2]]:off[rejected[2] + 1]] = 0.0
+    pi_b, info_b, _ = run_batched(scenes, "f32", tiles=tiles,
+                                  x0=torch.tensor(bad, dtype=torch.float32, device="cuda"))
+    assert np.all(info_b["status"] == 0)
+    flagged = (info_b["flags"] & d.DTM_INFO_WARM_REJECTED) != 0
+    assert sorted(np.flatnonzero(flagged).tolist()) == sorted(rejected)
+    for r, v in zip(ref, split(pi_b, off)):
+        assert np.abs(v - r).sum() <= TOL_F32
