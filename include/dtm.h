@@ -220,7 +220,8 @@ int dtm_stationary_pdf(const void* P_dev, int32_t n, int64_t ld, dtm_dtype dt,
  * autotuned defaults. */
 typedef struct dtm_tile_config {
   int32_t fused_threads;   /* threads per workgroup of the one-block solver: 256 or 512 */
-  int32_t fused_unroll;    /* rows in flight per thread in a sweep: 2, 4 or 8           */
+  int32_t fused_unroll;    /* rows in flight per thread in a one-block sweep: 2, 4 or 8
+                              (the banded sweep keeps 16 column vectors in flight)     */
   int32_t fused_max_bins;  /* pixels with n_b above this take the banded path (>= 2)    */
   int32_t band_rows;       /* rows per workgroup in the banded sweep, multiple of 16,
                               at most 8192 (0 = 1024)                                  */

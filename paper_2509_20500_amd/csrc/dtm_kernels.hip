@@ -506,7 +506,7 @@ __global__ __launch_bounds__(BT) void k_band_init(const PixelMeta* __restrict__ 
   }
 }
 
-template <typename T, int BT, int CPT, int U>
+template <typename T, int BT, int CPT>
 __global__ __launch_bounds__(BT) void k_band_sweep(const PixelMeta* __restrict__ metas,
                                                    const BandItem* __restrict__ items,
                                                    const T* __restrict__ colf,
@@ -519,7 +519,10 @@ __global__ __launch_bounds__(BT) void k_band_sweep(const PixelMeta* __restrict__
                                                    int first) {
   using V = typename Vec<T>::type;
   constexpr int VN = Vec<T>::n;
-  constexpr int UE = (U * CPT <= 8) ? U : (8 / CPT > 0 ? 8 / CPT : 1);
+  // 16 column vectors in flight per thread (twice the one-block solver's):
+  // once most pixels have converged, the last ones are swept by a handful of
+  // items, and an item's rate is bounded by the bytes it keeps in flight.
+  constexpr int UE = 16 / CPT;
   extern __shared__ __align__(16) unsigned char smem[];
   T* xs = reinterpret_cast<T*>(smem);
   const BandItem it = items[blockIdx.x];
@@ -1217,11 +1220,10 @@ int launch_banded(const dtm_plan* plan, int t0, int t1, const PixelMeta* metas, 
   int rc = DTM_OK;
   void (*sweep)(const PixelMeta*, const BandItem*, const T*, const double*, const T*, T*, const T*,
                 const SolveState*, double*, int, int) = nullptr;
-  const int u = plan->tiles.fused_unroll;
   switch (plan->band_cpt) {
-    case 1: sweep = u == 2 ? k_band_sweep<T, BT, 1, 2> : u == 4 ? k_band_sweep<T, BT, 1, 4> : k_band_sweep<T, BT, 1, 8>; break;
-    case 2: sweep = u == 2 ? k_band_sweep<T, BT, 2, 2> : u == 4 ? k_band_sweep<T, BT, 2, 4> : k_band_sweep<T, BT, 2, 8>; break;
-    default: sweep = u == 2 ? k_band_sweep<T, BT, 4, 2> : u == 4 ? k_band_sweep<T, BT, 4, 4> : k_band_sweep<T, BT, 4, 8>; break;
+    case 1: sweep = k_band_sweep<T, BT, 1>; break;
+    case 2: sweep = k_band_sweep<T, BT, 2>; break;
+    default: sweep = k_band_sweep<T, BT, 4>; break;
   }
   for (int t = t0; t < t1; ++t) {
     hipLaunchKernelGGL(sweep, dim3(nitems), dim3(BT), lds, st, metas, items, colf, scal, invs, pool,
