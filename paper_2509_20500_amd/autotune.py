@@ -33,15 +33,15 @@ def candidates(scenes):
     """The search space, pruned to shapes that differ for these scenes."""
     n_max = int(np.max(scenes["n_bins"]))
     out, seen = [], set()
-    for unroll, fmax, band, cpt in itertools.product((4, 8), (1024, 2048, 4096), (256, 1024, 8192),
-                                                     (1, 4)):
+    for threads, unroll, fmax, band, cpt in itertools.product((256, 512), (4, 8), (1024, 2048, 4096),
+                                                              (256, 1024, 8192), (1, 4)):
         eff_fmax = min(fmax, n_max)
         big = n_max > fmax
-        sig = (unroll, eff_fmax, band if big else 0, cpt if big else 0)
+        sig = (threads, unroll, eff_fmax, band if big else 0, cpt if big else 0)
         if sig in seen:
             continue
         seen.add(sig)
-        out.append(dtm.tiles(fused_threads=256, fused_unroll=unroll, fused_max_bins=fmax,
+        out.append(dtm.tiles(fused_threads=threads, fused_unroll=unroll, fused_max_bins=fmax,
                              band_rows=band, band_cpt=cpt))
     return out
 
