@@ -219,7 +219,9 @@ int dtm_stationary_pdf(const void* P_dev, int32_t n, int64_t ld, dtm_dtype dt,
 /* Launch shape of the batched kernels.  Zero fields take the built-in or
  * autotuned defaults. */
 typedef struct dtm_tile_config {
-  int32_t fused_threads;   /* threads per workgroup of the one-block solver: 256 or 512 */
+  int32_t fused_threads;   /* threads per workgroup of the one-block solver: 256 or 512
+                              (0 = 512 if a one-block pixel has more than 1024 bins,
+                              else 256)                                                 */
   int32_t fused_unroll;    /* rows in flight per thread in a one-block sweep: 2, 4 or 8
                               (the banded sweep keeps 16 column vectors in flight)     */
   int32_t fused_max_bins;  /* pixels with n_b above this take the banded path (>= 2)    */

@@ -187,7 +187,8 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   dtm_tile_config tc;
   std::memset(&tc, 0, sizeof(tc));
   if (tiles) tc = *tiles;
-  if (tc.fused_threads == 0) tc.fused_threads = 256;
+  const bool auto_threads = tc.fused_threads == 0;  // settled once the one-block pixels are known
+  if (auto_threads) tc.fused_threads = 256;
   if (tc.fused_unroll == 0) tc.fused_unroll = 8;
   if (tc.fused_max_bins == 0) tc.fused_max_bins = 2048;
   if (tc.band_rows == 0) tc.band_rows = 1024;
@@ -308,6 +309,10 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
     }
   }
   plan->part_elems = acc_part;
+  // A one-block pixel is streamed by one workgroup, whose rate is bounded by
+  // the bytes its threads keep in flight: pixels above 1024 bins get twice
+  // the threads by default.
+  if (auto_threads && plan->max_n_small > 1024) plan->tiles.fused_threads = 512;
   const size_t es = dtype_size(dt);
   size_t off = 0;
   plan->off_meta = off;

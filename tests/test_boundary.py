@@ -127,6 +127,21 @@ def test_plan_layout_and_offsets(d):
     plan.close()
 
 
+def test_default_one_block_threads(d):
+    """256 threads per one-block pixel up to 1024 bins, 512 once a one-block
+    pixel is wider; an explicit choice is kept."""
+    def threads(scenes, **kw):
+        plan = d.Plan(scenes, "f32", tiles=d.tiles(**kw) if kw else None)
+        t = plan.tiles.fused_threads
+        plan.close()
+        return t
+    uneven = sc.batched_uneven(200)
+    assert threads(sc.batched_uniform(8)) == 256
+    assert threads(uneven) == 512
+    assert threads(uneven, fused_max_bins=1024) == 256
+    assert threads(uneven, fused_threads=256) == 256
+
+
 def test_plan_rejects_bad_inputs(d):
     scenes = sc.batched_uniform(8).copy()
     scenes["n_bins"][3] = 1
