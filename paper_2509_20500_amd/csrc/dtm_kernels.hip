@@ -598,6 +598,24 @@ __global__ __launch_bounds__(BT) void k_band_sweep(const PixelMeta* __restrict__
   }
 }
 
+// Column j's partial sums of `bands` row bands (stride ld), added in band
+// order.  Eight loads are issued ahead of their adds, so the dependent chain
+// of additions does not wait on each load in turn; the order of the
+// additions, and so the result, is that of the plain loop.
+__device__ inline double band_sum(const double* __restrict__ p, int64_t ld, int bands) {
+  double s = 0.0;
+  int b = 0;
+  for (; b + 8 <= bands; b += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[static_cast<int64_t>(b + u) * ld];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; b < bands; ++b) s += p[static_cast<int64_t>(b) * ld];
+  return s;
+}
+
 template <typename T, int BT>
 __global__ __launch_bounds__(BT) void k_band_combine(const PixelMeta* __restrict__ metas,
                                                      const int32_t* __restrict__ big,
@@ -619,8 +637,7 @@ __global__ __launch_bounds__(BT) void k_band_combine(const PixelMeta* __restrict
   double* dp = dprev + m.vec_off;
   double sy = 0.0, rs = 0.0;
   for (int j = threadIdx.x; j < n; j += BT) {
-    double y = 0.0;
-    for (int b = 0; b < m.bands; ++b) y += pp[static_cast<int64_t>(b) * m.ld + j];
+    const double y = band_sum(pp + j, m.ld, m.bands);
     sy += y;
     rs += fabs(y - static_cast<double>(x[j]));
   }
@@ -628,8 +645,7 @@ __global__ __launch_bounds__(BT) void k_band_combine(const PixelMeta* __restrict
   const double inv = 1.0 / sy;
   double ch = 0.0, dd = 0.0, ddp = 0.0;
   for (int j = threadIdx.x; j < n; j += BT) {
-    double y = 0.0;
-    for (int b = 0; b < m.bands; ++b) y += pp[static_cast<int64_t>(b) * m.ld + j];
+    const double y = band_sum(pp + j, m.ld, m.bands);
     const T xn = static_cast<T>(y * inv);
     const double dj = static_cast<double>(xn) - static_cast<double>(x[j]);
     ch += fabs(dj);
@@ -876,8 +892,7 @@ __global__ __launch_bounds__(BT) void k_combine_cols(const double* __restrict__ 
   const int j = blockIdx.x * BT + threadIdx.x;
   double sy = 0.0, rs = 0.0;
   if (j < n) {
-    double yj = 0.0;
-    for (int b = 0; b < bands; ++b) yj += part[static_cast<int64_t>(b) * part_ld + j];
+    const double yj = band_sum(part + j, part_ld, bands);
     y[j] = yj;
     sy = yj;
     rs = fabs(yj - static_cast<double>(x[j]));
