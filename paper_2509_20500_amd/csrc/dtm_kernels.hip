@@ -616,6 +616,35 @@ __device__ inline double band_sum(const double* __restrict__ p, int64_t ld, int 
   return s;
 }
 
+// band_sum for the U columns j + BT u of one thread at once (8 U loads in
+// flight).  Columns at or past n read column n - 1 instead; their sums are
+// not used.
+template <int U, int BT>
+__device__ inline void band_sums(const double* __restrict__ p, int64_t ld, int bands, int j, int n,
+                                 double (&y)[U]) {
+  int jc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    jc[u] = min(j + BT * u, n - 1);
+    y[u] = 0.0;
+  }
+  int b = 0;
+  for (; b + 8 <= bands; b += 8) {
+    double v[U][8];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[u][k] = p[static_cast<int64_t>(b + k) * ld + jc[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) y[u] += v[u][k];
+  }
+  for (; b < bands; ++b)
+#pragma unroll
+    for (int u = 0; u < U; ++u) y[u] += p[static_cast<int64_t>(b) * ld + jc[u]];
+}
+
 template <typename T, int BT>
 __global__ __launch_bounds__(BT) void k_band_combine(const PixelMeta* __restrict__ metas,
                                                      const int32_t* __restrict__ big,
@@ -635,24 +664,41 @@ __global__ __launch_bounds__(BT) void k_band_combine(const PixelMeta* __restrict
   const double* pp = part + m.part_off;
   T* x = xbuf + m.vec_off;
   double* dp = dprev + m.vec_off;
+  // Columns j = tid, tid + BT, ... in that order (four at a time, so that
+  // their band loads are in flight together).
+  constexpr int UC = 4;
   double sy = 0.0, rs = 0.0;
-  for (int j = threadIdx.x; j < n; j += BT) {
-    const double y = band_sum(pp + j, m.ld, m.bands);
-    sy += y;
-    rs += fabs(y - static_cast<double>(x[j]));
+  for (int j0 = threadIdx.x; j0 < n; j0 += UC * BT) {
+    double y[UC];
+    band_sums<UC, BT>(pp, m.ld, m.bands, j0, n, y);
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int j = j0 + BT * u;
+      if (j < n) {
+        sy += y[u];
+        rs += fabs(y[u] - static_cast<double>(x[j]));
+      }
+    }
   }
   block_sum2<BT>(sy, rs, red);
   const double inv = 1.0 / sy;
   double ch = 0.0, dd = 0.0, ddp = 0.0;
-  for (int j = threadIdx.x; j < n; j += BT) {
-    const double y = band_sum(pp + j, m.ld, m.bands);
-    const T xn = static_cast<T>(y * inv);
-    const double dj = static_cast<double>(xn) - static_cast<double>(x[j]);
-    ch += fabs(dj);
-    dd += dj * dj;
-    ddp += dj * dp[j];
-    dp[j] = dj;
-    x[j] = xn;  // thread-private index: read above by this thread only
+  for (int j0 = threadIdx.x; j0 < n; j0 += UC * BT) {
+    double y[UC];
+    band_sums<UC, BT>(pp, m.ld, m.bands, j0, n, y);
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int j = j0 + BT * u;
+      if (j < n) {
+        const T xn = static_cast<T>(y[u] * inv);
+        const double dj = static_cast<double>(xn) - static_cast<double>(x[j]);
+        ch += fabs(dj);
+        dd += dj * dj;
+        ddp += dj * dp[j];
+        dp[j] = dj;
+        x[j] = xn;  // thread-private index: read above by this thread only
+      }
+    }
   }
   block_sum3<BT>(ch, dd, ddp, red);
   const bool restart = stop_update(s, o, ch, dd, ddp, rs, was_check,
@@ -923,14 +969,30 @@ __global__ __launch_bounds__(BT) void k_combine_finish(const double* __restrict_
   }
   const double inv = 1.0 / sy;
   double ch = 0.0, dd = 0.0, ddp = 0.0;
-  for (int j = threadIdx.x; j < n; j += BT) {
-    const T xn = static_cast<T>(y[j] * inv);
-    const double dj = static_cast<double>(xn) - static_cast<double>(x[j]);
-    ch += fabs(dj);
-    dd += dj * dj;
-    ddp += dj * dprev[j];
-    dprev[j] = dj;
-    x[j] = xn;  // each thread owns its j: no other thread reads it in this launch
+  // columns j = tid, tid + BT, ... in that order, four loaded at a time
+  constexpr int UC = 4;
+  for (int j0 = threadIdx.x; j0 < n; j0 += UC * BT) {
+    double yv[UC], xv[UC], pv[UC];
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int j = min(j0 + BT * u, n - 1);
+      yv[u] = y[j];
+      xv[u] = static_cast<double>(x[j]);
+      pv[u] = dprev[j];
+    }
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int j = j0 + BT * u;
+      if (j < n) {
+        const T xn = static_cast<T>(yv[u] * inv);
+        const double dj = static_cast<double>(xn) - xv[u];
+        ch += fabs(dj);
+        dd += dj * dj;
+        ddp += dj * pv[u];
+        dprev[j] = dj;
+        x[j] = xn;  // each thread owns its j: no other thread reads it in this launch
+      }
+    }
   }
   block_sum3<BT>(ch, dd, ddp, red);
   const bool restart = stop_update(s, o, ch, dd, ddp, rs, was_check,
