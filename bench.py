@@ -621,12 +621,15 @@ def warm_start_workload(args):
     targets, tinfo = solve_targets(train)
     targets = (targets / targets.sum(dim=1, keepdim=True)).contiguous()
     t_targets = time.perf_counter() - t0
+    print(f"warm_start: {train.size} training targets in {t_targets:.1f} s", file=sys.stderr, flush=True)
     net = WarmStartMLP(max_batch=1024, seed=0)
     feat = net.features(train)
     t1 = time.perf_counter()
     hist = net.fit(feat, targets, epochs=args.epochs, lr=3e-3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
+    print(f"warm_start: {args.epochs} epochs in {t_train:.1f} s, loss {hist[0]:.3f} -> {hist[-1]:.3f}",
+          file=sys.stderr, flush=True)
     del targets, feat
 
     held = sc.warm_start_eval()

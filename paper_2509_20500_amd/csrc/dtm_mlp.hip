@@ -65,19 +65,29 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += 16) {
-    // 64 x 16 tiles: thread t loads 4 elements of each
+    // 64 x 16 tiles: thread t loads 4 elements of each, consecutive threads
+    // along the operand's contiguous dimension (k for a row-major A or a
+    // transposed B, the row or column index otherwise), so that the loads
+    // of a wavefront are coalesced
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int idx = tid * 4 + e;  // 0..1023
-      const int r = idx / 16, kk = idx % 16;
-      const int gi = i0 + r, gk = k0 + kk;
-      bf16 va = 0;
-      if (gi < M && gk < K) va = TA ? A[static_cast<int64_t>(gk) * lda + gi] : A[static_cast<int64_t>(gi) * lda + gk];
-      As[r][kk] = va;
-      const int gj = j0 + r;
-      bf16 vb = 0;
-      if (gj < N && gk < K) vb = TB ? B[static_cast<int64_t>(gj) * ldb + gk] : B[static_cast<int64_t>(gk) * ldb + gj];
-      Bs[r][kk] = vb;
+      {
+        const int r = TA ? idx % 64 : idx / 16, kk = TA ? idx / 64 : idx % 16;
+        const int gi = i0 + r, gk = k0 + kk;
+        bf16 va = 0;
+        if (gi < M && gk < K)
+          va = TA ? A[static_cast<int64_t>(gk) * lda + gi] : A[static_cast<int64_t>(gi) * lda + gk];
+        As[r][kk] = va;
+      }
+      {
+        const int r = TB ? idx / 16 : idx % 64, kk = TB ? idx % 16 : idx / 64;
+        const int gj = j0 + r, gk = k0 + kk;
+        bf16 vb = 0;
+        if (gj < N && gk < K)
+          vb = TB ? B[static_cast<int64_t>(gj) * ldb + gk] : B[static_cast<int64_t>(gk) * ldb + gj];
+        Bs[r][kk] = vb;
+      }
     }
     __syncthreads();
     const int kq = 4 * (lane / 16);
@@ -205,13 +215,41 @@ __global__ void k_gelu_back(const float* __restrict__ dh, const float* __restric
   dab[idx] = f2bf(g);
 }
 
-// db[j] = sum_i d[i][j] (fixed order over rows).
-__global__ void k_bias_grad(const float* __restrict__ d, int rows, int cols, float* __restrict__ db) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
+// db[j] = sum_i d[i][j] in a fixed order: a block owns BG_COLS columns; its
+// BG_GROUPS thread groups each add one contiguous chunk of rows in row
+// order (eight loads issued ahead of their adds), and the chunk sums are
+// then added in chunk order.
+constexpr int BG_COLS = 16;
+constexpr int BG_THREADS = 1024;
+constexpr int BG_GROUPS = BG_THREADS / BG_COLS;
+
+__global__ __launch_bounds__(BG_THREADS) void k_bias_grad(const float* __restrict__ d, int rows, int cols,
+                                                          float* __restrict__ db) {
+  __shared__ float part[BG_GROUPS][BG_COLS];
+  const int c = threadIdx.x % BG_COLS, g = threadIdx.x / BG_COLS;
+  const int j = blockIdx.x * BG_COLS + c;
+  const int chunk = (rows + BG_GROUPS - 1) / BG_GROUPS;
+  const int i0 = min(g * chunk, rows), i1 = min(i0 + chunk, rows);
   float s = 0.f;
-  for (int i = 0; i < rows; ++i) s += d[static_cast<int64_t>(i) * cols + j];
-  db[j] = s;
+  if (j < cols) {
+    const float* col = d + j;
+    int i = i0;
+    for (; i + 8 <= i1; i += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = col[static_cast<int64_t>(i + u) * cols];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; i < i1; ++i) s += col[static_cast<int64_t>(i) * cols];
+  }
+  part[g][c] = s;
+  __syncthreads();
+  if (g == 0 && j < cols) {
+    float t = 0.f;
+    for (int q = 0; q < BG_GROUPS; ++q) t += part[q][c];
+    db[j] = t;
+  }
 }
 
 // Adam on the flat float32 parameters; refreshes their bfloat16 copies.
@@ -409,19 +447,22 @@ int dtm_mlp_backward(void* ws, int32_t max_batch, const float* feat_dev, const f
                      P.dz, P.dzb, loss_dev ? loss_dev : P.loss);
   // layer 3: dW3 = H2^T dZ, db3 = sum dZ, dH2 = dZ W3^T
   gemm<true, false, EPI_STORE>(H, OUT, batch, P.h2, H, P.dzb, OUT, P.gw3, OUT, nullptr, nullptr, 0, st);
-  hipLaunchKernelGGL(k_bias_grad, dim3((OUT + 255) / 256), dim3(256), 0, st, P.dz, batch, OUT, P.gb3);
+  hipLaunchKernelGGL(k_bias_grad, dim3((OUT + BG_COLS - 1) / BG_COLS), dim3(BG_THREADS), 0, st, P.dz, batch, OUT,
+                     P.gb3);
   gemm<false, true, EPI_STORE>(batch, H, OUT, P.dzb, OUT, P.w3b, OUT, P.dh2, H, nullptr, nullptr, 0, st);
   hipLaunchKernelGGL(k_gelu_back, dim3((batch * H + 255) / 256), dim3(256), 0, st, P.dh2, P.a2,
                      batch * H, P.da2, P.da2b);
   // layer 2
   gemm<true, false, EPI_STORE>(H, H, batch, P.h1, H, P.da2b, H, P.gw2, H, nullptr, nullptr, 0, st);
-  hipLaunchKernelGGL(k_bias_grad, dim3((H + 255) / 256), dim3(256), 0, st, P.da2, batch, H, P.gb2);
+  hipLaunchKernelGGL(k_bias_grad, dim3((H + BG_COLS - 1) / BG_COLS), dim3(BG_THREADS), 0, st, P.da2, batch, H,
+                     P.gb2);
   gemm<false, true, EPI_STORE>(batch, H, H, P.da2b, H, P.w2b, H, P.dh1, H, nullptr, nullptr, 0, st);
   hipLaunchKernelGGL(k_gelu_back, dim3((batch * H + 255) / 256), dim3(256), 0, st, P.dh1, P.a1,
                      batch * H, P.da1, P.da1b);
   // layer 1
   gemm<true, false, EPI_STORE>(INP, H, batch, P.x0, INP, P.da1b, H, P.gw1, H, nullptr, nullptr, 0, st);
-  hipLaunchKernelGGL(k_bias_grad, dim3((H + 255) / 256), dim3(256), 0, st, P.da1, batch, H, P.gb1);
+  hipLaunchKernelGGL(k_bias_grad, dim3((H + BG_COLS - 1) / BG_COLS), dim3(BG_THREADS), 0, st, P.da1, batch, H,
+                     P.gb1);
   return ok_launch();
 }
 
