@@ -43,18 +43,21 @@ enum Epi { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2 };
 // C[M x N] = op(A)[M x K] op(B)[K x N] with op(A)[i][k] = TA ? A[k*lda+i] :
 // A[i*lda+k] and op(B)[k][j] = TB ? B[j*ldb+k] : B[k*ldb+j].  A 64 x 64 tile
 // per block of 4 wavefronts, each wavefront a 32 x 32 quarter computed as
-// 2 x 2 v_mfma_f32_16x16x16_bf16 tiles; K advances by 16 through LDS.
+// 2 x 2 v_mfma_f32_16x16x16_bf16 tiles; K advances by GK = 64 through LDS
+// (four MFMA steps of 16 per stage, in k order).
 // Lane layout of the 16x16x16 instruction: lane l supplies A[l%16][4(l/16)+r]
 // and B[4(l/16)+r][l%16] (r = 0..3) and receives D[4(l/16)+r][l%16].
 // Out-of-range elements load as zero and are not stored.
+constexpr int GK = 64;
+
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* __restrict__ A,
                                               int lda, const bf16* __restrict__ B, int ldb,
                                               float* __restrict__ C, int ldc,
                                               const float* __restrict__ bias,
                                               bf16* __restrict__ Hout, int ldh) {
-  __shared__ bf16 As[64][16 + 4];
-  __shared__ bf16 Bs[64][16 + 4];  // transposed: Bs[j][k]
+  __shared__ bf16 As[64][GK + 4];
+  __shared__ bf16 Bs[64][GK + 4];  // transposed: Bs[j][k]
   const int tid = threadIdx.x;
   const int lane = tid % 64, wave = tid / 64;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
@@ -64,16 +67,16 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    // 64 x 16 tiles: thread t loads 4 elements of each, consecutive threads
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    // 64 x GK tiles: thread t loads 16 elements of each, consecutive threads
     // along the operand's contiguous dimension (k for a row-major A or a
     // transposed B, the row or column index otherwise), so that the loads
     // of a wavefront are coalesced
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = tid * 4 + e;  // 0..1023
+    for (int e = 0; e < 64 * GK / 256; ++e) {
+      const int idx = tid * (64 * GK / 256) + e;  // 0 .. 64 GK - 1
       {
-        const int r = TA ? idx % 64 : idx / 16, kk = TA ? idx / 64 : idx % 16;
+        const int r = TA ? idx % 64 : idx / GK, kk = TA ? idx / 64 : idx % GK;
         const int gi = i0 + r, gk = k0 + kk;
         bf16 va = 0;
         if (gi < M && gk < K)
@@ -81,7 +84,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
         As[r][kk] = va;
       }
       {
-        const int r = TB ? idx / 16 : idx % 64, kk = TB ? idx % 16 : idx / 64;
+        const int r = TB ? idx / GK : idx % 64, kk = TB ? idx % GK : idx / 64;
         const int gj = j0 + r, gk = k0 + kk;
         bf16 vb = 0;
         if (gj < N && gk < K)
@@ -90,20 +93,23 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
       }
     }
     __syncthreads();
-    const int kq = 4 * (lane / 16);
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      bf16x4 fa;
-      const int ra = wi + a * 16 + lane % 16;
+    for (int ks = 0; ks < GK; ks += 16) {
+      const int kq = ks + 4 * (lane / 16);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) fa[r] = static_cast<short>(As[ra][kq + r]);
+      for (int a = 0; a < 2; ++a) {
+        bf16x4 fa;
+        const int ra = wi + a * 16 + lane % 16;
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        bf16x4 fb;
-        const int cb = wj + b * 16 + lane % 16;
+        for (int r = 0; r < 4; ++r) fa[r] = static_cast<short>(As[ra][kq + r]);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) fb[r] = static_cast<short>(Bs[cb][kq + r]);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa, fb, acc[a][b], 0, 0, 0);
+        for (int b = 0; b < 2; ++b) {
+          bf16x4 fb;
+          const int cb = wj + b * 16 + lane % 16;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) fb[r] = static_cast<short>(Bs[cb][kq + r]);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa, fb, acc[a][b], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
