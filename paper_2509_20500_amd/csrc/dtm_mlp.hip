@@ -50,6 +50,42 @@ enum Epi { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2 };
 // Out-of-range elements load as zero and are not stored.
 constexpr int GK = 64;
 
+typedef uint16_t bf16x8 __attribute__((ext_vector_type(8)));
+
+// Thread tid's share of a 64 x GK operand tile T[r][kk] = op(X)[o + r][k0 + kk]:
+// the 16 elements idx = 16 tid + e.  ALONG_R: X is stored k-major
+// (X[k * ld + i]), the run goes along r; otherwise X[i * ld + k] and the
+// run goes along kk.  Out-of-range elements are zero.
+template <bool ALONG_R>
+__device__ inline void load_run(const bf16* __restrict__ X, int ld, int rows, int K, int o, int k0, int tid,
+                                bf16 (&T)[64][GK + 4]) {
+  const int idx0 = tid * 16;
+  const int r0 = ALONG_R ? idx0 % 64 : idx0 / GK, kk0 = ALONG_R ? idx0 / 64 : idx0 % GK;
+  const int gi0 = o + r0, gk0 = k0 + kk0;
+  const bf16* src = ALONG_R ? X + static_cast<int64_t>(gk0) * ld + gi0 : X + static_cast<int64_t>(gi0) * ld + gk0;
+  const bool full = ALONG_R ? (gk0 < K && gi0 + 16 <= rows) : (gi0 < rows && gk0 + 16 <= K);
+  bf16 v[16];
+  if (full && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+    const bf16x8 a = *reinterpret_cast<const bf16x8*>(src);
+    const bf16x8 b = *reinterpret_cast<const bf16x8*>(src + 8);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      v[e] = a[e];
+      v[8 + e] = b[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int gi = ALONG_R ? gi0 + e : gi0, gk = ALONG_R ? gk0 : gk0 + e;
+      v[e] = (gi < rows && gk < K) ? X[ALONG_R ? static_cast<int64_t>(gk) * ld + gi
+                                               : static_cast<int64_t>(gi) * ld + gk]
+                                   : static_cast<bf16>(0);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) T[ALONG_R ? r0 + e : r0][ALONG_R ? kk0 : kk0 + e] = v[e];
+}
+
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* __restrict__ A,
                                               int lda, const bf16* __restrict__ B, int ldb,
@@ -68,30 +104,12 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += GK) {
-    // 64 x GK tiles: thread t loads 16 elements of each, consecutive threads
-    // along the operand's contiguous dimension (k for a row-major A or a
-    // transposed B, the row or column index otherwise), so that the loads
-    // of a wavefront are coalesced
-#pragma unroll
-    for (int e = 0; e < 64 * GK / 256; ++e) {
-      const int idx = tid * (64 * GK / 256) + e;  // 0 .. 64 GK - 1
-      {
-        const int r = TA ? idx % 64 : idx / GK, kk = TA ? idx / 64 : idx % GK;
-        const int gi = i0 + r, gk = k0 + kk;
-        bf16 va = 0;
-        if (gi < M && gk < K)
-          va = TA ? A[static_cast<int64_t>(gk) * lda + gi] : A[static_cast<int64_t>(gi) * lda + gk];
-        As[r][kk] = va;
-      }
-      {
-        const int r = TB ? idx / GK : idx % 64, kk = TB ? idx % GK : idx / 64;
-        const int gj = j0 + r, gk = k0 + kk;
-        bf16 vb = 0;
-        if (gj < N && gk < K)
-          vb = TB ? B[static_cast<int64_t>(gj) * ldb + gk] : B[static_cast<int64_t>(gk) * ldb + gj];
-        Bs[r][kk] = vb;
-      }
-    }
+    // 64 x GK tiles: thread t loads 16 consecutive elements of each along
+    // the operand's contiguous dimension (k for a row-major A or a
+    // transposed B, the row or column index otherwise): two 16-byte loads
+    // when the run is in range and aligned, else element by element
+    load_run<TA>(A, lda, M, K, i0, k0, tid, As);
+    load_run<!TB>(B, ldb, N, K, j0, k0, tid, Bs);
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 16) {

@@ -20,12 +20,17 @@ def bf16_bits(x):
     return torch.from_numpy(r.view(np.int16).copy()), vals
 
 
+@pytest.mark.parametrize("shape", [(70, 130, 40), (200, 136, 208)])
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
-def test_gemm_bf16_matches_float64(ta, tb):
+def test_gemm_bf16_matches_float64(ta, tb, shape):
+    """Ragged against the 64 x 64 output tiles and the 64-deep K stages; the
+    second shape has every leading dimension a multiple of 8 elements, so
+    that most tile loads take the 16-byte path and the edges the element
+    path."""
     from paper_2509_20500_amd.warmstart import gemm_bf16
     lib()
     rng = np.random.default_rng(3)
-    M, N, K = 70, 130, 40  # ragged against the 64 x 64 x 16 tiles
+    M, N, K = shape
     a = rng.normal(size=(K, M) if ta else (M, K)).astype(np.float32)
     b = rng.normal(size=(N, K) if tb else (K, N)).astype(np.float32)
     A, av = bf16_bits(a)
