@@ -323,6 +323,7 @@ def spectral_workload(args):
         lam, third = ospec.second_eigenvalue(odtm.transition_matrix(scenes[p]))
         if third < 0.9 * abs(lam):
             worst = max(worst, abs(res["lambda2_abs"][p] - abs(lam)))
+    dynamics = single_bin_dynamics(scenes, res, grid=1)
     summary = {}
     for g, td in zip(range(2), (75.0, 95.0)):
         r = res[g * 121:(g + 1) * 121]
@@ -354,7 +355,83 @@ def spectral_workload(args):
                      "time": "whole call (k_spectral + k_mixing_wave)"},
         "lambda2_abs_vs_lapack_sampled_max": worst,
         "section4": summary,
+        "single_bin_dynamics": dynamics,
     }
+
+
+def fit_recurrence(e):
+    """Least-squares two-term recurrence e[t+1] = a e[t] + c e[t-1] over a
+    deviation sequence, each equation scaled by the size of its right-hand
+    terms (the sequence decays by orders of magnitude); returns the modulus
+    and argument of the larger root of z^2 = a z + c (the per-sweep decay
+    and rotation it follows)."""
+    import numpy as np
+    X = np.stack([e[1:-1], e[:-2]], axis=1)
+    w = 1.0 / np.maximum(np.abs(X).max(axis=1), 1e-300)
+    a, c = np.linalg.lstsq(X * w[:, None], e[2:] * w, rcond=None)[0]
+    roots = np.roots([1.0, -a, -c])
+    z = roots[np.argmax(np.abs(roots))]
+    return float(abs(z)), float(abs(np.angle(z)))
+
+
+def single_bin_dynamics(scenes, res, grid, sweeps=40, cells=None):
+    """Section 4's single-bin view: for three pixels of one dead-time grid
+    (the smallest gap, the largest phase, and the largest gap among those
+    with a phase below 0.1 rad), the deviation of the peak bin of the
+    iterate from pi after t = 1 .. sweeps float64 power sweeps from uniform
+    (batched dense solver, stopped after exactly t sweeps), and the decay and
+    rotation per sweep that a two-term recurrence fitted to it follows,
+    beside |lambda_2| and arg lambda_2 from the spectral call."""
+    import numpy as np
+    import torch
+
+    from paper_2509_20500_amd import dtm
+    lo, hi = grid * 121, (grid + 1) * 121
+    r = res[lo:hi]
+    if cells is None:
+        gap = 1.0 - r["lambda2_abs"]
+        near0 = np.flatnonzero(r["lambda2_arg"] < 0.1)
+        cells = [int(np.argmin(gap)), int(np.argmax(r["lambda2_arg"])),
+                 int(near0[np.argmax(gap[near0])]) if near0.size else int(np.argmax(gap))]
+    sel = scenes[lo:hi][cells]
+    traj = []
+    for t in range(1, sweeps + 1):
+        o = dtm.opts(tol=1e-300, max_iter=t, stop_rule=dtm.DTM_STOP_CHANGE)
+        plan = dtm.Plan(sel, "f64", o)
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+        plan.bind(ws)
+        pi = torch.empty(plan.pi_elems, dtype=torch.float64, device="cuda")
+        infos = torch.zeros(plan.n_pixels * 40, dtype=torch.uint8, device="cuda")
+        plan.solve(pi, infos)
+        torch.cuda.synchronize()
+        traj.append(pi.cpu().numpy())
+        off = plan.pi_offsets
+        plan.close()
+    plan = dtm.Plan(sel, "f64", dtm.opts(tol=1e-13))
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.bind(ws)
+    pi = torch.empty(plan.pi_elems, dtype=torch.float64, device="cuda")
+    infos = torch.zeros(plan.n_pixels * 40, dtype=torch.uint8, device="cuda")
+    plan.solve(pi, infos)
+    torch.cuda.synchronize()
+    pis = pi.cpu().numpy()
+    plan.close()
+    out = []
+    for q, cell in enumerate(cells):
+        p_q = pis[off[q]:off[q + 1]]
+        b = int(np.argmax(p_q))
+        e = np.array([x[off[q] + b] for x in traj]) - p_q[b]
+        keep = np.flatnonzero(np.abs(e) > 1e-9 * p_q[b])  # above float64 round-off
+        e_fit = e[: keep[-1] + 1] if keep.size else e[:0]
+        e_fit = e_fit[5:]  # past the first sweeps, where faster modes still show
+        fit = fit_recurrence(e_fit) if e_fit.size >= 6 else (None, None)
+        out.append({"S": float(sel[q]["signal_flux"]), "B": float(sel[q]["background_flux"]),
+                    "dead_time_ns": float(sel[q]["dead_time_ns"]), "bin": b,
+                    "lambda2_abs": float(r["lambda2_abs"][cell]), "lambda2_arg": float(r["lambda2_arg"][cell]),
+                    "fit_decay_per_sweep": fit[0], "fit_rotation_per_sweep": fit[1],
+                    "sweeps_fitted": int(e_fit.size),
+                    "deviation": [float(v) for v in e[:12]]})
+    return out
 
 
 def single_pixel_workload(args):
