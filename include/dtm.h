@@ -240,7 +240,8 @@ typedef struct dtm_plan dtm_plan; /* opaque host object */
 /* Validates every scene (DTM_EINVAL names nothing: use dtm_validate_scene to
  * find the pixel), fixes offsets, pixel order and launch shapes.  Copies the
  * scenes; scenes_host may be freed afterwards.  opt NULL = defaults; tiles
- * NULL = defaults. */
+ * NULL = defaults.  n_pixels >= 1: an empty batch (or scenes_host NULL) is
+ * DTM_EINVAL.  On every error *plan_out is set to NULL. */
 int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt,
                     const dtm_solve_opts* opt, const dtm_tile_config* tiles,
                     dtm_plan** plan_out);

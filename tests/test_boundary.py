@@ -149,6 +149,13 @@ def test_plan_rejects_bad_inputs(d):
         d.Plan(scenes, "f32")
     with pytest.raises(d.DtmError):
         d.Plan(sc.batched_uniform(4), "f32", tiles=d.tiles(fused_threads=300))
+    # an empty batch is an argument error, not an empty plan
+    import ctypes
+    h = ctypes.c_void_p(0xdead)
+    assert d.lib().dtm_plan_create(scenes.ctypes.data, 0, d.DTM_F32, None, None, ctypes.byref(h)) == d.DTM_EINVAL
+    assert h.value is None  # NULL on error
+    with pytest.raises(d.DtmError):
+        d.Plan(scenes[:0], "f32")
     # binding needs a big enough, 256-byte aligned workspace (checked on the host)
     plan = d.Plan(sc.batched_uniform(4), "f32")
     assert d.lib().dtm_plan_bind(plan.handle, 1 << 20, plan.workspace_bytes - 1, None) == d.DTM_ENOSPACE
