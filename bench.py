@@ -323,7 +323,8 @@ def spectral_workload(args):
         lam, third = ospec.second_eigenvalue(odtm.transition_matrix(scenes[p]))
         if third < 0.9 * abs(lam):
             worst = max(worst, abs(res["lambda2_abs"][p] - abs(lam)))
-    dynamics = single_bin_dynamics(scenes, res, grid=1)
+    dynamics = {"td75": single_bin_dynamics(scenes, res, grid=0),
+                "td95": single_bin_dynamics(scenes, res, grid=1)}
     summary = {}
     for g, td in zip(range(2), (75.0, 95.0)):
         r = res[g * 121:(g + 1) * 121]
@@ -375,9 +376,10 @@ def fit_recurrence(e):
 
 
 def single_bin_dynamics(scenes, res, grid, sweeps=40, cells=None):
-    """Section 4's single-bin view: for three pixels of one dead-time grid
-    (the smallest gap, the largest phase, and the largest gap among those
-    with a phase below 0.1 rad), the deviation of the peak bin of the
+    """Section 4's single-bin view: for three pixels of one dead-time grid,
+    chosen among those with |lambda_2| >= 0.5 (slow enough to leave tens of
+    sweeps above float64 round-off): the smallest gap, then the largest and
+    the smallest phase among the others.  Reports the deviation of the peak bin of the
     iterate from pi after t = 1 .. sweeps float64 power sweeps from uniform
     (batched dense solver, stopped after exactly t sweeps), and the decay and
     rotation per sweep that a two-term recurrence fitted to it follows,
@@ -389,10 +391,16 @@ def single_bin_dynamics(scenes, res, grid, sweeps=40, cells=None):
     lo, hi = grid * 121, (grid + 1) * 121
     r = res[lo:hi]
     if cells is None:
-        gap = 1.0 - r["lambda2_abs"]
-        near0 = np.flatnonzero(r["lambda2_arg"] < 0.1)
-        cells = [int(np.argmin(gap)), int(np.argmax(r["lambda2_arg"])),
-                 int(near0[np.argmax(gap[near0])]) if near0.size else int(np.argmax(gap))]
+        slow = np.flatnonzero(r["lambda2_abs"] >= 0.5)
+        if slow.size == 0:
+            slow = np.arange(len(r))
+        arg = r["lambda2_arg"][slow]
+        cells = []
+        for order in (np.argsort(-r["lambda2_abs"][slow], kind="stable"),
+                      np.argsort(-arg, kind="stable"), np.argsort(arg, kind="stable")):
+            pick = next((int(slow[i]) for i in order if int(slow[i]) not in cells), None)
+            if pick is not None:
+                cells.append(pick)
     sel = scenes[lo:hi][cells]
     traj = []
     for t in range(1, sweeps + 1):
