@@ -672,6 +672,45 @@ def pattern_ceiling(n_chunks, chunk_bytes, passes, reps=3):
             "chunk_bytes": chunk_bytes, "reads": passes, "ms": t}
 
 
+def host_inclusive(scenes, dtype, sopts, tiles, ws, reps=3):
+    """The headline step with the host in the loop: plan from the host scene
+    array (validation, offsets, launch shapes), bind (metadata upload, which
+    synchronises), solve, then pi and infos copied over PCIe into pinned host
+    buffers.  The caller-owned workspace is reused; wall clock, median of
+    reps after one warm-up."""
+    import time
+
+    import numpy as np
+    import torch
+
+    from paper_2509_20500_amd import dtm
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    times = []
+    pi_h = infos_h = None
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = dtm.Plan(scenes, dtype, sopts, tiles)
+        plan.bind(ws)
+        pi = torch.empty(plan.pi_elems, dtype=tdt, device="cuda")
+        infos = torch.zeros(plan.n_pixels * 40, dtype=torch.uint8, device="cuda")
+        if pi_h is None:
+            pi_h = torch.empty(plan.pi_elems, dtype=tdt, pin_memory=True)
+            infos_h = torch.empty(plan.n_pixels * 40, dtype=torch.uint8, pin_memory=True)
+        plan.solve(pi, infos)
+        pi_h.copy_(pi, non_blocking=True)
+        infos_h.copy_(infos, non_blocking=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan.close()
+        if r:
+            times.append(t1 - t0)
+    t = float(np.median(times))
+    return {"value": len(scenes) / t, "unit": "pixels/s", "ms": t * 1e3,
+            "what": "plan from host scenes + bind (metadata upload) + solve + pi and infos to pinned host memory",
+            "pi_bytes_to_host": int(pi_h.numel() * pi_h.element_size())}
+
+
 def timed(step, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -996,6 +1035,8 @@ def main():
     if graph:
         graph.close()
     plan.close()
+    if not uneven and not factored and not graph:
+        out["host_inclusive"] = host_inclusive(scenes, args.dtype, sopts, tiles, ws)
     del ws
     if not uneven and not factored and not graph and plan.n_pixels == 4096:
         # the same access pattern without arithmetic, for reading the roofline
