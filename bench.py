@@ -854,6 +854,8 @@ def main():
     ap.add_argument("--variant", default="paper",
                     choices=["paper", "nearest", "bin_mean", "bin_integral", "interp"],
                     help="discretisation of the model (interp needs --solver factored)")
+    ap.add_argument("--start", default="uniform", choices=["uniform", "flux"],
+                    help="dense solver start vector: uniform, or lambda / sum(lambda) (no-dead-time pi)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also time a plain 1 GiB device copy (the reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -900,6 +902,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     sopts.flags |= variant_flags[args.variant]
+    if args.start == "flux":
+        sopts.flags |= dtm.DTM_FLAG_START_FLUX
     plan = dtm.Plan(scenes, args.dtype, sopts, tiles)
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     plan.bind(ws)
@@ -968,6 +972,7 @@ def main():
     desc += (f"{args.dtype} build+sweeps, float64 check, L1<=1e-6" if not factored else
              f"factored solver (no matrix, O(n) float64 sweeps), {args.dtype} output, L1<=1e-6")
     desc += "; HIP graph" if graph else ""
+    desc += "; start lambda/sum(lambda)" if args.start == "flux" and not factored else ""
     desc += f"; model variant {args.variant}" if args.variant != "paper" else ""
     out = {
         "metric": "stationary-PDF pixels/s at N=1024, L1<=1e-6 vs FP64 oracle; % HBM roofline",

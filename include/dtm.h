@@ -97,6 +97,12 @@ typedef struct dtm_scene {
 #define DTM_FLAG_NO_FINAL_CHECK 0x1 /* skip the float64 residual sweep            */
 #define DTM_FLAG_NO_DENSE       0x2 /* plan without the dense matrix pool: only the
                                        factored solver and the spectral analysis */
+/* dtm_solve_batched without a warm start: begin the power iteration from
+ * x0_j = lambda(s_j) / sum_k lambda(s_k), the stationary vector of the
+ * chain without dead time (Section 2.2: registrations are then the arrivals),
+ * instead of the uniform vector.  Same stop rule and float64 check; the
+ * single-pixel and factored solvers start from uniform regardless. */
+#define DTM_FLAG_START_FLUX    0x40
 
 /* Discretisation variants (default: the paper's model, Section 3.4 with
  * Theorem 2's shift and lambda sampled at the bin centres).  With

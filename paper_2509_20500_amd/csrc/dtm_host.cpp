@@ -98,7 +98,7 @@ int fill_opts(const dtm_solve_opts* opt, KOpts* k, int32_t* check_every) {
   if (o.stop_rule != DTM_STOP_CHANGE && o.stop_rule != DTM_STOP_BOUND) return DTM_EINVAL;
   constexpr int32_t kModel =
       DTM_FLAG_SHIFT_NEAREST | DTM_FLAG_SHIFT_INTERP | DTM_FLAG_LAMBDA_BIN_MEAN | DTM_FLAG_BIN_INTEGRAL;
-  if (o.flags & ~(DTM_FLAG_NO_FINAL_CHECK | DTM_FLAG_NO_DENSE | kModel)) return DTM_EINVAL;
+  if (o.flags & ~(DTM_FLAG_NO_FINAL_CHECK | DTM_FLAG_NO_DENSE | DTM_FLAG_START_FLUX | kModel)) return DTM_EINVAL;
   if ((o.flags & DTM_FLAG_SHIFT_NEAREST) && (o.flags & DTM_FLAG_SHIFT_INTERP)) return DTM_EINVAL;
   if ((o.flags & DTM_FLAG_LAMBDA_BIN_MEAN) && (o.flags & DTM_FLAG_BIN_INTEGRAL)) return DTM_EINVAL;
   k->tol = o.tol_l1;
@@ -108,7 +108,7 @@ int fill_opts(const dtm_solve_opts* opt, KOpts* k, int32_t* check_every) {
   k->final_check = (o.flags & DTM_FLAG_NO_FINAL_CHECK) ? 0 : 1;
   k->pad = (o.flags & DTM_FLAG_NO_DENSE) ? 1 : 0;  // no dense pool
   k->model = o.flags & kModel;
-  k->pad2 = 0;
+  k->start_flux = (o.flags & DTM_FLAG_START_FLUX) ? 1 : 0;
   if (check_every) *check_every = o.check_every;
   return DTM_OK;
 }

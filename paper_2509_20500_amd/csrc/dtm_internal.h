@@ -62,7 +62,7 @@ struct KOpts {
   int32_t final_check;
   int32_t pad;    // host only: 1 = the plan has no dense matrix pool
   int32_t model;  // host only: DTM_FLAG_SHIFT_* / LAMBDA_BIN_MEAN / BIN_INTEGRAL
-  int32_t pad2;
+  int32_t start_flux;  // batched dense solver: start from lambda / sum(lambda)
 };
 
 // Convergence bookkeeping of one pixel, shared by both solvers.

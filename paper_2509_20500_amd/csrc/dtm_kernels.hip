@@ -235,11 +235,20 @@ __device__ inline void sweep_rows(const T* __restrict__ mat, int64_t ld, int n, 
 // launches through the workspace; the start vector is derived again, the
 // same way, so the iterates are those of one fused kernel, bit for bit.
 
-// Start vector into xs (LDS): the caller's, validated and normalised, or the
-// uniform one; records the warm start in st.  Ends with a block barrier.
+// Flux at the centre of bin j, lambda(s_j) = S N(s_j; tau, sigma^2) + B / t_r
+// (the model's point sampling; only a start vector is made from it).
+__device__ inline double start_flux_value(const PixelMeta& m, int j) {
+  const double s = (j + 0.5) * (m.t_r / m.n);
+  const double z = (s - m.tau) / m.sigma;
+  return m.S * exp(-0.5 * z * z) / (m.sigma * 2.5066282746310002) + m.B / m.t_r;
+}
+
+// Start vector into xs (LDS): the caller's, validated and normalised; else
+// lambda / sum(lambda) when flux is set; else the uniform one; records the
+// warm start in st.  Ends with a block barrier.
 template <typename T, int BT>
-__device__ inline void start_vector(const PixelMeta& m, const T* __restrict__ x0_packed, T* xs, StopState& st,
-                                    double* red) {
+__device__ inline void start_vector(const PixelMeta& m, const T* __restrict__ x0_packed, int flux, T* xs,
+                                    StopState& st, double* red) {
   const int n = m.n, tid = threadIdx.x;
   if (x0_packed) {
     double sum = 0.0, bad = 0.0;
@@ -257,6 +266,11 @@ __device__ inline void start_vector(const PixelMeta& m, const T* __restrict__ x0
       st.flags |= DTM_INFO_WARM_REJECTED;
       for (int j = tid; j < n; j += BT) xs[j] = static_cast<T>(1.0 / n);
     }
+  } else if (flux) {
+    double sum = 0.0, unused = 0.0;
+    for (int j = tid; j < n; j += BT) sum += start_flux_value(m, j);
+    block_sum2<BT>(sum, unused, red);
+    for (int j = tid; j < n; j += BT) xs[j] = static_cast<T>(start_flux_value(m, j) / sum);
   } else {
     for (int j = tid; j < n; j += BT) xs[j] = static_cast<T>(1.0 / n);
   }
@@ -274,7 +288,8 @@ __global__ __launch_bounds__(BT) void k_solve_build(const PixelMeta* __restrict_
                                                     T* __restrict__ pool,
                                                     const T* __restrict__ x0_packed,
                                                     double* __restrict__ y1,
-                                                    const int32_t* __restrict__ sel, int lds_ld) {
+                                                    const int32_t* __restrict__ sel, int lds_ld,
+                                                    int start_flux) {
   using V = typename Vec<T>::type;
   constexpr int VN = Vec<T>::n;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -296,7 +311,7 @@ __global__ __launch_bounds__(BT) void k_solve_build(const PixelMeta* __restrict_
   __syncthreads();
   StopState st;
   stop_init(st, 0, 0);
-  start_vector<T, BT>(m, x0_packed, xs, st, red);
+  start_vector<T, BT>(m, x0_packed, start_flux, xs, st, red);
 
   T gr[CPT][VN];
   T acc[CPT][VN], cmp[CPT][VN];
@@ -363,7 +378,7 @@ __global__ __launch_bounds__(BT) void k_solve_sweeps(const PixelMeta* __restrict
 
   StopState st;
   stop_init(st, 0, 0);
-  start_vector<T, BT>(m, x0_packed, xs, st, red);
+  start_vector<T, BT>(m, x0_packed, o.start_flux, xs, st, red);
 
   // This thread's columns (clamped to 0 past n: those sums are never used).
   int jc[CPT];
@@ -477,7 +492,7 @@ __global__ __launch_bounds__(BT) void k_band_init(const PixelMeta* __restrict__ 
                                                   const int32_t* __restrict__ big,
                                                   const T* __restrict__ x0_packed,
                                                   T* __restrict__ xbuf, double* __restrict__ dprev,
-                                                  SolveState* __restrict__ states) {
+                                                  SolveState* __restrict__ states, int start_flux) {
   __shared__ double red[3 * BT / kWave];
   const int q = big[blockIdx.x];
   const PixelMeta m = metas[q];
@@ -492,9 +507,16 @@ __global__ __launch_bounds__(BT) void k_band_init(const PixelMeta* __restrict__ 
   }
   block_sum2<BT>(sum, bad, red);
   const bool warm = x0_packed && bad == 0.0 && sum > 0.0 && isfinite(sum);
+  double fsum = 0.0, unused = 0.0;
+  if (!x0_packed && start_flux) {
+    for (int j = threadIdx.x; j < n; j += BT) fsum += start_flux_value(m, j);
+    block_sum2<BT>(fsum, unused, red);
+  }
   for (int j = threadIdx.x; j < n; j += BT) {
     xbuf[m.vec_off + j] =
-        warm ? static_cast<T>(static_cast<double>(x0_packed[m.pi_off + j]) / sum) : static_cast<T>(1.0 / n);
+        warm ? static_cast<T>(static_cast<double>(x0_packed[m.pi_off + j]) / sum)
+             : (!x0_packed && start_flux) ? static_cast<T>(start_flux_value(m, j) / fsum)
+                                          : static_cast<T>(1.0 / n);
     dprev[m.vec_off + j] = 0.0;
   }
   if (threadIdx.x == 0) {
@@ -1215,7 +1237,7 @@ int launch_fused_cpt(const dtm_plan* plan, int phase, int unroll, const PixelMet
   double* y1 = reinterpret_cast<double*>(w + plan->off_dprev);
   if (phase == 0)
     hipLaunchKernelGGL(build, dim3(count), dim3(BT), lds_build, st, metas, colf, invs, scal, pool, x0, y1, sel,
-                       lds_ld);
+                       lds_ld, plan->kopts.start_flux);
   else
     hipLaunchKernelGGL(sweeps, dim3(count), dim3(BT), lds_sweeps, st, metas, pool, x0, y1, pi, infos, sel,
                        plan->kopts, lds_ld);
@@ -1275,7 +1297,7 @@ int launch_band_init(const dtm_plan* plan, const PixelMeta* metas, const T* x0, 
   SolveState* states = reinterpret_cast<SolveState*>(w + plan->off_state);
   const int nbig = static_cast<int>(plan->big_sel.size());
   hipLaunchKernelGGL((k_band_init<T, BT>), dim3(nbig), dim3(BT), 0, st, metas, big, x0, xbuf, dprev,
-                     states);
+                     states, plan->kopts.start_flux);
   return last_launch();
 }
 

@@ -37,6 +37,7 @@ DTM_FLAG_SHIFT_NEAREST = 0x4
 DTM_FLAG_SHIFT_INTERP = 0x8
 DTM_FLAG_LAMBDA_BIN_MEAN = 0x10
 DTM_FLAG_BIN_INTEGRAL = 0x20
+DTM_FLAG_START_FLUX = 0x40
 
 DTM_INFO_WARM_REJECTED = 0x1
 DTM_INFO_RESTARTED = 0x2

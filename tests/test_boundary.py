@@ -106,7 +106,7 @@ def test_argument_errors_before_any_launch(d):
     bad = d.opts(tol=-1.0)
     st, _ = d.dtm_stationary_pdf(fake, 1000, 1000, "f64", bad, None, fake, fake * 4, ws, None)
     assert st == d.DTM_EINVAL
-    for o in (d.opts(max_iter=0), d.opts(safety=0.0), d.opts(stop_rule=7), d.opts(flags=0x40),
+    for o in (d.opts(max_iter=0), d.opts(safety=0.0), d.opts(stop_rule=7), d.opts(flags=0x80),
               d.opts(flags=d.DTM_FLAG_LAMBDA_BIN_MEAN), d.opts(flags=d.DTM_FLAG_SHIFT_INTERP)):
         st, _ = d.dtm_stationary_pdf(fake, 1000, 1000, "f64", o, None, fake, fake * 4, ws, None)
         assert st == d.DTM_EINVAL
@@ -203,7 +203,7 @@ def test_model_shift_matches_oracle_variants(d):
 def test_variant_flags_on_plans(d):
     s = sc.random_small(4, seed=43)
     for flags in (d.DTM_FLAG_SHIFT_NEAREST | d.DTM_FLAG_SHIFT_INTERP,
-                  d.DTM_FLAG_LAMBDA_BIN_MEAN | d.DTM_FLAG_BIN_INTEGRAL, 0x40):
+                  d.DTM_FLAG_LAMBDA_BIN_MEAN | d.DTM_FLAG_BIN_INTEGRAL, 0x80):
         with pytest.raises(d.DtmError):
             d.Plan(s, "f64", d.opts(flags=flags | d.DTM_FLAG_NO_DENSE))
     with pytest.raises(d.DtmError) as e:  # the dense kernels read whole shifted rows

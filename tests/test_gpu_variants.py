@@ -136,7 +136,7 @@ def test_variant_flag_errors():
     d = lib()
     s = sc.random_small(3, seed=173)
     for flags in (d.DTM_FLAG_SHIFT_NEAREST | d.DTM_FLAG_SHIFT_INTERP,
-                  d.DTM_FLAG_LAMBDA_BIN_MEAN | d.DTM_FLAG_BIN_INTEGRAL, 0x40):
+                  d.DTM_FLAG_LAMBDA_BIN_MEAN | d.DTM_FLAG_BIN_INTEGRAL, 0x80):
         o = d.opts(tol=1e-10)
         o.flags |= flags | d.DTM_FLAG_NO_DENSE
         with pytest.raises(d.DtmError):
