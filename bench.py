@@ -854,8 +854,9 @@ def main():
     ap.add_argument("--variant", default="paper",
                     choices=["paper", "nearest", "bin_mean", "bin_integral", "interp"],
                     help="discretisation of the model (interp needs --solver factored)")
-    ap.add_argument("--start", default="uniform", choices=["uniform", "flux"],
-                    help="dense solver start vector: uniform, or lambda / sum(lambda) (no-dead-time pi)")
+    ap.add_argument("--start", default="flux", choices=["uniform", "flux"],
+                    help="dense solver start vector: lambda / sum(lambda), the no-dead-time pi (default), "
+                         "or uniform")
     ap.add_argument("--calibrate", action="store_true",
                     help="also time a plain 1 GiB device copy (the reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -972,7 +973,8 @@ def main():
     desc += (f"{args.dtype} build+sweeps, float64 check, L1<=1e-6" if not factored else
              f"factored solver (no matrix, O(n) float64 sweeps), {args.dtype} output, L1<=1e-6")
     desc += "; HIP graph" if graph else ""
-    desc += "; start lambda/sum(lambda)" if args.start == "flux" and not factored else ""
+    desc += (("; start lambda/sum(lambda)" if args.start == "flux" else "; uniform start")
+             if not factored else "")
     desc += f"; model variant {args.variant}" if args.variant != "paper" else ""
     out = {
         "metric": "stationary-PDF pixels/s at N=1024, L1<=1e-6 vs FP64 oracle; % HBM roofline",
@@ -1021,7 +1023,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (measured_traffic("k_solve_build+k_solve_sweeps", f"batched_uniform_n1024_{args.dtype}")
+            "traffic": (measured_traffic("k_solve_build+k_solve_sweeps",
+                                         f"batched_uniform_n1024_{args.dtype}_start_{args.start}")
                         if (not uneven and plan.n_pixels == 4096 and not graph and not tiles
                             and args.variant == "paper") else None),
             "kernel": ("k_solve_build + k_solve_sweeps" if not uneven
