@@ -68,7 +68,10 @@ typedef enum dtm_dtype { DTM_F64 = 0, DTM_F32 = 1 } dtm_dtype;
  * Valid: t_r > 0, t_d >= 0 (the chain depends on t_d mod t_r only; the Monte
  * Carlo simulator uses t_d itself), sigma > 0, S >= 0, B >= 0, S + B > 0,
  * 2 <= n_b <= DTM_MAX_BINS, reserved == 0, every field finite; otherwise
- * DTM_EINVAL. */
+ * DTM_EINVAL.  Not detected: with B = 0 and a pulse so narrow that
+ * lambda(s_j) underflows to zero at every bin centre (no centre within about
+ * 38 sigma of tau), every row of the matrix is zero and the chain is
+ * undefined; the solvers then return NaN in pi for that pixel. */
 typedef struct dtm_scene {
   double period_ns;       /* t_r */
   double dead_time_ns;    /* t_d */
