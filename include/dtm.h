@@ -71,7 +71,7 @@ typedef enum dtm_dtype { DTM_F64 = 0, DTM_F32 = 1 } dtm_dtype;
  * DTM_EINVAL.  Not detected: with B = 0 and a pulse so narrow that
  * lambda(s_j) underflows to zero at every bin centre (no centre within about
  * 38 sigma of tau), every row of the matrix is zero and the chain is
- * undefined; the solvers then return NaN in pi for that pixel. */
+ * undefined; the output for that pixel is then meaningless (not checked). */
 typedef struct dtm_scene {
   double period_ns;       /* t_r */
   double dead_time_ns;    /* t_d */
