@@ -646,6 +646,20 @@ def copy_calibration(nbytes=1 << 30, reps=10):
             "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def probe_lib():
+    """The bandwidth probe's own library (built beside libdtm.so, not part of
+    the method's C-ABI)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2509_20500_amd", "libdtm_probe.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build with `python -m paper_2509_20500_amd.build`")
+    L = ctypes.CDLL(path)
+    P, I32 = ctypes.c_void_p, ctypes.c_int32
+    L.dtm_stream_probe.restype = ctypes.c_int
+    L.dtm_stream_probe.argtypes = [P, ctypes.c_size_t, I32, I32, P, P]
+    return L
+
+
 def pattern_ceiling(n_chunks, chunk_bytes, passes, reps=3):
     """GB/s of the dense solver's access pattern without its arithmetic
     (dtm_stream_probe): every chunk written once in one launch, then read
@@ -656,14 +670,15 @@ def pattern_ceiling(n_chunks, chunk_bytes, passes, reps=3):
     import torch
 
     from paper_2509_20500_amd import dtm
+    probe = probe_lib()
     buf = torch.empty(n_chunks * chunk_bytes, dtype=torch.uint8, device="cuda")
     sink = torch.zeros(1, dtype=torch.float32, device="cuda")
     lo = max(0, int(math.floor(passes)))
     ms = {}
     for r in (lo, lo + 1):
         def run():
-            dtm.check(dtm.lib().dtm_stream_probe(buf.data_ptr(), chunk_bytes, n_chunks, r, sink.data_ptr(),
-                                                 dtm._stream(None)), "dtm_stream_probe")
+            dtm.check(probe.dtm_stream_probe(buf.data_ptr(), chunk_bytes, n_chunks, r, sink.data_ptr(),
+                                             dtm._stream(None)), "dtm_stream_probe")
         ms[r] = timed(run, reps, 1)
     f = passes - lo
     t = ms[lo] + f * (ms[lo + 1] - ms[lo])
@@ -822,7 +837,8 @@ def warm_start_workload(args):
         "training": {"targets_s": t_targets, "train_s": t_train, "loss_first": hist[0], "loss_last": hist[-1],
                      "targets_all_converged": bool(np.all(tinfo["status"] == 0))},
         "all_converged": bool(np.all(iw["status"] == 0) and np.all(iu["status"] == 0)),
-        "l1_vs_oracle_sampled_max": l1,
+        "l1_vs_oracle_max": l1_report["max"],
+        "l1_vs_oracle": l1_report,
     }
 
 
@@ -841,7 +857,10 @@ def main():
     ap.add_argument("--solver", default="dense", choices=["dense", "factored"],
                     help="dense: the materialised matrix (headline); factored: O(n) sweeps, float64")
     ap.add_argument("--autotune", action="store_true", help="pick tile shapes by timing candidates")
-    ap.add_argument("--check", type=int, default=16, help="pixels compared with the oracle after timing")
+    ap.add_argument("--check", type=int, default=None,
+                    help="pixels compared with the float64 oracle after timing: 0 = every pixel (default "
+                         "for the uniform batch), k > 0 = k sampled pixels (uniform batch) or k pixels of "
+                         "each size (uneven batch, default 4)")
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--single-sample", type=int, default=256,
                     help="pixels timed on the plain single-pixel GPU path (0 = skip)")
@@ -947,21 +966,43 @@ def main():
                  if (factored and not uneven and plan.n_pixels == 4096 and args.variant == "paper"
                      and args.dtype == "f32") else None)
 
-    # correctness gate on sampled pixels (those the dense oracle solves fast)
+    # correctness gate, outside the timed region: every pixel of the uniform
+    # batch against the float64 oracle (a pool of host-core processes); for
+    # the uneven batch, `--check` pixels of each size (the dense oracle at
+    # 8192 bins takes tens of seconds per pixel)
     from oracle import dtm as odtm
+    from oracle import pool as opool
     got = pi.cpu().numpy().astype(np.float64)
     off = plan.pi_offsets
+    vecs = [got[off[p]:off[p + 1]] for p in range(plan.n_pixels)]
     rng = np.random.default_rng(0)
-    small = np.flatnonzero(scenes["n_bins"] <= 2048)
-    l1 = 0.0
-    from oracle import variants as ovar
-    shift_lam = {"paper": ("ceil", "point"), "nearest": ("nearest", "point"), "bin_mean": ("ceil", "bin_mean"),
-                 "bin_integral": ("ceil", "bin_integral"), "interp": ("interp", "point")}[args.variant]
-    for p in rng.choice(small, min(args.check, small.size), replace=False):
-        mat = (odtm.transition_matrix(scenes[p]) if args.variant == "paper"
-               else ovar.transition_matrix_variant(scenes[p], *shift_lam))
-        ref = odtm.stationary_solve(mat)
-        l1 = max(l1, float(np.abs(got[off[p]:off[p + 1]] - ref).sum()))
+    if uneven:
+        per = 4 if args.check is None else args.check
+        sample = np.sort(np.concatenate([
+            rng.choice(np.flatnonzero(scenes["n_bins"] == size), min(per, int(np.sum(scenes["n_bins"] == size))),
+                       replace=False) for size in np.unique(scenes["n_bins"])])) if per > 0 \
+            else np.arange(plan.n_pixels)
+        sample_desc = f"{per} pixels of each size" if per > 0 else "every pixel"
+    else:
+        per = 0 if args.check is None else args.check
+        sample = (np.sort(rng.choice(plan.n_pixels, min(per, plan.n_pixels), replace=False)) if per > 0
+                  else np.arange(plan.n_pixels))
+        sample_desc = f"{sample.size} sampled pixels" if per > 0 else "every pixel"
+    t_check = time.perf_counter()
+    if args.variant == "paper":
+        l1s = opool.l1_many(scenes[sample], [vecs[p] for p in sample])
+    else:
+        from oracle import variants as ovar
+        shift_lam = {"nearest": ("nearest", "point"), "bin_mean": ("ceil", "bin_mean"),
+                     "bin_integral": ("ceil", "bin_integral"), "interp": ("interp", "point")}[args.variant]
+        sample = sample[:16]
+        sample_desc = f"{sample.size} sampled pixels (model variant)"
+        l1s = np.array([float(np.abs(vecs[p] - odtm.stationary_solve(
+            ovar.transition_matrix_variant(scenes[p], *shift_lam))).sum()) for p in sample])
+    t_check = time.perf_counter() - t_check
+    l1_report = {"max": float(l1s.max()), "median": float(np.median(l1s)), "pixels": int(sample.size),
+                 "of": int(plan.n_pixels), "sample": sample_desc,
+                 "oracle": "float64 dense build + LAPACK solve per pixel", "wall_s": t_check}
 
     if uneven:
         desc = ("2048 pixels, N from {512,1024,2048,4096,8192} weighted 16:8:4:2:1, period U[50,200] ns, "
@@ -1036,7 +1077,8 @@ def main():
         "all_converged": bool(np.all(info["status"] == 0)),
         "refined_pixels": int(np.sum((info["flags"] & dtm.DTM_INFO_REFINED) != 0)),
         "max_residual_l1": float(info["residual_l1"].max()),
-        "l1_vs_oracle_sampled_max": l1,
+        "l1_vs_oracle_max": l1_report["max"],
+        "l1_vs_oracle": l1_report,
     }
     if tune_report is not None:
         out["autotune"] = {"cached": tune_report["cached"], "ms": tune_report["ms"]}

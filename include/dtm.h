@@ -68,10 +68,16 @@ typedef enum dtm_dtype { DTM_F64 = 0, DTM_F32 = 1 } dtm_dtype;
  * Valid: t_r > 0, t_d >= 0 (the chain depends on t_d mod t_r only; the Monte
  * Carlo simulator uses t_d itself), sigma > 0, S >= 0, B >= 0, S + B > 0,
  * 2 <= n_b <= DTM_MAX_BINS, reserved == 0, every field finite; otherwise
- * DTM_EINVAL.  Not detected: with B = 0 and a pulse so narrow that
- * lambda(s_j) underflows to zero at every bin centre (no centre within about
- * 38 sigma of tau), every row of the matrix is zero and the chain is
- * undefined; the output for that pixel is then meaningless (not checked). */
+ * DTM_EINVAL.  Also DTM_EINVAL: a scene whose flux underflows at every bin,
+ * which leaves every row of the matrix zero (the chain is undefined).  The
+ * test: the largest g_j = lambda_j exp(-F_j) over the first bin and the three
+ * bins around tau (where g peaks), evaluated on the host in float64 under the
+ * plan's flux sampling, must reach the smallest normal number of the
+ * computing dtype (1.2e-38 float32, 2.2e-308 float64; dtm_validate_scene
+ * checks float64).  With B = 0 and lambda sampled at the centres this
+ * rejects scenes with no centre within about 13 sigma (float32) or
+ * 37 sigma (float64) of tau, the exact distance depending on S / sigma; the
+ * bin-averaged variants keep the pulse's mass and accept them. */
 typedef struct dtm_scene {
   double period_ns;       /* t_r */
   double dead_time_ns;    /* t_d */
@@ -103,8 +109,10 @@ typedef struct dtm_scene {
 /* dtm_solve_batched without a warm start: begin the power iteration from
  * x0_j = lambda(s_j) / sum_k lambda(s_k), the stationary vector of the
  * chain without dead time (Section 2.2: registrations are then the arrivals),
- * instead of the uniform vector.  Same stop rule and float64 check; the
- * single-pixel and factored solvers start from uniform regardless. */
+ * instead of the uniform vector (uniform when that flux underflows at every
+ * centre, which the bin-averaged variants allow).  Same stop rule and
+ * float64 check; the single-pixel and factored solvers start from uniform
+ * regardless. */
 #define DTM_FLAG_START_FLUX    0x40
 
 /* Discretisation variants (default: the paper's model, Section 3.4 with
@@ -376,18 +384,6 @@ int dtm_mc_histograms(const dtm_plan* plan, int32_t runs_per_pixel, int64_t cycl
                       int64_t burn_cycles, uint64_t seed, int32_t lanes_per_run,
                       int32_t segments_per_run, uint32_t* hist_packed_dev, uint32_t* overflow_dev,
                       void* scratch_dev, size_t scratch_bytes, dtm_stream_t stream);
-
-/* Calibration probe, not part of the method: the dense solver's memory
- * access pattern without its arithmetic.  A first launch of n_chunks
- * workgroups writes every chunk_bytes chunk of buf_dev (nontemporal stores),
- * a second one reads each chunk back `reads` times (nontemporal loads), as
- * the batched solve writes every matrix in its build launch and then sweeps
- * them in its sweep launch.  buf_dev holds n_chunks * chunk_bytes bytes (caller
- * owned, contents overwritten); sink_dev is one float that is never written
- * for these values.  chunk_bytes a positive multiple of 16, n_chunks >= 1,
- * reads >= 0, else DTM_EINVAL.  Launch only. */
-int dtm_stream_probe(void* buf_dev, size_t chunk_bytes, int32_t n_chunks, int32_t reads, float* sink_dev,
-                     dtm_stream_t stream);
 
 /* HIP graph of one dtm_solve_batched call: every launch of the solve is
  * captured once and replayed by dtm_graph_launch, which saves the per-launch

@@ -25,12 +25,6 @@ def second_eigenvalue(Pt):
     return complex(lam), float(third)
 
 
-def mixing_distance(Pt, pi, n):
-    """d(n) = max_s (1/2) || e_s P~^n - pi ||_1."""
-    M = np.linalg.matrix_power(np.asarray(Pt, dtype=np.float64), n)
-    return float(0.5 * np.abs(M - pi[None, :]).sum(axis=1).max())
-
-
 def mixing_steps(Pt, pi, eps=0.25, max_steps=10000):
     """Smallest n >= 1 with d(n) <= eps (rows of P~^n advanced one step at a
     time), or -1 if not reached within max_steps."""

@@ -1,4 +1,5 @@
-"""Builds the HIP library ``libdtm.so`` for gfx950, in the package directory.
+"""Builds the HIP library ``libdtm.so`` (the method) and ``libdtm_probe.so``
+(the benchmark's bandwidth probe) for gfx950, in the package directory.
 
     python -m paper_2509_20500_amd.build
 
@@ -18,8 +19,11 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdtm.so")
+PROBE_LIB = os.path.join(PKG, "libdtm_probe.so")
 
-SOURCES = ["dtm_kernels.hip", "dtm_factored.hip", "dtm_mc.hip", "dtm_mlp.hip", "dtm_probe.hip", "dtm_host.cpp"]
+SOURCES = ["dtm_kernels.hip", "dtm_factored.hip", "dtm_mc.hip", "dtm_mlp.hip", "dtm_host.cpp"]
+# the benchmark's bandwidth probe: a library of its own, outside the C-ABI
+PROBE_SOURCES = ["dtm_probe.hip"]
 HEADERS = ["dtm_internal.h", "dtm_device.hpp"]
 
 HIPCC_FLAGS = [
@@ -35,11 +39,10 @@ def hipcc():
     return path
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the library (always; no staleness check) and return its path."""
+def _build_lib(sources, out, verbose):
     objs = []
-    tmp = LIB + ".tmp"
-    for src in SOURCES:
+    tmp = out + ".tmp"
+    for src in sources:
         obj = os.path.join(CSRC, src + ".o")
         cmd = [hipcc(), *HIPCC_FLAGS, "-I" + INCLUDE, "-I" + CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
@@ -53,10 +56,17 @@ def build(verbose: bool = False) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
-    return LIB
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    """Compile both libraries (always; no staleness check) and return the
+    path of the method's library."""
+    _build_lib(PROBE_SOURCES, PROBE_LIB, verbose)
+    return _build_lib(SOURCES, LIB, verbose)
 
 
 if __name__ == "__main__":

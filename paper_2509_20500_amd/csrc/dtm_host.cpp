@@ -10,9 +10,49 @@
 
 namespace dtm {
 
+// Normal tail beyond z on z's side, and the normal mass on [za, zb] from the
+// tails at its ends, each difference taken where it keeps its digits.
+static double host_tail(double z) { return 0.5 * std::erfc(std::fabs(z) * 0.70710678118654752440); }
+static double host_mass(double za, double zb) {
+  const double ta = host_tail(za), tb = host_tail(zb);
+  if (za >= 0.0) return ta - tb;
+  if (zb <= 0.0) return tb - ta;
+  return 1.0 - ta - tb;
+}
+
+// g_j = lambda_j exp(-F_j) of bin j (the column factor of every row of the
+// base matrix, Section 3.4) evaluated on the host in float64, under the
+// flux sampling of lam_mode (0: lambda at the centre; 1: lambda averaged
+// over the bin; 2: lambda e^{-F} averaged over the bin).  F is Theorem 1's
+// cumulative flux with the pulse cut to [0, t_r).
+static double host_g(const dtm_scene& s, int32_t j, int32_t lam_mode) {
+  const double delta = s.period_ns / s.n_bins, is = 1.0 / s.pulse_sigma_ns;
+  const double lo = j * delta, mid = lo + 0.5 * delta, hi = lo + delta;
+  const double z0 = -s.pulse_center_ns * is;
+  const auto F = [&](double t) {
+    return s.signal_flux * host_mass(z0, (t - s.pulse_center_ns) * is) + s.background_flux * t / s.period_ns;
+  };
+  const double Fm = F(mid);
+  if (lam_mode == 0) {
+    const double z = (mid - s.pulse_center_ns) * is;
+    const double lam = s.signal_flux * std::exp(-0.5 * z * z) * (0.39894228040143267794 * is) +
+                       s.background_flux / s.period_ns;
+    return lam * std::exp(-Fm);
+  }
+  const double dF = s.signal_flux * host_mass((lo - s.pulse_center_ns) * is, (hi - s.pulse_center_ns) * is) +
+                    s.background_flux * delta / s.period_ns;
+  if (lam_mode == 1) return dF / delta * std::exp(-Fm);
+  return std::exp(-F(lo)) * -std::expm1(-dF) / delta;
+}
+
 // Scene validation (Section 2.2's theta; flux model of Eq. arrival_flux).
 // float32 needs exp(-Lambda) and exp(-F) to stay normal: S + B <= 80.
-int validate_scene(const dtm_scene& s, dtm_dtype dt) {
+// A scene whose flux underflows at every bin leaves every row of the matrix
+// zero (the chain is undefined): g_j is largest at the first bin (the
+// background term, where F is smallest) or at a bin next to the pulse
+// centre, so those bins decide; below the smallest normal number of the
+// dtype the scene is rejected.
+int validate_scene(const dtm_scene& s, dtm_dtype dt, int32_t lam_mode) {
   const double v[6] = {s.period_ns, s.dead_time_ns, s.pulse_center_ns,
                        s.pulse_sigma_ns, s.signal_flux, s.background_flux};
   for (double x : v)
@@ -24,7 +64,21 @@ int validate_scene(const dtm_scene& s, dtm_dtype dt) {
   if (dt != DTM_F32 && dt != DTM_F64) return DTM_EINVAL;
   const double lim = dt == DTM_F32 ? 80.0 : 700.0;
   if (s.signal_flux + s.background_flux > lim) return DTM_ENOTSUP;
+  if (degenerate_scene(s, dt, lam_mode)) return DTM_EINVAL;
   return DTM_OK;
+}
+
+bool degenerate_scene(const dtm_scene& s, dtm_dtype dt, int32_t lam_mode) {
+  const double tiny = dt == DTM_F32 ? 1.17549435082228750797e-38 : 2.22507385850720138309e-308;
+  // the background alone keeps every g_j >= (B / t_r) exp(-Lambda), Lambda <= S + B
+  if (s.background_flux / s.period_ns * std::exp(-(s.signal_flux + s.background_flux)) >= tiny) return false;
+  const double delta = s.period_ns / s.n_bins;
+  const double jt = std::floor(s.pulse_center_ns / delta);
+  const int32_t jc = static_cast<int32_t>(std::min<double>(std::max<double>(jt, 0.0), s.n_bins - 1));
+  double gmax = host_g(s, 0, lam_mode);
+  for (int32_t j = std::max(jc - 1, 0); j <= std::min(jc + 1, s.n_bins - 1); ++j)
+    gmax = std::max(gmax, host_g(s, j, lam_mode));
+  return !(gmax >= tiny);
 }
 
 // l = ceil(x_d / Delta) mod n_b (Theorem 2) with x_d = t_d mod t_r.
@@ -176,7 +230,7 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   // the dense kernels take whole rows of the shifted matrix
   if ((ko.model & DTM_FLAG_SHIFT_INTERP) && !ko.pad) return DTM_ENOTSUP;
   for (int32_t p = 0; p < n_pixels; ++p) {
-    st = validate_scene(scenes_host[p], dt);
+    st = validate_scene(scenes_host[p], dt, model_lam_mode(ko.model));
     if (st != DTM_OK) return st;
   }
   dtm_plan* plan = new (std::nothrow) dtm_plan();

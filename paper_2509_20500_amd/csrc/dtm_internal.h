@@ -91,7 +91,8 @@ struct SolveState {
 };
 
 // Shared host logic (dtm_host.cpp).
-int validate_scene(const dtm_scene& s, dtm_dtype dt);
+int validate_scene(const dtm_scene& s, dtm_dtype dt, int32_t lam_mode = 0);
+bool degenerate_scene(const dtm_scene& s, dtm_dtype dt, int32_t lam_mode);
 int shift_bins(const dtm_scene& s, int32_t* l);
 void model_shift(const dtm_scene& s, int32_t model, int32_t* l, double* frac);
 int32_t model_lam_mode(int32_t model);

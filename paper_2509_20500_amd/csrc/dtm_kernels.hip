@@ -270,7 +270,11 @@ __device__ inline void start_vector(const PixelMeta& m, const T* __restrict__ x0
     double sum = 0.0, unused = 0.0;
     for (int j = tid; j < n; j += BT) sum += start_flux_value(m, j);
     block_sum2<BT>(sum, unused, red);
-    for (int j = tid; j < n; j += BT) xs[j] = static_cast<T>(start_flux_value(m, j) / sum);
+    // a flux that underflows at every centre (possible under the bin-averaged
+    // variants, whose matrix is still defined) falls back to uniform
+    const bool ok = sum > 0.0 && isfinite(sum);
+    for (int j = tid; j < n; j += BT)
+      xs[j] = ok ? static_cast<T>(start_flux_value(m, j) / sum) : static_cast<T>(1.0 / n);
   } else {
     for (int j = tid; j < n; j += BT) xs[j] = static_cast<T>(1.0 / n);
   }
@@ -512,11 +516,12 @@ __global__ __launch_bounds__(BT) void k_band_init(const PixelMeta* __restrict__ 
     for (int j = threadIdx.x; j < n; j += BT) fsum += start_flux_value(m, j);
     block_sum2<BT>(fsum, unused, red);
   }
+  // as in start_vector: no usable flux at the centres falls back to uniform
+  const bool flux = !x0_packed && start_flux && fsum > 0.0 && isfinite(fsum);
   for (int j = threadIdx.x; j < n; j += BT) {
     xbuf[m.vec_off + j] =
         warm ? static_cast<T>(static_cast<double>(x0_packed[m.pi_off + j]) / sum)
-             : (!x0_packed && start_flux) ? static_cast<T>(start_flux_value(m, j) / fsum)
-                                          : static_cast<T>(1.0 / n);
+             : flux ? static_cast<T>(start_flux_value(m, j) / fsum) : static_cast<T>(1.0 / n);
     dprev[m.vec_off + j] = 0.0;
   }
   if (threadIdx.x == 0) {

@@ -3,6 +3,17 @@
 // block writes its chunk (as the build launch writes one pixel's matrix),
 // then one in which every block streams its chunk back `reads` times with
 // nontemporal loads (the sweep launch).
+//
+// A measurement aid, not part of the method: it is built into its own
+// library, libdtm_probe.so, which only the benchmark and its test load.
+//
+//   int dtm_stream_probe(void* buf_dev, size_t chunk_bytes, int32_t n_chunks,
+//                        int32_t reads, float* sink_dev, void* stream);
+//
+// buf_dev holds n_chunks * chunk_bytes bytes (caller owned, overwritten);
+// sink_dev is one float that is never written for these values.  chunk_bytes
+// a positive multiple of 16, n_chunks >= 1, reads >= 0, else DTM_EINVAL
+// (nothing launched); a failed launch gives DTM_EHIP.  Launch only.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>

@@ -58,7 +58,7 @@ SYMBOLS = [
     "dtm_mlp_workspace_layout", "dtm_mlp_features", "dtm_mlp_sync_bf16", "dtm_mlp_forward",
     "dtm_mlp_backward", "dtm_mlp_adam", "dtm_mlp_gemm_bf16",
     "dtm_solve_factored_batched", "dtm_spectral_scratch_bytes", "dtm_spectral_batched",
-    "dtm_mc_scratch_bytes", "dtm_mc_histograms", "dtm_stream_probe",
+    "dtm_mc_scratch_bytes", "dtm_mc_histograms",
 ]
 
 
@@ -172,7 +172,6 @@ def lib() -> ctypes.CDLL:
         "dtm_mc_scratch_bytes": (_SZ, [_P, _I32, _I64, _I32]),
         "dtm_mc_histograms": (ctypes.c_int, [_P, _I32, _I64, _I64, ctypes.c_uint64, _I32, _I32, _P, _P, _P,
                                              _SZ, _P]),
-        "dtm_stream_probe": (ctypes.c_int, [_P, _SZ, _I32, _I32, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

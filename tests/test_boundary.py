@@ -78,6 +78,41 @@ def test_zero_flux_is_rejected(d):
     assert d.dtm_validate_scene(s) == d.DTM_EINVAL
 
 
+def test_degenerate_scenes_are_rejected(d):
+    """B = 0 with no bin centre near a narrow pulse: lambda_j exp(-F_j)
+    underflows at every centre and every row of the matrix would be zero.
+    At 50 sigma it does so in both dtypes; at 25 sigma only in float32.  The
+    bin-averaged flux keeps the pulse's mass, so those plans are accepted."""
+    far = sc.scene(period=100.0, dead_time=33.0, center=30.0, sigma=0.01, signal=1.0, background=0.0,
+                   n_bins=100)
+    mid = far.copy()
+    mid["pulse_center_ns"] = 30.25
+    near = far.copy()
+    near["pulse_center_ns"] = 30.4  # 10 sigma from the centre 30.5
+    assert d.dtm_validate_scene(far) == d.DTM_EINVAL
+    assert d.dtm_validate_scene(mid) == d.DTM_OK
+    assert d.dtm_validate_scene(near) == d.DTM_OK
+    for s, dt in ((far, "f32"), (far, "f64"), (mid, "f32")):
+        with pytest.raises(d.DtmError) as e:
+            d.Plan(s, dt)
+        assert e.value.status == d.DTM_EINVAL
+    d.Plan(mid, "f64").close()
+    d.Plan(near, "f32").close()
+    for flag in (d.DTM_FLAG_LAMBDA_BIN_MEAN, d.DTM_FLAG_BIN_INTEGRAL):
+        for dt in ("f32", "f64"):
+            d.Plan(far, dt, d.opts(flags=flag)).close()
+    # the single-pixel entry points validate the same way before any launch
+    fake = 1 << 20
+    ws = d.dtm_workspace_bytes(100, "f32")
+    assert d.dtm_build_transition(far, "f64", fake, 100, fake, ws * 2, None) == d.DTM_EINVAL
+    assert d.dtm_build_transition(mid, "f32", fake, 100, fake, ws, None) == d.DTM_EINVAL
+    # a background keeps every scene defined
+    bg = far.copy()
+    bg["background_flux"] = 1e-3
+    assert d.dtm_validate_scene(bg) == d.DTM_OK
+    d.Plan(bg, "f32").close()
+
+
 def test_float32_flux_limit(d):
     s = sc.scene(signal=60.0, background=30.0, n_bins=64)
     assert d.dtm_validate_scene(s) == d.DTM_OK

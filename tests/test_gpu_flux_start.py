@@ -58,3 +58,26 @@ def test_flux_start_saves_sweeps_on_headline_pixels():
     vs = split(pf, off)
     for p in range(0, 256, 16):
         assert np.abs(vs[p] - oracle_pi(scenes[p])).sum() <= TOL_F32, p
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_flux_start_falls_back_to_uniform_without_flux_at_the_centres(dt):
+    """B = 0 and a pulse 50 sigma from the nearest centres: lambda(s_j) is zero
+    at every centre, but the bin-averaged variants keep the pulse's mass and
+    define the chain.  The flux start then has nothing to normalise and must
+    fall back to the uniform vector (one-block and banded pixels)."""
+    from oracle import variants as ovar
+    d = lib()
+    s = sc.scene(period=100.0, dead_time=33.0, center=30.0, sigma=0.01, signal=1.0, background=0.0,
+                 n_bins=100)
+    scenes = np.concatenate([s, s])
+    tol = TOL_F32 if dt == "f32" else TOL_F64
+    for flag, lam in ((d.DTM_FLAG_LAMBDA_BIN_MEAN, "bin_mean"), (d.DTM_FLAG_BIN_INTEGRAL, "bin_integral")):
+        o = _flux_opts(dt)
+        o.flags |= flag
+        ref = odtm.stationary_solve(ovar.transition_matrix_variant(s, "ceil", lam))
+        for tiles in (None, d.tiles(fused_max_bins=64, band_rows=32)):
+            pi, info, off = run_batched(scenes, dt, solve_opts=o, tiles=tiles)
+            assert np.all(info["status"] == 0), info
+            for v in split(pi, off):
+                assert np.all(np.isfinite(v)) and np.abs(v - ref).sum() <= tol

@@ -230,21 +230,36 @@ def test_no_dead_time_continuum_limit():
 # ---------------------------------------------------------------------------
 def test_factorised_left_product_matches_dense():
     """(x P~)_j = g_j [c U_{N-1} + (1-c) U_j] with u_k = x_{(k-l) mod N}/Rh_k
-    and U the prefix sum of u (derived from Eqs. (Eij_ours) and the row shift)."""
+    and U the prefix sum of u (derived from Eqs. (Eij_ours) and the row shift),
+    as the O(n) reference of the large-pixel GPU tests writes it."""
+    from factored_ref import factored_power, factored_product, residual_l1
     rng = np.random.default_rng(7)
-    for s in sc.random_small(5, seed=3):
+    scenes = np.concatenate([sc.random_small(5, seed=3),
+                             sc.scene(dead_time=41.3, center=33.0, sigma=0.3, signal=2.0,
+                                      background=0.4, n_bins=300),
+                             sc.scene(dead_time=130.0, period=80.0, center=5.0, sigma=1.0,
+                                      signal=0.3, background=3.0, n_bins=97)])
+    for s in scenes:
         n = int(s["n_bins"])
         Pt = dtm.transition_matrix(s)
-        lam, F, Lam, l = dtm.bin_tables(s)
-        g = lam * np.exp(-F)
-        c = math.exp(-Lam)
-        Rh = c * g.sum() + (1 - c) * np.cumsum(g[::-1])[::-1]
         x = rng.uniform(0, 1, n)
-        u = np.roll(x, l) / Rh
-        U = np.cumsum(u)
-        y = g * (c * U[-1] + (1 - c) * U)
+        y = factored_product(s)(x)
         ref = x @ Pt
         assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+        pi = dtm.stationary_solve(Pt)
+        xp, ok = factored_power(s, tol=1e-15)
+        assert ok and np.abs(xp - pi).sum() < 1e-12
+        assert residual_l1(s, pi) < 1e-13
+        # the same product with the roll the wrong way round disagrees with
+        # the dense matrix (whenever the two directions differ)
+        lam, F, Lam, l = dtm.bin_tables(s)
+        if l != 0 and 2 * l != n:
+            g = lam * np.exp(-F)
+            c = math.exp(-Lam)
+            Rh = c * g.sum() + (1 - c) * np.cumsum(g[::-1])[::-1]
+            U = np.cumsum(np.roll(x, -l) / Rh)
+            wrong = g * (c * U[-1] + (1 - c) * U)
+            assert np.abs(wrong - ref).max() > 1e-6 * np.abs(ref).max()
 
 
 def test_power_iteration_reaches_solve():
