@@ -35,7 +35,8 @@ def test_headline_line_keeps_the_contract():
     assert 0.3 < rf["frac"] < 1.0
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["unit"] == "pixels/s"
-    assert d["all_converged"] and d["l1_vs_oracle_sampled_max"] <= 1e-6
+    assert d["all_converged"] and d["l1_vs_oracle_max"] <= 1e-6
+    assert d["l1_vs_oracle"]["pixels"] == 2 and d["l1_vs_oracle"]["of"] == 4096
     # the host-in-the-loop rate is reported beside value, never as it
     hi = d["host_inclusive"]
     assert hi["unit"] == "pixels/s" and 0 < hi["value"] < 1.2 * d["value"]  # timing noise of a 2-step run
