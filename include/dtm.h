@@ -231,6 +231,25 @@ int dtm_stationary_pdf(const void* P_dev, int32_t n, int64_t ld, dtm_dtype dt,
                        void* workspace_dev, size_t workspace_bytes,
                        dtm_solve_info* info_host, dtm_stream_t stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): dtm_stationary_pdf with the solver's
+ * workspace taken from a static device array of the library instead of a
+ * caller's buffer.  Same arguments, results and synchronisation as
+ * dtm_stationary_pdf without workspace_dev / workspace_bytes.  Allocates
+ * nothing: no hipMalloc, hipFree or allocating library call.  The array holds
+ * DTM_NOALLOC_SCRATCH_BYTES bytes per GPU (held from the first call on that
+ * GPU until the process ends), enough for n <= DTM_NOALLOC_MAX_BINS in either
+ * dtype; a larger n returns DTM_ENOSPACE before any launch.  Every call on
+ * one GPU shares that GPU's array and the solver initialises what it reads
+ * on every call; calls that overlap on one GPU (two streams or two threads)
+ * race on the array and must be serialised by the caller.  The device is the
+ * current one (hipSetDevice); `stream` must belong to it. */
+#define DTM_NOALLOC_MAX_BINS 8192
+#define DTM_NOALLOC_SCRATCH_BYTES 8912896 /* 8.5 MiB */
+int dtm_stationary_pdf_noalloc(const void* P_dev, int32_t n, int64_t ld, dtm_dtype dt,
+                               const dtm_solve_opts* opt, const void* x0_dev, void* pi_dev,
+                               dtm_solve_info* info_host, dtm_stream_t stream);
+
 /* ---- batched: many pixels with uneven n_b and dead time ------------------ */
 
 /* Launch shape of the batched kernels.  Zero fields take the built-in or

@@ -97,12 +97,12 @@ int shift_bins(const dtm_scene& s, int32_t* l);
 void model_shift(const dtm_scene& s, int32_t model, int32_t* l, double* frac);
 int32_t model_lam_mode(int32_t model);
 int fill_opts(const dtm_solve_opts* opt, KOpts* k, int32_t* check_every);
-inline int32_t padded_ld(int32_t n, dtm_dtype dt) {
+constexpr int32_t padded_ld(int32_t n, dtm_dtype dt) {
   const int32_t vec = dt == DTM_F32 ? 4 : 2;  // 16 bytes
   return (n + vec - 1) / vec * vec;
 }
-inline size_t dtype_size(dtm_dtype dt) { return dt == DTM_F32 ? 4 : 8; }
-inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t dtype_size(dtm_dtype dt) { return dt == DTM_F32 ? 4 : 8; }
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Workspace layout of the single-pixel entry points (byte offsets).  The
 // band count caps the float64 partial sums at 256 rows of length ld; y and
@@ -111,8 +111,8 @@ struct SingleLayout {
   int32_t ld, bands, band_rows, cblocks;
   size_t off_colf, off_invs, off_x, off_scal, off_state, off_dprev, off_part, off_y, off_bsum, total;
 };
-inline SingleLayout single_layout(int32_t n, dtm_dtype dt) {
-  SingleLayout L;
+constexpr SingleLayout single_layout(int32_t n, dtm_dtype dt) {
+  SingleLayout L{};
   L.ld = padded_ld(n, dt);
   const int32_t want = (n + 63) / 64;
   L.bands = want < 256 ? want : 256;

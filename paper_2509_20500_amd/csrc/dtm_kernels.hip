@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "dtm_device.hpp"
@@ -1459,6 +1460,67 @@ int batched_build(const dtm_plan* plan, void* out, int shifted, hipStream_t st) 
                          1, st);
 }
 
+// Single-pixel power iteration on a caller's matrix with the solver's
+// workspace at ws (argument checks first; nothing is launched on an error).
+int stationary_pdf_in(const void* P_dev, int32_t n, int64_t ld, dtm_dtype dt, const dtm_solve_opts* opt,
+                      const void* x0_dev, void* pi_dev, void* ws, size_t ws_bytes, dtm_solve_info* info_host,
+                      dtm_stream_t stream) {
+  if (!P_dev || !pi_dev || !ws) return DTM_EINVAL;
+  if (dt != DTM_F32 && dt != DTM_F64) return DTM_EINVAL;
+  if (n < 2 || n > DTM_MAX_BINS || ld < n) return DTM_EINVAL;
+  KOpts ko;
+  int32_t ce = 4;
+  int rc = fill_opts(opt, &ko, &ce);
+  if (rc) return rc;
+  if (ko.model) return DTM_EINVAL;  // discretisation flags describe a plan's matrices, not a given one
+  const SingleLayout L = single_layout(n, dt);
+  if (ws_bytes < L.total) return DTM_ENOSPACE;
+  const size_t es = dtype_size(dt);
+  if (overlaps(pi_dev, es * n, ws, L.total)) return DTM_EALIAS;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dt == DTM_F32)
+    return single_solve<float>(static_cast<const float*>(P_dev), n, ld, ko, ce, static_cast<const float*>(x0_dev),
+                               static_cast<float*>(pi_dev), ws, info_host, st, dt);
+  return single_solve<double>(static_cast<const double*>(P_dev), n, ld, ko, ce,
+                              static_cast<const double*>(x0_dev), static_cast<double*>(pi_dev), ws, info_host, st,
+                              dt);
+}
+
+// The single-pixel solver's workspace for dtm_stationary_pdf_noalloc, sized
+// for DTM_NOALLOC_MAX_BINS bins in either dtype.  Every GPU holds its own
+// copy; host code reaches it only through the address hipGetSymbolAddress
+// returns on that device (the array's name is a host-side stand-in).
+constexpr size_t kNoallocBytes =
+    std::max(single_layout(DTM_NOALLOC_MAX_BINS, DTM_F64).total, single_layout(DTM_NOALLOC_MAX_BINS, DTM_F32).total);
+static_assert(kNoallocBytes <= DTM_NOALLOC_SCRATCH_BYTES, "no-allocation scratch larger than documented");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) on its first use.
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return DTM_EHIP;
+  if (dev >= kMaxDevices) return DTM_ENOTSUP;
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* p = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = p;
+  });
+  if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev]) return DTM_EHIP;
+  *out = g_scratch_ptr[dev];
+  return DTM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1532,26 +1594,18 @@ int dtm_stationary_pdf(const void* P_dev, int32_t n, int64_t ld, dtm_dtype dt,
                        const dtm_solve_opts* opt, const void* x0_dev, void* pi_dev,
                        void* workspace_dev, size_t workspace_bytes, dtm_solve_info* info_host,
                        dtm_stream_t stream) {
-  if (!P_dev || !pi_dev || !workspace_dev) return DTM_EINVAL;
-  if (dt != DTM_F32 && dt != DTM_F64) return DTM_EINVAL;
-  if (n < 2 || n > DTM_MAX_BINS || ld < n) return DTM_EINVAL;
-  KOpts ko;
-  int32_t ce = 4;
-  int rc = fill_opts(opt, &ko, &ce);
+  return stationary_pdf_in(P_dev, n, ld, dt, opt, x0_dev, pi_dev, workspace_dev, workspace_bytes, info_host,
+                           stream);
+}
+
+int dtm_stationary_pdf_noalloc(const void* P_dev, int32_t n, int64_t ld, dtm_dtype dt,
+                               const dtm_solve_opts* opt, const void* x0_dev, void* pi_dev,
+                               dtm_solve_info* info_host, dtm_stream_t stream) {
+  if (n > DTM_NOALLOC_MAX_BINS) return DTM_ENOSPACE;
+  void* ws = nullptr;
+  const int rc = noalloc_scratch(&ws);
   if (rc) return rc;
-  if (ko.model) return DTM_EINVAL;  // discretisation flags describe a plan's matrices, not a given one
-  const SingleLayout L = single_layout(n, dt);
-  if (workspace_bytes < L.total) return DTM_ENOSPACE;
-  const size_t es = dtype_size(dt);
-  if (overlaps(pi_dev, es * n, workspace_dev, L.total)) return DTM_EALIAS;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (dt == DTM_F32)
-    return single_solve<float>(static_cast<const float*>(P_dev), n, ld, ko, ce,
-                               static_cast<const float*>(x0_dev), static_cast<float*>(pi_dev),
-                               workspace_dev, info_host, st, dt);
-  return single_solve<double>(static_cast<const double*>(P_dev), n, ld, ko, ce,
-                              static_cast<const double*>(x0_dev), static_cast<double*>(pi_dev),
-                              workspace_dev, info_host, st, dt);
+  return stationary_pdf_in(P_dev, n, ld, dt, opt, x0_dev, pi_dev, ws, kNoallocBytes, info_host, stream);
 }
 
 int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes, dtm_stream_t stream) {

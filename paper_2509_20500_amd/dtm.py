@@ -46,6 +46,8 @@ DTM_INFO_STALLED = 0x8
 DTM_INFO_REFINED = 0x10
 
 DTM_MAX_BINS = 65536
+DTM_NOALLOC_MAX_BINS = 8192
+DTM_NOALLOC_SCRATCH_BYTES = 8912896
 
 SYMBOLS = [
     "dtm_status_string", "dtm_version", "dtm_validate_scene", "dtm_shift_bins", "dtm_model_shift",
@@ -58,7 +60,7 @@ SYMBOLS = [
     "dtm_mlp_workspace_layout", "dtm_mlp_features", "dtm_mlp_sync_bf16", "dtm_mlp_forward",
     "dtm_mlp_backward", "dtm_mlp_adam", "dtm_mlp_gemm_bf16",
     "dtm_solve_factored_batched", "dtm_spectral_scratch_bytes", "dtm_spectral_batched",
-    "dtm_mc_scratch_bytes", "dtm_mc_histograms",
+    "dtm_mc_scratch_bytes", "dtm_mc_histograms", "dtm_stationary_pdf_noalloc",
 ]
 
 
@@ -150,6 +152,8 @@ def lib() -> ctypes.CDLL:
         "dtm_build_transition": (ctypes.c_int, [ctypes.POINTER(Scene), ctypes.c_int, _P, _I64, _P, _SZ, _P]),
         "dtm_stationary_pdf": (ctypes.c_int, [_P, _I32, _I64, ctypes.c_int, ctypes.POINTER(SolveOpts),
                                               _P, _P, _P, _SZ, ctypes.POINTER(SolveInfo), _P]),
+        "dtm_stationary_pdf_noalloc": (ctypes.c_int, [_P, _I32, _I64, ctypes.c_int, ctypes.POINTER(SolveOpts),
+                                                      _P, _P, ctypes.POINTER(SolveInfo), _P]),
         "dtm_plan_create": (ctypes.c_int, [_P, _I32, ctypes.c_int, ctypes.POINTER(SolveOpts),
                                            ctypes.POINTER(TileConfig), ctypes.POINTER(_P)]),
         "dtm_plan_destroy": (None, [_P]),
@@ -293,6 +297,14 @@ def dtm_stationary_pdf(P_ptr, n, ld, dtype, solve_opts, x0_ptr, pi_ptr, ws_ptr, 
     return st, info
 
 
+def dtm_stationary_pdf_noalloc(P_ptr, n, ld, dtype, solve_opts, x0_ptr, pi_ptr, stream):
+    info = SolveInfo()
+    o = solve_opts if solve_opts is not None else None
+    st = lib().dtm_stationary_pdf_noalloc(P_ptr, n, ld, _dt(dtype), ctypes.byref(o) if o is not None else None,
+                                          x0_ptr, pi_ptr, ctypes.byref(info), stream)
+    return st, info
+
+
 # ---- tensor helpers --------------------------------------------------------------
 
 def _ptr(t):
@@ -334,6 +346,14 @@ def stationary_pdf(P, pi, ws, solve_opts=None, x0=None, stream=None) -> SolveInf
     st, info = dtm_stationary_pdf(_ptr(P), n, P.stride(0), _dt(P.dtype), solve_opts, _ptr(x0),
                                   _ptr(pi), _ptr(ws), ws.numel(), _stream(stream))
     check(st, "dtm_stationary_pdf")
+    return info
+
+
+def stationary_pdf_noalloc(P, pi, solve_opts=None, x0=None, stream=None) -> SolveInfo:
+    n = P.shape[0]
+    st, info = dtm_stationary_pdf_noalloc(_ptr(P), n, P.stride(0), _dt(P.dtype), solve_opts, _ptr(x0), _ptr(pi),
+                                          _stream(stream))
+    check(st, "dtm_stationary_pdf_noalloc")
     return info
 
 

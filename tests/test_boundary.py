@@ -38,6 +38,14 @@ def test_every_declared_symbol_is_exported(d):
     assert sorted(d.SYMBOLS) == names
 
 
+def test_noalloc_solver_rejects_oversize_before_any_hip_call(d):
+    # n above the static scratch's capacity is refused before the device is
+    # looked up, so this runs without a GPU (the pointers are never read)
+    n = d.DTM_NOALLOC_MAX_BINS + 1
+    st, _ = d.dtm_stationary_pdf_noalloc(1 << 20, n, n, "f32", d.opts(), None, 1 << 21, 0)
+    assert st == d.DTM_ENOSPACE
+
+
 def test_struct_layouts(d):
     assert ctypes.sizeof(d.Scene) == sc.SCENE_DTYPE.itemsize == 56
     assert ctypes.sizeof(d.SolveOpts) == 32
