@@ -306,7 +306,7 @@ def spectral_workload(args):
     plan.bind(ws)
     eps = 0.25
     scratch = torch.empty(plan.spectral_scratch_bytes(True), dtype=torch.uint8, device="cuda")
-    out = torch.zeros(plan.n_pixels * 48, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(plan.n_pixels * dtm.SPECTRAL_INFO_BYTES, dtype=torch.uint8, device="cuda")
     ms = timed(lambda: plan.spectral(out, scratch, eps, 10000), args.steps, args.warmup)
     res = dtm.spectral_to_numpy(out)
     plan.close()
@@ -321,8 +321,7 @@ def spectral_workload(args):
     worst = 0.0
     for p in rng.choice(len(scenes), min(args.check, 4), replace=False):
         lam, third = ospec.second_eigenvalue(odtm.transition_matrix(scenes[p]))
-        if third < 0.9 * abs(lam):
-            worst = max(worst, abs(res["lambda2_abs"][p] - abs(lam)))
+        worst = max(worst, abs(res["lambda2_abs"][p] - abs(lam)))
     dynamics = {"td75": single_bin_dynamics(scenes, res, grid=0),
                 "td95": single_bin_dynamics(scenes, res, grid=1)}
     summary = {}

@@ -154,6 +154,9 @@ typedef struct dtm_solve_opts {
 #define DTM_INFO_CHECKED       0x4 /* residual_l1 comes from a float64 check sweep       */
 #define DTM_INFO_STALLED       0x8 /* changes stopped shrinking at the precision floor   */
 #define DTM_INFO_REFINED      0x10 /* float32 could not certify: re-solved in float64    */
+#define DTM_INFO_CONTINUED    0x20 /* banded pixel still running after the launched
+                                      sweeps: finished in float64 on the factored
+                                      product of the same matrix                   */
 typedef struct dtm_solve_info {
   int32_t iterations;  /* sweeps performed (each reads the matrix once)         */
   int32_t status;
@@ -263,8 +266,11 @@ typedef struct dtm_tile_config {
   int32_t fused_max_bins;  /* pixels with n_b above this take the banded path (>= 2)    */
   int32_t band_rows;       /* rows per workgroup in the banded sweep, multiple of 16,
                               at most 8192 (0 = 1024)                                  */
-  int32_t band_sweeps;     /* sweeps launched for banded pixels (<= max_iter); a banded
-                              pixel not converged by then ends with DTM_ENOTCONV       */
+  int32_t band_sweeps;     /* dense sweeps launched for banded pixels (<= max_iter;
+                              0 = min(max_iter, 64)); a banded pixel still running
+                              after them continues from its iterate in float64 with
+                              the factored product (see dtm_solve_factored_batched)
+                              up to max_iter sweeps in all (DTM_INFO_CONTINUED)       */
   int32_t band_cpt;        /* column vectors per thread in the banded sweep: 1, 2 or 4
                               (0 = 1); a workgroup covers 256 x band_cpt x (4 float /
                               2 double) columns of its rows                            */
@@ -305,7 +311,8 @@ int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes,
  * iteration with the plan's stop rule, float64 residual check.  Pixels up to
  * fused_max_bins take one workgroup each in two launches: every matrix is
  * written (with the first sweep taken on the way), then the remaining sweeps
- * read them; larger pixels take the banded launches.  Writes pi
+ * read them; larger pixels take the banded launches (band_sweeps dense
+ * sweeps, then the float64 continuation for those still running).  Writes pi
  * packed by pi_offsets (dtype of the plan) and one dtm_solve_info per pixel
  * to infos_dev (device memory, plan order = input order).  x0_packed_dev
  * (packed like pi, dtype of the plan) seeds the iteration; NULL = uniform.
@@ -334,24 +341,38 @@ int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, 
  * eigenvalue lambda_2 of P~ (magnitude and phase; the spectral gap is
  * 1 - |lambda_2|) and, when mixing_eps > 0, the empirical mixing steps
  *   min n : max_s (1/2) || e_s P~^n - pi ||_1 <= mixing_eps   (n <= max_steps <= 2^30,
- * else -1).  lambda_2 comes from power iteration on the deflated operator
- * x -> x P~ - (x 1) pi with a two-term recurrence fit
- * v_{t+2} = a v_{t+1} + b v_t, whose roots are the dominant eigenvalue (or
- * complex pair); the fit is reliable when |lambda_3| is clearly below
- * |lambda_2|.  Uses the factored operator (O(n) per step per vector).  The
- * mixing search advances every start state: for plans whose pixels have at
- * most 1024 bins on chip (the call then only launches); above that in the
- * scratch (2 n^2 float64 per pixel), and the call then copies the per-pixel
- * scratch offsets from the host and synchronises `stream` before
- * returning.  scratch_bytes below
+ * else -1).  lambda_2 comes from orthogonal iteration with Rayleigh-Ritz on
+ * the deflated operator x -> x P~ - (x 1) pi: a subspace of six vectors
+ * (n - 1 when n <= 6) is mapped by the operator and re-orthonormalised each
+ * step, and the eigenvalues of its 6 x 6 Rayleigh quotient (Ritz values)
+ * approach the six eigenvalues of largest modulus after the Perron value;
+ * lambda_2 is the largest, which converges at the rate |lambda_8 / lambda_2|
+ * per step, so a third eigenvalue close to lambda_2 in modulus does not
+ * slow or spoil it.  The search stops when lambda_2 and |lambda_3| have each
+ * moved by at most 1e-13 (1 + |lambda_2|) in two successive steps; max_steps also caps
+ * the steps of this search (DTM_SPECTRAL_UNSETTLED when reached).  Uses the
+ * factored operator (O(n) per step per vector).  The mixing search advances
+ * every start state: for plans whose pixels have at most 1024 bins on chip
+ * (the call then only launches); above that in the scratch (2 n^2 float64
+ * per pixel), and the call then copies the per-pixel scratch offsets from
+ * the host and synchronises `stream` before returning.  scratch_bytes below
  * dtm_spectral_scratch_bytes gives DTM_ENOSPACE; max_steps outside
  * [1, 2^30] or an unbound plan DTM_EINVAL. */
+#define DTM_SPECTRAL_UNSETTLED 0x1 /* lambda_2 had not settled after max_steps steps  */
+#define DTM_SPECTRAL_TIED      0x2 /* another eigenvalue, not lambda_2's conjugate,
+                                      has lambda_2's modulus to 1e-9 (relative): the
+                                      modulus stands, the phase is one of several   */
 typedef struct dtm_spectral_info {
-  double lambda2_re, lambda2_im;  /* lambda_2 (one of a conjugate pair: im >= 0) */
-  double lambda2_abs, lambda2_arg;/* |lambda_2| and its phase in [0, pi]          */
-  double fit_residual;            /* relative residual of the recurrence fit      */
-  int32_t iterations;             /* deflated power steps                          */
-  int32_t mixing_steps;           /* -1: not reached / not requested              */
+  double lambda2_re, lambda2_im;  /* lambda_2 (one of a conjugate pair: im >= 0)    */
+  double lambda2_abs, lambda2_arg;/* |lambda_2| and its phase in [0, pi]             */
+  double lambda3_abs;             /* largest modulus among the other Ritz values
+                                     (lambda_2's conjugate left out): |lambda_3|    */
+  double ritz_change;             /* change of lambda_2 (or of |lambda_3|, the larger)
+                                     over the last step                              */
+  int32_t iterations;             /* subspace steps                                  */
+  int32_t mixing_steps;           /* -1: not reached / not requested                 */
+  int32_t flags;                  /* DTM_SPECTRAL_*                                  */
+  int32_t reserved;
 } dtm_spectral_info;
 size_t dtm_spectral_scratch_bytes(const dtm_plan* plan, int32_t with_mixing);
 int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_steps,

@@ -12,16 +12,18 @@ import numpy as np
 
 def second_eigenvalue(Pt):
     """lambda_2: the eigenvalue of largest modulus after the Perron value 1
-    (for a conjugate pair, the member with nonnegative imaginary part)."""
+    (for a conjugate pair, the member with nonnegative imaginary part), and
+    the largest modulus among the remaining eigenvalues once lambda_2's
+    conjugate is left out (0 when none remain)."""
     w = np.linalg.eigvals(np.asarray(Pt, dtype=np.float64))
     k = int(np.argmin(np.abs(w - 1.0)))
-    rest = np.delete(w, k)
-    order = np.argsort(-np.abs(rest), kind="stable")
-    lam = rest[order[0]]
-    if lam.imag < 0:
-        lam = np.conj(lam)
-    third = np.abs(rest[order[2]]) if rest.size > 2 and abs(rest[order[1]] - np.conj(lam)) < 1e-9 \
-        else (np.abs(rest[order[1]]) if rest.size > 1 else 0.0)
+    rest = list(np.delete(w, k)[np.argsort(-np.abs(np.delete(w, k)), kind="stable")])
+    first = rest.pop(0)
+    if first.imag != 0.0 and rest:
+        # a complex eigenvalue comes with its conjugate: leave that one out
+        rest.pop(int(np.argmin([abs(z - np.conj(first)) for z in rest])))
+    lam = first if first.imag >= 0 else np.conj(first)
+    third = max((abs(z) for z in rest), default=0.0)
     return complex(lam), float(third)
 
 

@@ -19,8 +19,12 @@ namespace dtm {
 namespace fact {
 
 constexpr int BT = 256;
-constexpr int NVEC = 8;  // float64 vectors of ld per pixel in the scratch region
 constexpr int kLdsMaxN = 2048;  // largest n whose solver vectors are kept in LDS
+constexpr int KSUB = 6;  // dimension of the subspace that the lambda_2 search iterates
+// float64 vectors of ld per pixel in the spectral scratch: the solver's five
+// (g, 1/S, pi, u, last difference), then the subspace basis Q and its image W
+constexpr int NVEC = 5 + 2 * KSUB;
+constexpr int kSpecLdsMaxN = 1024;  // largest n whose spectral vectors are kept in LDS
 
 // Chunk of bins owned by this thread (the layout of pixel_tables).
 __device__ inline void chunk_of(int n, int& j0, int& j1) {
@@ -64,7 +68,7 @@ __device__ void apply(int n, int l, double f, const double* x, const double* g, 
 }
 
 struct Vecs {
-  double *g, *invs, *x, *u, *dp, *v0, *v1, *v2;
+  double *g, *invs, *x, *u, *dp;
 };
 
 __device__ inline Vecs vecs(double* fact, int64_t vec_elems, const PixelMeta& m) {
@@ -75,9 +79,6 @@ __device__ inline Vecs vecs(double* fact, int64_t vec_elems, const PixelMeta& m)
   V.x = base + 2 * vec_elems;
   V.u = base + 3 * vec_elems;
   V.dp = base + 4 * vec_elems;
-  V.v0 = base + 5 * vec_elems;
-  V.v1 = base + 6 * vec_elems;
-  V.v2 = base + 7 * vec_elems;
   return V;
 }
 
@@ -90,34 +91,14 @@ __device__ double tables(const PixelMeta& m, const Vecs& V, double* red) {
   return c;
 }
 
-// Power iteration on the factored matrix (every sweep float64, treated as a
-// check sweep by the stop rule).  x0 (may be null) seeds it.  Returns the
-// stop state; V.x holds the result.
-template <typename TI>
-__device__ StopState power(const PixelMeta& m, const Vecs& V, double c, const TI* x0, KOpts o,
+// Power iteration on the factored matrix from the iterate in V.x (every
+// sweep float64, treated as a check sweep by the stop rule), continuing the
+// stop state st.  Returns when st is done; V.x holds the result.
+__device__ void power_loop(const PixelMeta& m, const Vecs& V, double c, KOpts o, StopState& st,
                            double* red) {
   const int n = m.n;
   int j0, j1;
   chunk_of(n, j0, j1);
-  StopState st;
-  stop_init(st, 0, 0);
-  double sum = 0.0, bad = 0.0;
-  if (x0) {
-    for (int j = j0; j < j1; ++j) {
-      const double v = static_cast<double>(x0[j]);
-      if (!(v >= 0.0) || !isfinite(v)) bad += 1.0;
-      else sum += v;
-    }
-  }
-  block_sum2<BT>(sum, bad, red);
-  const bool warm = x0 && bad == 0.0 && sum > 0.0 && isfinite(sum);
-  if (x0 && !warm) st.flags |= DTM_INFO_WARM_REJECTED;
-  st.warm = warm ? 1 : 0;
-  for (int j = j0; j < j1; ++j) {
-    V.x[j] = warm ? static_cast<double>(x0[j]) / sum : 1.0 / n;
-    V.dp[j] = 0.0;
-  }
-  __syncthreads();
   for (;;) {
     apply(n, m.l, m.frac, V.x, V.g, V.invs, c, V.u, V.u, red);
     double sy = 0.0, rs = 0.0;
@@ -147,7 +128,91 @@ __device__ StopState power(const PixelMeta& m, const Vecs& V, double c, const TI
     __syncthreads();
     if (st.done) break;
   }
+}
+
+// Starting vector in V.x: x0 normalised to sum 1 when it is a positive
+// finite vector, else uniform.  Returns whether x0 was taken.
+template <typename TI>
+__device__ bool power_start(const PixelMeta& m, const Vecs& V, const TI* x0, double* red) {
+  const int n = m.n;
+  int j0, j1;
+  chunk_of(n, j0, j1);
+  double sum = 0.0, bad = 0.0;
+  if (x0) {
+    for (int j = j0; j < j1; ++j) {
+      const double v = static_cast<double>(x0[j]);
+      if (!(v >= 0.0) || !isfinite(v)) bad += 1.0;
+      else sum += v;
+    }
+  }
+  block_sum2<BT>(sum, bad, red);
+  const bool warm = x0 && bad == 0.0 && sum > 0.0 && isfinite(sum);
+  for (int j = j0; j < j1; ++j) {
+    V.x[j] = warm ? static_cast<double>(x0[j]) / sum : 1.0 / n;
+    V.dp[j] = 0.0;
+  }
+  __syncthreads();
+  return warm;
+}
+
+// Power iteration on the factored matrix from x0 (may be null: uniform).
+// Returns the stop state; V.x holds the result.
+template <typename TI>
+__device__ StopState power(const PixelMeta& m, const Vecs& V, double c, const TI* x0, KOpts o,
+                           double* red) {
+  const bool warm = power_start(m, V, x0, red);
+  StopState st;
+  stop_init(st, warm ? 1 : 0, (x0 && !warm) ? DTM_INFO_WARM_REJECTED : 0);
+  power_loop(m, V, c, o, st, red);
   return st;
+}
+
+// Banded pixels of the dense solver that used all their launched sweeps
+// without stopping: the power iteration goes on from the pixel's current
+// iterate with the factored product of the same matrix, every sweep in
+// float64, until the stop rule ends it or max_iter sweeps since the start
+// (or the warm start's restart) have been taken.  Pixels that stopped
+// return at once.  The stop rule's contraction estimate starts afresh from
+// the continued iterate.  Writes pi and the pixel's report, flagged
+// DTM_INFO_CONTINUED.
+template <typename T>
+__global__ __launch_bounds__(BT) void k_band_tail(const PixelMeta* __restrict__ metas,
+                                                  const int32_t* __restrict__ big,
+                                                  double* __restrict__ fact, int64_t vec_elems,
+                                                  const T* __restrict__ xbuf, SolveState* __restrict__ states,
+                                                  T* __restrict__ pi_packed, dtm_solve_info* __restrict__ infos,
+                                                  KOpts o) {
+  __shared__ double red[3 * BT / kWave];
+  const int q = big[blockIdx.x];
+  const PixelMeta m = metas[q];
+  const StopState prev = states[q].s;
+  if (prev.done) return;
+  const Vecs V = vecs(fact, vec_elems, m);
+  int j0, j1;
+  chunk_of(m.n, j0, j1);
+  StopState st = prev;
+  if (prev.iter < o.max_iter) {
+    const double c = tables(m, V, red);
+    power_start(m, V, xbuf + m.vec_off, red);
+    // the remaining sweeps of this start (the iterate is not re-run from
+    // uniform when they run out, whatever the start was)
+    stop_init(st, 0, 0);
+    KOpts oc = o;
+    oc.max_iter = o.max_iter - prev.iter;
+    power_loop(m, V, c, oc, st, red);
+    for (int j = j0; j < j1; ++j) pi_packed[m.pi_off + j] = static_cast<T>(V.x[j]);
+    st.total_iter += prev.total_iter;
+    st.flags |= prev.flags & (DTM_INFO_WARM_REJECTED | DTM_INFO_RESTARTED);
+  } else {  // no sweeps left: the last iterate is the answer
+    for (int j = j0; j < j1; ++j) pi_packed[m.pi_off + j] = xbuf[m.vec_off + j];
+    st.done = 1;
+    st.status = DTM_ENOTCONV;
+  }
+  st.flags |= DTM_INFO_CONTINUED;
+  if (threadIdx.x == 0) {
+    infos[m.index] = make_info(st);
+    states[q].s = st;
+  }
 }
 
 // IN_LDS: the five vectors the iteration touches (g, 1/S, x, u, the last
@@ -480,115 +545,301 @@ __device__ inline void block_sum_n(double (&v)[N], double* red) {
   }
 }
 
-// IN_LDS: the eight vectors live in LDS (8 n doubles, n <= kLdsMaxN); g, 1/S
-// and pi are copied to the workspace at the end for k_mixing.
+// ---- eigenvalues of a small dense matrix (the Rayleigh-Ritz step) --------
+// Real k x k matrix h (row-major, k <= KSUB, overwritten) -> its k
+// eigenvalues (er, ei).  Householder reduction to upper Hessenberg form,
+// then the shifted QR algorithm in complex arithmetic on the unreduced
+// trailing block: each step factors A - mu I = QR by Givens rotations and
+// forms RQ + mu I, with mu the eigenvalue of the trailing 2 x 2 block nearer
+// its last diagonal entry (an exceptional shift every eleventh step without
+// a deflation); a subdiagonal entry below unit round-off relative to its
+// diagonal neighbours splits the block.  ar, ai: k x k scratch.  Returns
+// false when a block did not split within 60 steps (the diagonal is then
+// taken as it stands).  Run by one thread.
+struct Cx {
+  double re, im;
+};
+__device__ inline Cx cx_mul(Cx a, Cx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline Cx cx_sqrt(Cx z) {
+  const double r = hypot(z.re, z.im);
+  if (r == 0.0) return {0.0, 0.0};
+  const double t = sqrt(0.5 * (r + fabs(z.re)));
+  if (z.re >= 0.0) return {t, z.im / (2.0 * t)};
+  return {fabs(z.im) / (2.0 * t), copysign(t, z.im)};
+}
+__device__ inline double cx_abs(Cx z) { return hypot(z.re, z.im); }
+
+__device__ bool small_eigvals(double* h, int k, double* ar, double* ai, double* er, double* ei) {
+  for (int j = 0; j + 2 < k; ++j) {
+    double v[KSUB];
+    double alpha = 0.0;
+    for (int i = j + 1; i < k; ++i) alpha += h[i * k + j] * h[i * k + j];
+    alpha = sqrt(alpha);
+    if (alpha == 0.0) continue;
+    if (h[(j + 1) * k + j] > 0.0) alpha = -alpha;
+    double vn = 0.0;
+    for (int i = j + 1; i < k; ++i) {
+      v[i - j - 1] = h[i * k + j] - (i == j + 1 ? alpha : 0.0);
+      vn += v[i - j - 1] * v[i - j - 1];
+    }
+    if (vn == 0.0) continue;
+    const double f = 2.0 / vn;
+    for (int col = 0; col < k; ++col) {  // rows j+1.. from the left
+      double t = 0.0;
+      for (int i = j + 1; i < k; ++i) t += v[i - j - 1] * h[i * k + col];
+      t *= f;
+      for (int i = j + 1; i < k; ++i) h[i * k + col] -= t * v[i - j - 1];
+    }
+    for (int row = 0; row < k; ++row) {  // columns j+1.. from the right
+      double t = 0.0;
+      for (int i = j + 1; i < k; ++i) t += h[row * k + i] * v[i - j - 1];
+      t *= f;
+      for (int i = j + 1; i < k; ++i) h[row * k + i] -= t * v[i - j - 1];
+    }
+  }
+  for (int i = 0; i < k * k; ++i) {
+    ar[i] = h[i];
+    ai[i] = 0.0;
+  }
+  const auto at = [&](int r, int c) { return Cx{ar[r * k + c], ai[r * k + c]}; };
+  const auto put = [&](int r, int c, Cx z) {
+    ar[r * k + c] = z.re;
+    ai[r * k + c] = z.im;
+  };
+  constexpr double eps = 1.1102230246251565e-16;
+  bool ok = true;
+  int hi = k - 1, steps = 0;
+  while (hi >= 0) {
+    if (hi == 0) {
+      er[0] = ar[0];
+      ei[0] = ai[0];
+      break;
+    }
+    int lo = hi;
+    while (lo > 0 && cx_abs(at(lo, lo - 1)) > eps * (cx_abs(at(lo - 1, lo - 1)) + cx_abs(at(lo, lo)))) --lo;
+    if (lo == hi || steps >= 60) {
+      if (lo != hi) ok = false;
+      er[hi] = ar[hi * k + hi];
+      ei[hi] = ai[hi * k + hi];
+      --hi;
+      steps = 0;
+      continue;
+    }
+    const Cx a = at(hi - 1, hi - 1), b = at(hi - 1, hi), c = at(hi, hi - 1), d = at(hi, hi);
+    Cx mu;
+    if (steps > 0 && steps % 11 == 0) {
+      mu = {d.re + cx_abs(c), d.im};
+    } else {
+      const Cx half = {0.5 * (a.re - d.re), 0.5 * (a.im - d.im)};
+      const Cx hh = cx_mul(half, half), bc = cx_mul(b, c);
+      const Cx disc = cx_sqrt({hh.re + bc.re, hh.im + bc.im});
+      const Cx m1 = {d.re + half.re + disc.re, d.im + half.im + disc.im};
+      const Cx m2 = {d.re + half.re - disc.re, d.im + half.im - disc.im};
+      mu = cx_abs({m1.re - d.re, m1.im - d.im}) <= cx_abs({m2.re - d.re, m2.im - d.im}) ? m1 : m2;
+    }
+    ++steps;
+    for (int i = lo; i <= hi; ++i) put(i, i, {ar[i * k + i] - mu.re, ai[i * k + i] - mu.im});
+    Cx cs[KSUB], sn[KSUB];
+    for (int i = lo; i < hi; ++i) {  // R = G_{hi-1} ... G_lo (A - mu I)
+      const Cx x = at(i, i), y = at(i + 1, i);
+      const double r = hypot(cx_abs(x), cx_abs(y));
+      const Cx cc = r == 0.0 ? Cx{1.0, 0.0} : Cx{x.re / r, x.im / r};
+      const Cx ss = r == 0.0 ? Cx{0.0, 0.0} : Cx{y.re / r, y.im / r};
+      cs[i] = cc;
+      sn[i] = ss;
+      const Cx ccc = {cc.re, -cc.im}, ssc = {ss.re, -ss.im};
+      for (int col = i; col <= hi; ++col) {
+        const Cx u = at(i, col), w = at(i + 1, col);
+        const Cx p = cx_mul(ccc, u), q = cx_mul(ssc, w), s1 = cx_mul(ss, u), s2 = cx_mul(cc, w);
+        put(i, col, {p.re + q.re, p.im + q.im});
+        put(i + 1, col, {s2.re - s1.re, s2.im - s1.im});
+      }
+    }
+    for (int i = lo; i < hi; ++i) {  // R G_lo^H ... G_{hi-1}^H
+      const Cx cc = cs[i], ss = sn[i];
+      const Cx ccc = {cc.re, -cc.im}, ssc = {ss.re, -ss.im};
+      const int rmax = min(i + 2, hi);
+      for (int row = lo; row <= rmax; ++row) {
+        const Cx u = at(row, i), w = at(row, i + 1);
+        const Cx p = cx_mul(u, cc), q = cx_mul(w, ss), s1 = cx_mul(u, ssc), s2 = cx_mul(w, ccc);
+        put(row, i, {p.re + q.re, p.im + q.im});
+        put(row, i + 1, {s2.re - s1.re, s2.im - s1.im});
+      }
+    }
+    for (int i = lo; i <= hi; ++i) put(i, i, {ar[i * k + i] + mu.re, ai[i * k + i] + mu.im});
+  }
+  return ok;
+}
+
+// Start vector number i of the subspace: a fixed non-symmetric pattern.
+__device__ inline double start_pattern(int i, int j) {
+  return 1.0 + 0.5 * sin((0.7 + 0.37 * i) * j + 0.3 * i) + ((j * 7919 + i * 104729) % 13) * 0.01;
+}
+
+// lambda_2 of the dead-time matrix (Section 4): orthogonal iteration on the
+// deflated operator A v = v P~ - (v . 1) pi with a KSUB-dimensional subspace
+// (min(KSUB, n - 1) vectors), each step
+//   Q = orthonormal basis of W (classical Gram-Schmidt, two passes),
+//   W = A Q,  H = Q^T W  (the Rayleigh quotient of the subspace),
+// whose eigenvalues (Ritz values) approach the KSUB eigenvalues of largest
+// modulus of A, i.e. lambda_2, lambda_3, ... of P~: the one of largest
+// modulus converges at the rate |lambda_{KSUB+2} / lambda_2| per step, so
+// eigenvalues close to lambda_2 in modulus (a near-tie with lambda_3) do not
+// slow it.  Stops when lambda_2 and the next modulus have each changed by
+// at most 1e-13 (1 + |lambda_2|) in two successive steps, or after max_iter
+// steps.  A basis vector that A
+// annihilates (its orthogonalised norm below 1e-14 of its norm) stays zero.
+// IN_LDS: the NVEC vectors live in LDS (n <= kSpecLdsMaxN); g, 1/S and pi
+// are copied to the workspace at the end for the mixing search.
 template <bool IN_LDS>
 __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ metas,
                                                  double* __restrict__ fact, int64_t vec_elems,
                                                  double* __restrict__ scal_out,
                                                  dtm_spectral_info* __restrict__ out, KOpts o,
                                                  int max_iter) {
-  __shared__ double red[8 * BT / kWave];
+  __shared__ double red[KSUB * KSUB * BT / kWave];
+  __shared__ double hs[KSUB * KSUB], har[KSUB * KSUB], hai[KSUB * KSUB], er[KSUB], ei[KSUB];
+  __shared__ int eig_ok;
   extern __shared__ double lds_vec[];
   const PixelMeta m = metas[blockIdx.x];
   const int n = m.n;
   const Vecs G = vecs(fact, vec_elems, m);
   Vecs V = G;
-  if constexpr (IN_LDS) {
-    V.g = lds_vec;
-    V.invs = lds_vec + n;
-    V.x = lds_vec + 2 * n;
-    V.u = lds_vec + 3 * n;
-    V.dp = lds_vec + 4 * n;
-    V.v0 = lds_vec + 5 * n;
-    V.v1 = lds_vec + 6 * n;
-    V.v2 = lds_vec + 7 * n;
+  double* Q[KSUB];
+  double* W[KSUB];
+  {
+    double* base = IN_LDS ? lds_vec : fact + m.vec_off;
+    const int64_t stride = IN_LDS ? static_cast<int64_t>(n) : vec_elems;
+    if constexpr (IN_LDS) {
+      V.g = base;
+      V.invs = base + stride;
+      V.x = base + 2 * stride;
+      V.u = base + 3 * stride;
+      V.dp = base + 4 * stride;
+    }
+#pragma unroll
+    for (int i = 0; i < KSUB; ++i) {
+      Q[i] = base + (5 + i) * stride;
+      W[i] = base + (5 + KSUB + i) * stride;
+    }
   }
   const double c = tables(m, V, red);
   if (threadIdx.x == 0) scal_out[blockIdx.x] = c;
   power<double>(m, V, c, static_cast<const double*>(nullptr), o, red);  // pi -> V.x
   int j0, j1;
   chunk_of(n, j0, j1);
-  // start: a fixed non-symmetric pattern, deflated and normalised
-  for (int j = j0; j < j1; ++j) V.v2[j] = 1.0 + 0.5 * sin(0.7 * j + 0.3) + ((j * 7919) % 13) * 0.01;
-  double s2 = 0.0;
-  for (int j = j0; j < j1; ++j) s2 += V.v2[j];
-  s2 = block_sum<BT>(s2, red);
-  deflated(m, V, c, V.v2, s2, V.v0, red);
-  double nv = 0.0, s0 = 0.0;
-  for (int j = j0; j < j1; ++j) {
-    nv += V.v0[j] * V.v0[j];
-    s0 += V.v0[j];
-  }
-  block_sum2<BT>(nv, s0, red);
-  double re = 0.0, im = 0.0, fit = 1.0, prev_re = 2.0, prev_im = 2.0;
-  int it = 0;
-  if (!(nv > 0.0)) {  // the deflated operator is nil on the start vector
-    re = im = 0.0;
-    fit = 0.0;
-  } else {
-    const double sc = 1.0 / sqrt(nv);
-    for (int j = j0; j < j1; ++j) V.v0[j] *= sc;
-    s0 *= sc;
-    __syncthreads();
-    // Every deflated vector sums to zero (P~ is stochastic and pi sums to
-    // one), so v1 = A v0 is taken with s = 0; the rounding-level sum that v0
-    // carries is removed each step (s0, from the fused sums below).  One
-    // block reduction per step gives the Gram entries, v2 . 1 and ||v2||,
-    // with which v2 becomes the next normalised v0.
-    for (; it < max_iter; ++it) {
-      deflated(m, V, c, V.v0, s0, V.v1, red);
-      deflated(m, V, c, V.v1, 0.0, V.v2, red);
-      // least squares v2 ~ a v1 + b v0
-      double q[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-      for (int j = j0; j < j1; ++j) {
-        q[0] += V.v1[j] * V.v1[j];
-        q[1] += V.v1[j] * V.v0[j];
-        q[2] += V.v0[j] * V.v0[j];
-        q[3] += V.v2[j] * V.v1[j];
-        q[4] += V.v2[j] * V.v0[j];
-        q[5] += V.v2[j] * V.v2[j];
-        q[6] += V.v2[j];
-      }
-      block_sum_n<7>(q, red);
-      const double g11 = q[0], g10 = q[1], g00 = q[2], r1 = q[3], r0 = q[4], w22 = q[5];
-      const double det = g11 * g00 - g10 * g10;
-      double a, b;
-      if (det > 1e-12 * g11 * g00) {
-        a = (r1 * g00 - r0 * g10) / det;
-        b = (g11 * r0 - g10 * r1) / det;
-        const double disc = a * a + 4.0 * b;
-        if (disc < 0.0) {
-          re = 0.5 * a;
-          im = 0.5 * sqrt(-disc);
-        } else {
-          const double sq = sqrt(disc);
-          const double z1 = 0.5 * (a + sq), z2 = 0.5 * (a - sq);
-          re = fabs(z1) >= fabs(z2) ? z1 : z2;
-          im = 0.0;
+  const int ke = min(KSUB, n - 1);
+  {
+    double sums[KSUB];
+#pragma unroll
+    for (int i = 0; i < KSUB; ++i) {
+      sums[i] = 0.0;
+      if (i < ke)
+        for (int j = j0; j < j1; ++j) {
+          const double v = start_pattern(i, j);
+          Q[i][j] = v;
+          sums[i] += v;
         }
-        // residual ||v2 - a v1 - b v0||^2 / ||v2||^2 from the Gram entries
-        const double res2 = w22 - 2.0 * (a * r1 + b * r0) + a * a * g11 + 2.0 * a * b * g10 + b * b * g00;
-        fit = w22 > 0.0 ? sqrt(fmax(res2, 0.0) / w22) : 0.0;
-      } else {  // v1 parallel to v0: one real dominant eigenvalue
-        a = g00 > 0.0 ? g10 / g00 : 0.0;
-        re = a;
-        im = 0.0;
-        const double res2 = g11 - 2.0 * a * g10 + a * a * g00;
-        fit = g11 > 0.0 ? sqrt(fmax(res2, 0.0) / g11) : 0.0;
+    }
+    block_sum_n<KSUB>(sums, red);
+#pragma unroll
+    for (int i = 0; i < KSUB; ++i)
+      if (i < ke) deflated(m, V, c, Q[i], sums[i], W[i], red);
+  }
+  double re = 0.0, im = 0.0, l3 = 0.0, change = 0.0, prev_re = 2.0, prev_im = 2.0, prev_l3 = 2.0;
+  int it = 0, settled = 0, flags = 0;
+  bool all_ok = true;
+  for (; it < max_iter; ++it) {
+    // Q = orthonormal basis of W (two classical Gram-Schmidt passes)
+    double s[KSUB];
+#pragma unroll
+    for (int i = 0; i < KSUB; ++i) {
+      s[i] = 0.0;
+      if (i >= ke) continue;
+      for (int j = j0; j < j1; ++j) Q[i][j] = W[i][j];
+      double n0 = 0.0;
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
+        double d[KSUB + 1];
+#pragma unroll
+        for (int a = 0; a <= KSUB; ++a) d[a] = 0.0;
+        for (int j = j0; j < j1; ++j) {
+          const double qi = Q[i][j];
+#pragma unroll
+          for (int a = 0; a < KSUB; ++a)
+            if (a < i) d[a] += Q[a][j] * qi;
+          d[KSUB] += qi * qi;
+        }
+        block_sum_n<KSUB + 1>(d, red);
+        if (pass == 0) n0 = d[KSUB];
+        for (int j = j0; j < j1; ++j) {
+          double v = Q[i][j];
+#pragma unroll
+          for (int a = 0; a < KSUB; ++a)
+            if (a < i) v -= d[a] * Q[a][j];
+          Q[i][j] = v;
+        }
       }
-      const bool settled = fabs(re - prev_re) <= 1e-12 * (1.0 + fabs(re)) &&
-                           fabs(im - prev_im) <= 1e-12 * (1.0 + fabs(im));
-      prev_re = re;
-      prev_im = im;
-      if ((settled && it >= 4) || !(w22 > 0.0)) break;
-      // next start: v2 (two steps further along), normalised
-      const double sc2 = 1.0 / sqrt(w22);
-      for (int j = j0; j < j1; ++j) V.v0[j] = V.v2[j] * sc2;
-      s0 = q[6] * sc2;
+      double t[2] = {0.0, 0.0};
+      for (int j = j0; j < j1; ++j) {
+        t[0] += Q[i][j] * Q[i][j];
+        t[1] += Q[i][j];
+      }
+      block_sum_n<2>(t, red);
+      const double sc = (t[0] > 1e-28 * n0 && t[0] > 0.0) ? 1.0 / sqrt(t[0]) : 0.0;
+      for (int j = j0; j < j1; ++j) Q[i][j] *= sc;
+      s[i] = t[1] * sc;
       __syncthreads();
     }
+    // W = A Q and the Rayleigh quotient H = Q^T W
+#pragma unroll
+    for (int i = 0; i < KSUB; ++i)
+      if (i < ke) deflated(m, V, c, Q[i], s[i], W[i], red);
+    double h[KSUB * KSUB];
+#pragma unroll
+    for (int e = 0; e < KSUB * KSUB; ++e) h[e] = 0.0;
+    for (int j = j0; j < j1; ++j) {
+#pragma unroll
+      for (int a = 0; a < KSUB; ++a)
+#pragma unroll
+        for (int b = 0; b < KSUB; ++b)
+          if (a < ke && b < ke) h[a * KSUB + b] += Q[a][j] * W[b][j];
+    }
+    block_sum_n<KSUB * KSUB>(h, red);
+    if (threadIdx.x == 0) {
+      for (int a = 0; a < ke; ++a)
+        for (int b = 0; b < ke; ++b) hs[a * ke + b] = h[a * KSUB + b];
+      eig_ok = small_eigvals(hs, ke, har, hai, er, ei) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!eig_ok) all_ok = false;
+    // lambda_2: the Ritz value of largest modulus; lambda_3: the largest of
+    // the others, leaving out lambda_2's conjugate
+    int i2 = 0;
+    for (int i = 1; i < ke; ++i)
+      if (hypot(er[i], ei[i]) > hypot(er[i2], ei[i2])) i2 = i;
+    re = er[i2];
+    im = fabs(ei[i2]);
+    const double a2 = hypot(re, im);
+    if (im <= 1e-13 * (1.0 + a2)) im = 0.0;  // a real eigenvalue, up to the rounding of the QR steps
+    int partner = -1;
+    if (im > 0.0)
+      for (int i = 0; i < ke; ++i)
+        if (i != i2 && partner < 0 && hypot(er[i] - er[i2], ei[i] + ei[i2]) <= 1e-9 * (1.0 + a2)) partner = i;
+    l3 = 0.0;
+    for (int i = 0; i < ke; ++i)
+      if (i != i2 && i != partner) l3 = fmax(l3, hypot(er[i], ei[i]));
+    change = fmax(hypot(re - prev_re, im - prev_im), fabs(l3 - prev_l3));
+    settled = change <= 1e-13 * (1.0 + a2) ? settled + 1 : 0;
+    prev_re = re;
+    prev_im = im;
+    prev_l3 = l3;
+    __syncthreads();  // every thread has read er / ei before the next step writes them
+    if (settled >= 2) break;
   }
+  if (settled < 2) flags |= DTM_SPECTRAL_UNSETTLED;
+  if (!all_ok) flags |= DTM_SPECTRAL_UNSETTLED;
+  if (l3 >= (1.0 - 1e-9) * hypot(re, im) && l3 > 0.0) flags |= DTM_SPECTRAL_TIED;
   if constexpr (IN_LDS) {
     for (int j = j0; j < j1; ++j) {
       G.g[j] = V.g[j];
@@ -597,15 +848,18 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
     }
   }
   if (threadIdx.x == 0) {
-    dtm_spectral_info s;
-    s.lambda2_re = re;
-    s.lambda2_im = im;
-    s.lambda2_abs = sqrt(re * re + im * im);
-    s.lambda2_arg = atan2(im, re);
-    s.fit_residual = fit;
-    s.iterations = it + 1;
-    s.mixing_steps = -1;
-    out[m.index] = s;
+    dtm_spectral_info si;
+    si.lambda2_re = re;
+    si.lambda2_im = im;
+    si.lambda2_abs = hypot(re, im);
+    si.lambda2_arg = atan2(im, re);
+    si.lambda3_abs = l3;
+    si.ritz_change = change;
+    si.iterations = min(it + 1, max_iter);
+    si.mixing_steps = -1;
+    si.flags = flags;
+    si.reserved = 0;
+    out[m.index] = si;
   }
 }
 
@@ -775,6 +1029,30 @@ __global__ __launch_bounds__(BT) void k_mixing_final(const PixelMeta* __restrict
 
 using namespace dtm;
 
+namespace dtm {
+
+int launch_band_tail(const dtm_plan* plan, void* pi, dtm_solve_info* infos, void* stream) {
+  const int nbig = static_cast<int>(plan->big_sel.size());
+  if (nbig == 0) return DTM_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(plan->ws);
+  const PixelMeta* metas = reinterpret_cast<const PixelMeta*>(w + plan->off_meta);
+  const int32_t* big = reinterpret_cast<const int32_t*>(w + plan->off_big);
+  double* fact = reinterpret_cast<double*>(w + plan->off_fact);
+  SolveState* states = reinterpret_cast<SolveState*>(w + plan->off_state);
+  if (plan->dt == DTM_F32)
+    hipLaunchKernelGGL((fact::k_band_tail<float>), dim3(nbig), dim3(fact::BT), 0, st, metas, big, fact,
+                       plan->vec_elems, reinterpret_cast<const float*>(w + plan->off_xbuf), states,
+                       static_cast<float*>(pi), infos, plan->kopts);
+  else
+    hipLaunchKernelGGL((fact::k_band_tail<double>), dim3(nbig), dim3(fact::BT), 0, st, metas, big, fact,
+                       plan->vec_elems, reinterpret_cast<const double*>(w + plan->off_xbuf), states,
+                       static_cast<double*>(pi), infos, plan->kopts);
+  return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP;
+}
+
+}  // namespace dtm
+
 extern "C" {
 
 int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, void* pi_packed_dev,
@@ -855,7 +1133,7 @@ int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, 
 
 size_t dtm_spectral_scratch_bytes(const dtm_plan* plan, int32_t with_mixing) {
   if (!plan) return 0;
-  // 8 float64 vectors per pixel for the deflated iteration, c per pixel, and
+  // NVEC float64 vectors per pixel for the subspace iteration, c per pixel, and
   // for the mixing search of plans with n above 1024 (one thread per start
   // state) two n x n float64 blocks per pixel plus their offsets; up to
   // 1024 bins the search keeps every start state on chip
@@ -889,8 +1167,8 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
   o.safety = 1.0;
   o.stop_rule = DTM_STOP_BOUND;
   o.pad = 0;
-  if (plan->max_n <= fact::kLdsMaxN) {
-    const size_t lds = 8 * sizeof(double) * static_cast<size_t>(plan->max_n);
+  if (plan->max_n <= fact::kSpecLdsMaxN) {
+    const size_t lds = fact::NVEC * sizeof(double) * static_cast<size_t>(plan->max_n);
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(fact::k_spectral<true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
       return DTM_EHIP;

@@ -97,6 +97,9 @@ int shift_bins(const dtm_scene& s, int32_t* l);
 void model_shift(const dtm_scene& s, int32_t model, int32_t* l, double* frac);
 int32_t model_lam_mode(int32_t model);
 int fill_opts(const dtm_solve_opts* opt, KOpts* k, int32_t* check_every);
+// Float64 continuation of the banded pixels of a bound plan whose launched
+// sweeps ran out (dtm_factored.hip; launch only, on the hipStream_t stream).
+int launch_band_tail(const dtm_plan* plan, void* pi, dtm_solve_info* infos, void* stream);
 constexpr int32_t padded_ld(int32_t n, dtm_dtype dt) {
   const int32_t vec = dt == DTM_F32 ? 4 : 2;  // 16 bytes
   return (n + vec - 1) / vec * vec;

@@ -680,8 +680,7 @@ __global__ __launch_bounds__(BT) void k_band_combine(const PixelMeta* __restrict
                                                      T* __restrict__ xbuf, double* __restrict__ dprev,
                                                      SolveState* __restrict__ states,
                                                      T* __restrict__ pi_packed,
-                                                     dtm_solve_info* __restrict__ infos, KOpts o,
-                                                     int last) {
+                                                     dtm_solve_info* __restrict__ infos, KOpts o) {
   __shared__ double red[3 * BT / kWave];
   const int q = big[blockIdx.x];
   const PixelMeta m = metas[q];
@@ -736,10 +735,6 @@ __global__ __launch_bounds__(BT) void k_band_combine(const PixelMeta* __restrict
       x[j] = static_cast<T>(1.0 / n);
       dp[j] = 0.0;
     }
-  }
-  if (!s.done && last) {  // out of launched sweeps
-    s.done = 1;
-    s.status = DTM_ENOTCONV;
   }
   if (s.done) {
     for (int j = threadIdx.x; j < n; j += BT) pi_packed[m.pi_off + j] = x[j];
@@ -1334,7 +1329,7 @@ int launch_banded(const dtm_plan* plan, int t0, int t1, const PixelMeta* metas, 
     hipLaunchKernelGGL(sweep, dim3(nitems), dim3(BT), lds, st, metas, items, colf, scal, invs, pool,
                        xbuf, states, part, plan->tiles.band_rows, t == 0 ? 1 : 0);
     hipLaunchKernelGGL((k_band_combine<T, BT>), dim3(nbig), dim3(BT), 0, st, metas, big, part, xbuf,
-                       dprev, states, pi, infos, plan->kopts, t == plan->tiles.band_sweeps - 1 ? 1 : 0);
+                       dprev, states, pi, infos, plan->kopts);
     rc = last_launch();
     if (rc) return rc;
   }
@@ -1422,6 +1417,9 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
   }
   if (nbig > 0) {
     rc = launch_banded<T>(plan, 1, plan->tiles.band_sweeps, metas, colf, scal, invs, pool, pit, infos, st);
+    if (rc) return rc;
+    // pixels still running after the launched sweeps go on in float64
+    rc = launch_band_tail(plan, pit, infos, st);
     if (rc) return rc;
   }
   if (fork) {

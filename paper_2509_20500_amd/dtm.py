@@ -44,6 +44,10 @@ DTM_INFO_RESTARTED = 0x2
 DTM_INFO_CHECKED = 0x4
 DTM_INFO_STALLED = 0x8
 DTM_INFO_REFINED = 0x10
+DTM_INFO_CONTINUED = 0x20
+
+DTM_SPECTRAL_UNSETTLED = 0x1
+DTM_SPECTRAL_TIED = 0x2
 
 DTM_MAX_BINS = 65536
 DTM_NOALLOC_MAX_BINS = 8192
@@ -109,9 +113,11 @@ def tiles(fused_threads=0, fused_unroll=0, fused_max_bins=0, band_rows=0, band_s
 
 SPECTRAL_INFO_DTYPE = np.dtype([
     ("lambda2_re", "<f8"), ("lambda2_im", "<f8"), ("lambda2_abs", "<f8"), ("lambda2_arg", "<f8"),
-    ("fit_residual", "<f8"), ("iterations", "<i4"), ("mixing_steps", "<i4"),
+    ("lambda3_abs", "<f8"), ("ritz_change", "<f8"), ("iterations", "<i4"), ("mixing_steps", "<i4"),
+    ("flags", "<i4"), ("reserved", "<i4"),
 ])
-assert SPECTRAL_INFO_DTYPE.itemsize == 48
+assert SPECTRAL_INFO_DTYPE.itemsize == 64
+SPECTRAL_INFO_BYTES = SPECTRAL_INFO_DTYPE.itemsize
 
 SOLVE_INFO_DTYPE = np.dtype([
     ("iterations", "<i4"), ("status", "<i4"), ("flags", "<i4"), ("reserved", "<i4"),

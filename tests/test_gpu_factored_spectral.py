@@ -78,7 +78,7 @@ def test_mixing_steps_each_launch_shape(n_max):
     scenes["n_bins"][1] = n_max - 37
     d, plan, ws = _plan(scenes, "f64", lib().opts(tol=1e-12))
     scratch = torch.empty(plan.spectral_scratch_bytes(True), dtype=torch.uint8, device="cuda")
-    out = torch.zeros(plan.n_pixels * 48, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(plan.n_pixels * d.SPECTRAL_INFO_BYTES, dtype=torch.uint8, device="cuda")
     plan.spectral(out, scratch, 0.25, 5000)
     torch.cuda.synchronize()
     res = d.spectral_to_numpy(out)
@@ -110,28 +110,65 @@ def test_factored_solver_at_large_n():
     assert np.abs(y - x).sum() < 1e-11
 
 
+def _check_spectral(res, scenes, refs, mod_tol, arg_tol, l3_tol):
+    d = lib()
+    for p, s in enumerate(scenes):
+        lam, third = refs[p]
+        r = res[p]
+        assert not (r["flags"] & d.DTM_SPECTRAL_UNSETTLED), (p, s, r)
+        assert abs(r["lambda2_abs"] - abs(lam)) <= mod_tol * max(1.0, abs(lam)), (p, s, r, lam)
+        tied = third >= (1.0 - 1e-9) * abs(lam) and third > 0.0
+        assert bool(r["flags"] & d.DTM_SPECTRAL_TIED) == tied, (p, s, r, lam, third)
+        if not tied:
+            assert abs(r["lambda2_arg"] - abs(np.angle(lam))) <= arg_tol, (p, s, r, lam)
+        assert abs(r["lambda3_abs"] - third) <= l3_tol, (p, s, r, third)
+
+
 def test_spectral_second_eigenvalue_matches_dense_eig():
-    """|lambda_2| and its phase on the paper's (S, B) grids at t_d = 75 and
-    95 ns (Section 4), N = 128, against LAPACK eigenvalues."""
+    """lambda_2 (modulus and phase) and the next modulus of every pixel of the
+    paper's Section 4 grid (S, B in {0.1, 1, ..., 10}, t_d = 75 and 95 ns,
+    N = 256), of the coarse grid at N = 128 and of random small scenes,
+    against LAPACK eigenvalues of the oracle's dense matrix.  The grid holds
+    pixels whose third eigenvalue lies within a few per cent of lambda_2 in
+    modulus (S, B near 10 at t_d = 95 ns)."""
     levels = (0.1, 3.0, 6.0, 9.0)
-    scenes = np.concatenate([sc.paper_grid(levels, dead_time=75.0, n_bins=128),
+    scenes = np.concatenate([sc.paper_rmse_grid(n_bins=256, dead_time=75.0),
+                             sc.paper_rmse_grid(n_bins=256, dead_time=95.0),
+                             sc.paper_grid(levels, dead_time=75.0, n_bins=128),
                              sc.paper_grid(levels, dead_time=95.0, n_bins=128),
-                             sc.random_small(12, seed=131)])
+                             sc.random_small(24, seed=131)])
     d, plan, ws = _plan(scenes, "f64", lib().opts(tol=1e-12))
     scratch = torch.empty(plan.spectral_scratch_bytes(False), dtype=torch.uint8, device="cuda")
-    out = torch.zeros(plan.n_pixels * 48, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(plan.n_pixels * d.SPECTRAL_INFO_BYTES, dtype=torch.uint8, device="cuda")
     plan.spectral(out, scratch, 0.0, 5000)
     torch.cuda.synchronize()
     res = d.spectral_to_numpy(out)
-    checked = 0
-    for p, s in enumerate(scenes):
-        lam, third = ospec.second_eigenvalue(odtm.transition_matrix(s))
-        if third > 0.9 * abs(lam) or abs(lam) < 1e-6:
-            continue  # the two-term fit needs a separated dominant eigenvalue
-        checked += 1
-        assert abs(res["lambda2_abs"][p] - abs(lam)) < 1e-6 * max(1.0, abs(lam)), (p, s, res[p], lam)
-        assert abs(res["lambda2_arg"][p] - abs(np.angle(lam))) < 1e-4, (p, s, res[p], lam)
-    assert checked >= 24
+    refs = [ospec.second_eigenvalue(odtm.transition_matrix(s)) for s in scenes]
+    near = sum(1 for lam, third in refs if third > 0.9 * abs(lam))
+    print(f"{scenes.size} pixels, {near} with |lambda_3| > 0.9 |lambda_2|; subspace steps max "
+          f"{res['iterations'].max()}, mean {res['iterations'].mean():.1f}", flush=True)
+    assert near >= 7
+    _check_spectral(res, scenes, refs, 1e-9, 1e-7, 1e-6)
+    plan.close()
+
+
+def test_spectral_slowest_grid_pixels_at_n1024():
+    """The Section 4 grid pixels with the smallest spectral gaps and the
+    closest third eigenvalues, at N = 1024 and one at 1536 (the plan then
+    keeps the subspace in the workspace rather than on chip), against
+    LAPACK."""
+    cells = [(75.0, 10.0, 10.0, 1024), (75.0, 0.1, 10.0, 1024), (95.0, 10.0, 7.0, 1024),
+             (95.0, 10.0, 10.0, 1024), (95.0, 9.0, 9.0, 1024), (95.0, 8.0, 10.0, 1536)]
+    scenes = np.concatenate([sc.scene(dead_time=td, center=30.0, sigma=0.5, signal=S, background=B,
+                                      n_bins=n) for td, S, B, n in cells])
+    d, plan, ws = _plan(scenes, "f64", lib().opts(tol=1e-12))
+    scratch = torch.empty(plan.spectral_scratch_bytes(False), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(plan.n_pixels * d.SPECTRAL_INFO_BYTES, dtype=torch.uint8, device="cuda")
+    plan.spectral(out, scratch, 0.0, 5000)
+    torch.cuda.synchronize()
+    res = d.spectral_to_numpy(out)
+    refs = [ospec.second_eigenvalue(odtm.transition_matrix(s)) for s in scenes]
+    _check_spectral(res, scenes, refs, 1e-9, 1e-7, 1e-6)
     plan.close()
 
 
@@ -141,7 +178,7 @@ def test_mixing_steps_match_dense_powers():
                              sc.paper_grid(levels, dead_time=95.0, n_bins=96)])
     d, plan, ws = _plan(scenes, "f64", lib().opts(tol=1e-12))
     scratch = torch.empty(plan.spectral_scratch_bytes(True), dtype=torch.uint8, device="cuda")
-    out = torch.zeros(plan.n_pixels * 48, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(plan.n_pixels * d.SPECTRAL_INFO_BYTES, dtype=torch.uint8, device="cuda")
     for eps in (0.25, 1e-3):
         plan.spectral(out, scratch, eps, 5000)
         torch.cuda.synchronize()

@@ -327,12 +327,19 @@ def test_banded_path_ragged(dt):
         assert err <= tol, (p, int(s["n_bins"]), err, info[p])
 
 
-def test_banded_sweep_cap_is_soft():
-    """A banded pixel that needs more sweeps than were launched ends with
+def test_banded_sweep_cap_continues_in_float64():
+    """A banded pixel that needs more sweeps than were launched goes on from
+    its iterate in float64 (flagged DTM_INFO_CONTINUED) and meets the
+    tolerance; with max_iter equal to the launched sweeps it ends with
     DTM_ENOTCONV and its last iterate."""
     d = lib()
     scenes = sc.paper_grid(levels=(9.0,), dead_time=75.0, n_bins=512)
     pi, info, off = run_batched(scenes, "f32", tiles=d.tiles(fused_max_bins=256, band_sweeps=3))
+    assert np.all(info["status"] == 0)
+    assert np.all(info["flags"] & d.DTM_INFO_CONTINUED) and np.all(info["iterations"] > 3)
+    assert np.abs(pi - oracle_pi(scenes[0])).sum() <= TOL_F32
+    pi, info, off = run_batched(scenes, "f32", solve_opts=d.opts(tol=1e-6, max_iter=3),
+                                tiles=d.tiles(fused_max_bins=256, band_sweeps=3))
     assert np.all(info["status"] == d.DTM_ENOTCONV)
     assert np.all(info["iterations"] == 3)
     assert np.all(np.isfinite(pi)) and abs(pi.sum() - 1) < 1e-5

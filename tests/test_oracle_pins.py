@@ -314,8 +314,9 @@ def test_second_eigenvalue_two_state_closed_form():
     from oracle import spectral
     s = sc.scene(dead_time=13.0, center=20.0, sigma=5.0, signal=1.3, background=0.4, n_bins=2)
     Pt = dtm.transition_matrix(s)
-    lam, _ = spectral.second_eigenvalue(Pt)
+    lam, third = spectral.second_eigenvalue(Pt)
     assert abs(lam - (1.0 - Pt[0, 1] - Pt[1, 0])) < 1e-15
+    assert third == 0.0  # two states: no eigenvalue besides 1 and lambda_2
 
 
 def test_second_eigenvalue_of_pure_background_is_a_dft_value():
@@ -328,8 +329,14 @@ def test_second_eigenvalue_of_pure_background_is_a_dft_value():
     k = np.arange(64)
     dft = np.array([np.sum(row * np.exp(2j * np.pi * k * m / 64)) for m in range(64)])
     dft = dft[np.argsort(-np.abs(dft))]
-    lam, _ = spectral.second_eigenvalue(Pt)
+    lam, third = spectral.second_eigenvalue(Pt)
     assert abs(abs(lam) - abs(dft[1])) < 1e-12
+    # the first row is real, so DFT values m and 64 - m are conjugate: the
+    # moduli after the Perron value come in equal pairs (m = 32 aside), and
+    # the next modulus once lambda_2's pair is set aside is the third one
+    mods = np.sort(np.abs(dft[1:]))[::-1]
+    assert abs(mods[0] - mods[1]) < 1e-12 and mods[2] < mods[1] - 1e-6
+    assert abs(third - mods[2]) < 1e-12
 
 
 def test_mixing_steps_two_state_closed_form():
