@@ -348,8 +348,10 @@ int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, 
  * approach the six eigenvalues of largest modulus after the Perron value;
  * lambda_2 is the largest, which converges at the rate |lambda_8 / lambda_2|
  * per step, so a third eigenvalue close to lambda_2 in modulus does not
- * slow or spoil it.  The search stops when lambda_2 and |lambda_3| have each
- * moved by at most 1e-13 (1 + |lambda_2|) in two successive steps; max_steps also caps
+ * slow or spoil it.  The Rayleigh quotient is formed every eighth step until
+ * two of them give Ritz values within 1e-9 of each other, then every step;
+ * the search stops when lambda_2 has moved by at most 1e-13 (1 + |lambda_2|)
+ * and |lambda_3| by at most 1e-11 (1 + |lambda_2|) in two successive steps; max_steps also caps
  * the steps of this search (DTM_SPECTRAL_UNSETTLED when reached).  Uses the
  * factored operator (O(n) per step per vector).  The mixing search advances
  * every start state: for plans whose pixels have at most 1024 bins on chip
@@ -368,7 +370,7 @@ typedef struct dtm_spectral_info {
   double lambda3_abs;             /* largest modulus among the other Ritz values
                                      (lambda_2's conjugate left out): |lambda_3|    */
   double ritz_change;             /* change of lambda_2 (or of |lambda_3|, the larger)
-                                     over the last step                              */
+                                     between the last two Rayleigh-Ritz steps        */
   int32_t iterations;             /* subspace steps                                  */
   int32_t mixing_steps;           /* -1: not reached / not requested                 */
   int32_t flags;                  /* DTM_SPECTRAL_*                                  */
@@ -449,13 +451,16 @@ int dtm_build_transition_batched(const dtm_plan* plan, void* P_packed_dev,
  * iteration (dtm_solve_batched's x0; the solver's float64 residual decides,
  * uniform is the fallback):
  *   features phi (5, see dtm_mlp_features) -> Linear(5, 256) -> GELU
- *   -> Linear(256, 256) -> GELU -> Linear(256, 1024) -> softmax.
+ *   -> Linear(256, 256) -> GELU -> Linear(256, 1024) -> (+ prior logits)
+ *   -> softmax,
+ * the optional prior being the log of the flux start (dtm_mlp_flux_prior).
  * GELU is the erf form.  GEMMs use bfloat16 operands with float32
  * accumulation on the matrix cores; everything else is float32.  All state
  * lives in a caller-owned workspace described by dtm_mlp_layout: float32
  * master parameters (W1 is stored as 16 x 256 with input rows 5..15 zero),
- * their bfloat16 copies, gradients, Adam moments and the activations of one
- * batch of up to max_batch rows.  Weights are row-major (in x out). */
+ * their bfloat16 copies, gradients, Adam moments, the activations of one
+ * batch of up to max_batch rows and the weight gradients' split partial
+ * products.  Weights are row-major (in x out). */
 #define DTM_MLP_IN 5
 #define DTM_MLP_IN_PAD 16
 #define DTM_MLP_HIDDEN 256
@@ -463,7 +468,7 @@ int dtm_build_transition_batched(const dtm_plan* plan, void* P_packed_dev,
 #define DTM_MLP_MAX_BATCH 65536
 
 typedef struct dtm_mlp_layout {
-  size_t params, params_bf16, grads, adam_m, adam_v, act, total; /* byte offsets, total size */
+  size_t params, params_bf16, grads, adam_m, adam_v, act, partial, total; /* byte offsets, total size */
   int64_t off_w1, off_b1, off_w2, off_b2, off_w3, off_b3;         /* element offsets of each tensor
                                                                      in params / grads / moments */
   int64_t n_params;
@@ -478,18 +483,29 @@ int dtm_mlp_workspace_layout(int32_t max_batch, dtm_mlp_layout* layout_out);
 int dtm_mlp_features(const dtm_scene* scenes_dev, int32_t n, float* feat_dev, dtm_stream_t stream);
 /* Refresh the bfloat16 copies after writing the float32 parameters. */
 int dtm_mlp_sync_bf16(void* workspace_dev, int32_t max_batch, dtm_stream_t stream);
-/* probs_dev (batch x 1024 float32) = softmax(network(feat_dev)). */
-int dtm_mlp_forward(void* workspace_dev, int32_t max_batch, const float* feat_dev, int32_t batch,
-                    float* probs_dev, dtm_stream_t stream);
-/* Forward, cross-entropy -sum_j target_j log q_j per row (loss_dev, may be
- * NULL), and the gradients of the mean loss into the workspace's grads. */
-int dtm_mlp_backward(void* workspace_dev, int32_t max_batch, const float* feat_dev,
+/* Prior logits for the network's output (n x 1024 float32):
+ * log(lambda_j / sum_k lambda_k) at the 1024 bin centres (j + 1/2) t_r / 1024
+ * of each device scene, lambda of Eq. (arrival_flux): the logarithm of the
+ * solver's flux start (DTM_FLAG_START_FLUX).  With it the network learns a
+ * correction to that start rather than the whole PDF. */
+int dtm_mlp_flux_prior(const dtm_scene* scenes_dev, int32_t n, float* prior_dev, dtm_stream_t stream);
+/* probs_dev (batch x 1024 float32) = softmax(network(feat_dev) + prior_dev);
+ * prior_dev (batch x 1024 float32) may be NULL (no prior). */
+int dtm_mlp_forward(void* workspace_dev, int32_t max_batch, const float* feat_dev, const float* prior_dev,
+                    int32_t batch, float* probs_dev, dtm_stream_t stream);
+/* Forward (with the same optional prior), cross-entropy
+ * -sum_j target_j log q_j per row (loss_dev, may be NULL), and the gradients
+ * of the mean loss into the workspace's grads.  The weight gradients split
+ * the batch over blocks when their outputs have few tiles; the partial
+ * products are added in a fixed order, so results are reproducible. */
+int dtm_mlp_backward(void* workspace_dev, int32_t max_batch, const float* feat_dev, const float* prior_dev,
                      const float* target_dev, int32_t batch, float* loss_dev, dtm_stream_t stream);
 /* One Adam step (bias-corrected, step >= 1) on every parameter. */
 int dtm_mlp_adam(void* workspace_dev, int32_t max_batch, float lr, float beta1, float beta2,
                  float eps, int32_t step, dtm_stream_t stream);
 /* The network's GEMM: C (M x N float32, ldc) = op(A) op(B), A and B bfloat16
- * row-major, op = transpose when trans_* != 0. */
+ * row-major, op = transpose when trans_* != 0 (v_mfma_f32_16x16x32_bf16,
+ * float32 accumulation). */
 int dtm_mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const void* A_dev, int32_t lda,
                       int32_t trans_a, const void* B_dev, int32_t ldb, int32_t trans_b,
                       float* C_dev, int32_t ldc, dtm_stream_t stream);

@@ -685,9 +685,10 @@ __device__ inline double start_pattern(int i, int j) {
 // modulus of A, i.e. lambda_2, lambda_3, ... of P~: the one of largest
 // modulus converges at the rate |lambda_{KSUB+2} / lambda_2| per step, so
 // eigenvalues close to lambda_2 in modulus (a near-tie with lambda_3) do not
-// slow it.  Stops when lambda_2 and the next modulus have each changed by
-// at most 1e-13 (1 + |lambda_2|) in two successive steps, or after max_iter
-// steps.  A basis vector that A
+// slow it.  The Rayleigh-Ritz step is taken every eighth step until two of
+// them agree to 1e-9, then every step; the search stops when lambda_2 has
+// changed by at most 1e-13 (1 + |lambda_2|) and the next modulus by at most
+// 1e-11 (1 + |lambda_2|) in two successive steps, or after max_iter steps.  A basis vector that A
 // annihilates (its orthogonalised norm below 1e-14 of its norm) stays zero.
 // IN_LDS: the NVEC vectors live in LDS (n <= kSpecLdsMaxN); g, 1/S and pi
 // are copied to the workspace at the end for the mixing search.
@@ -749,29 +750,46 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
   double re = 0.0, im = 0.0, l3 = 0.0, change = 0.0, prev_re = 2.0, prev_im = 2.0, prev_l3 = 2.0;
   int it = 0, settled = 0, flags = 0;
   bool all_ok = true;
+  int next_rr = 8;     // step count at which the next Rayleigh-Ritz step is taken
+  bool fine = false;   // Ritz values within 1e-9 of settling: take one every step
   for (; it < max_iter; ++it) {
-    // Q = orthonormal basis of W (two classical Gram-Schmidt passes)
+    // Q = orthonormal basis of W: two classical Gram-Schmidt passes; the
+    // second pass's reduction also gives ||v||^2 and sum(v), from which the
+    // norm and sum after its projection follow (the q_a are orthonormal:
+    // ||v - sum d_a q_a||^2 = ||v||^2 - sum d_a^2)
     double s[KSUB];
 #pragma unroll
     for (int i = 0; i < KSUB; ++i) {
       s[i] = 0.0;
       if (i >= ke) continue;
       for (int j = j0; j < j1; ++j) Q[i][j] = W[i][j];
-      double n0 = 0.0;
+      double n0 = 0.0, nrm2 = 0.0, sum = 0.0;
 #pragma unroll
       for (int pass = 0; pass < 2; ++pass) {
-        double d[KSUB + 1];
+        double d[KSUB + 2];
 #pragma unroll
-        for (int a = 0; a <= KSUB; ++a) d[a] = 0.0;
+        for (int a = 0; a < KSUB + 2; ++a) d[a] = 0.0;
         for (int j = j0; j < j1; ++j) {
           const double qi = Q[i][j];
 #pragma unroll
           for (int a = 0; a < KSUB; ++a)
             if (a < i) d[a] += Q[a][j] * qi;
           d[KSUB] += qi * qi;
+          d[KSUB + 1] += qi;
         }
-        block_sum_n<KSUB + 1>(d, red);
-        if (pass == 0) n0 = d[KSUB];
+        block_sum_n<KSUB + 2>(d, red);
+        if (pass == 0) {
+          n0 = d[KSUB];
+        } else {
+          nrm2 = d[KSUB];
+          sum = d[KSUB + 1];
+#pragma unroll
+          for (int a = 0; a < KSUB; ++a)
+            if (a < i) {
+              nrm2 -= d[a] * d[a];
+              sum -= d[a] * s[a];
+            }
+        }
         for (int j = j0; j < j1; ++j) {
           double v = Q[i][j];
 #pragma unroll
@@ -780,21 +798,18 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
           Q[i][j] = v;
         }
       }
-      double t[2] = {0.0, 0.0};
-      for (int j = j0; j < j1; ++j) {
-        t[0] += Q[i][j] * Q[i][j];
-        t[1] += Q[i][j];
-      }
-      block_sum_n<2>(t, red);
-      const double sc = (t[0] > 1e-28 * n0 && t[0] > 0.0) ? 1.0 / sqrt(t[0]) : 0.0;
+      const double sc = (nrm2 > 1e-28 * n0 && nrm2 > 0.0) ? 1.0 / sqrt(nrm2) : 0.0;
       for (int j = j0; j < j1; ++j) Q[i][j] *= sc;
-      s[i] = t[1] * sc;
+      s[i] = sum * sc;
       __syncthreads();
     }
-    // W = A Q and the Rayleigh quotient H = Q^T W
+    // W = A Q
 #pragma unroll
     for (int i = 0; i < KSUB; ++i)
       if (i < ke) deflated(m, V, c, Q[i], s[i], W[i], red);
+    // Rayleigh-Ritz every eighth step until the Ritz values have nearly
+    // settled, then every step
+    if (!fine && it + 1 < next_rr && it + 1 < max_iter) continue;
     double h[KSUB * KSUB];
 #pragma unroll
     for (int e = 0; e < KSUB * KSUB; ++e) h[e] = 0.0;
@@ -829,12 +844,18 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
     l3 = 0.0;
     for (int i = 0; i < ke; ++i)
       if (i != i2 && i != partner) l3 = fmax(l3, hypot(er[i], ei[i]));
-    change = fmax(hypot(re - prev_re, im - prev_im), fabs(l3 - prev_l3));
-    settled = change <= 1e-13 * (1.0 + a2) ? settled + 1 : 0;
+    const double ch2 = hypot(re - prev_re, im - prev_im), ch3 = fabs(l3 - prev_l3);
+    change = fmax(ch2, ch3);
     prev_re = re;
     prev_im = im;
     prev_l3 = l3;
     __syncthreads();  // every thread has read er / ei before the next step writes them
+    if (!fine) {
+      fine = change <= 1e-9 * (1.0 + a2);
+      next_rr = it + 1 + 8;
+      continue;
+    }
+    settled = (ch2 <= 1e-13 * (1.0 + a2) && ch3 <= 1e-11 * (1.0 + a2)) ? settled + 1 : 0;
     if (settled >= 2) break;
   }
   if (settled < 2) flags |= DTM_SPECTRAL_UNSETTLED;

@@ -5,6 +5,7 @@
 // update are float32.  Float32 master weights, bfloat16 copies for the GEMMs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -43,14 +44,20 @@ enum Epi { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2 };
 // C[M x N] = op(A)[M x K] op(B)[K x N] with op(A)[i][k] = TA ? A[k*lda+i] :
 // A[i*lda+k] and op(B)[k][j] = TB ? B[j*ldb+k] : B[k*ldb+j].  A 64 x 64 tile
 // per block of 4 wavefronts, each wavefront a 32 x 32 quarter computed as
-// 2 x 2 v_mfma_f32_16x16x16_bf16 tiles; K advances by GK = 64 through LDS
-// (four MFMA steps of 16 per stage, in k order).
-// Lane layout of the 16x16x16 instruction: lane l supplies A[l%16][4(l/16)+r]
-// and B[4(l/16)+r][l%16] (r = 0..3) and receives D[4(l/16)+r][l%16].
+// 2 x 2 v_mfma_f32_16x16x32_bf16 tiles; K advances by GK = 64 through LDS
+// (two MFMA steps of 32 per stage, in k order).
+// Lane layout of the 16x16x32 instruction: lane l supplies A[l%16][8(l/16)+r]
+// and B[8(l/16)+r][l%16] (r = 0..7) and receives D[4(l/16)+r][l%16]
+// (r = 0..3).
+// Split K (gridDim.z > 1): block z covers k in [z kc, (z + 1) kc) and
+// writes its partial product to C + z * M * ldc; k_sum_splits adds the
+// partials in z order.
 // Out-of-range elements load as zero and are not stored.
 constexpr int GK = 64;
+constexpr int LDS_PITCH = GK + 8;  // 144-byte rows: every 8-element k run is one aligned 16-byte LDS read
 
 typedef uint16_t bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 mfma_bf16x8 __attribute__((ext_vector_type(8)));
 
 // Thread tid's share of a 64 x GK operand tile T[r][kk] = op(X)[o + r][k0 + kk]:
 // the 16 elements idx = 16 tid + e.  ALONG_R: X is stored k-major
@@ -58,7 +65,7 @@ typedef uint16_t bf16x8 __attribute__((ext_vector_type(8)));
 // run goes along kk.  Out-of-range elements are zero.
 template <bool ALONG_R>
 __device__ inline void load_run(const bf16* __restrict__ X, int ld, int rows, int K, int o, int k0, int tid,
-                                bf16 (&T)[64][GK + 4]) {
+                                bf16 (&T)[64][LDS_PITCH]) {
   const int idx0 = tid * 16;
   const int r0 = ALONG_R ? idx0 % 64 : idx0 / GK, kk0 = ALONG_R ? idx0 / 64 : idx0 % GK;
   const int gi0 = o + r0, gk0 = k0 + kk0;
@@ -91,42 +98,40 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
                                               int lda, const bf16* __restrict__ B, int ldb,
                                               float* __restrict__ C, int ldc,
                                               const float* __restrict__ bias,
-                                              bf16* __restrict__ Hout, int ldh) {
-  __shared__ bf16 As[64][GK + 4];
-  __shared__ bf16 Bs[64][GK + 4];  // transposed: Bs[j][k]
+                                              bf16* __restrict__ Hout, int ldh, int kc) {
+  __shared__ __align__(16) bf16 As[64][LDS_PITCH];
+  __shared__ __align__(16) bf16 Bs[64][LDS_PITCH];  // transposed: Bs[j][k]
   const int tid = threadIdx.x;
   const int lane = tid % 64, wave = tid / 64;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   const int wi = (wave / 2) * 32, wj = (wave % 2) * 32;
+  const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
+  C += static_cast<int64_t>(blockIdx.z) * M * ldc;
   f32x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += GK) {
+  for (int k0 = kb; k0 < ke; k0 += GK) {
     // 64 x GK tiles: thread t loads 16 consecutive elements of each along
     // the operand's contiguous dimension (k for a row-major A or a
     // transposed B, the row or column index otherwise): two 16-byte loads
     // when the run is in range and aligned, else element by element
-    load_run<TA>(A, lda, M, K, i0, k0, tid, As);
-    load_run<!TB>(B, ldb, N, K, j0, k0, tid, Bs);
+    load_run<TA>(A, lda, M, ke, i0, k0, tid, As);
+    load_run<!TB>(B, ldb, N, ke, j0, k0, tid, Bs);
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < GK; ks += 16) {
-      const int kq = ks + 4 * (lane / 16);
+    for (int ks = 0; ks < GK; ks += 32) {
+      const int kq = ks + 8 * (lane / 16);
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        bf16x4 fa;
         const int ra = wi + a * 16 + lane % 16;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) fa[r] = static_cast<short>(As[ra][kq + r]);
+        const mfma_bf16x8 fa = *reinterpret_cast<const mfma_bf16x8*>(&As[ra][kq]);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          bf16x4 fb;
           const int cb = wj + b * 16 + lane % 16;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) fb[r] = static_cast<short>(Bs[cb][kq + r]);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa, fb, acc[a][b], 0, 0, 0);
+          const mfma_bf16x8 fb = *reinterpret_cast<const mfma_bf16x8*>(&Bs[cb][kq]);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[a][b], 0, 0, 0);
         }
       }
     }
@@ -148,6 +153,15 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
       }
 }
 
+// C[i][j] = sum over z of part[z][i][j] (M x N, row-major, dense), in z order.
+__global__ void k_sum_splits(const float* __restrict__ part, int splits, int64_t mn, float* __restrict__ C) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= mn) return;
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += part[static_cast<int64_t>(z) * mn + idx];
+  C[idx] = s;
+}
+
 // Features of a scene, fixed affine maps onto about [-1, 1]:
 //   2 tau / t_r - 1, sigma / 1 ns, 2 (ln S - ln 0.05) / ln 100 - 1,
 //   2 (ln B - ln 0.01) / ln 100 - 1, (t_d mod t_r) / t_r.
@@ -163,6 +177,45 @@ __global__ void k_features(const dtm_scene* __restrict__ scenes, int n, float* _
   feat[p * IN + 4] = static_cast<float>(fmod(s.dead_time_ns, s.period_ns) / s.period_ns);
 }
 
+// Prior logits of the warm start: log(lambda_j / sum_k lambda_k) at the OUT
+// bin centres s_j = (j + 1/2) t_r / OUT of each scene, lambda of
+// Eq. (arrival_flux) (the flux start of the solver, the stationary vector
+// without dead time).  Float64 in the log domain (a Gaussian far from its
+// centre would underflow as a flux), stored as float32.  One block of 256
+// threads per scene.
+__global__ __launch_bounds__(256) void k_flux_prior(const dtm_scene* __restrict__ scenes, float* __restrict__ prior) {
+  __shared__ double red[4];
+  const dtm_scene s = scenes[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  const double delta = s.period_ns / OUT, is = 1.0 / s.pulse_sigma_ns;
+  const double la = s.signal_flux > 0.0 ? log(s.signal_flux * 0.39894228040143267794 * is) : -INFINITY;
+  const double lb = s.background_flux > 0.0 ? log(s.background_flux / s.period_ns) : -INFINITY;
+  double lv[4], mx = -INFINITY;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double z = ((tid + 256 * r + 0.5) * delta - s.pulse_center_ns) * is;
+    const double a = la - 0.5 * z * z;
+    const double hi = fmax(a, lb), lo = fmin(a, lb);
+    lv[r] = hi == -INFINITY ? -INFINITY : hi + log1p(exp(lo - hi));
+    mx = fmax(mx, lv[r]);
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) red[w] = mx;
+  __syncthreads();
+  mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  double sum = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) sum += exp(lv[r] - mx);
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+  if (lane == 0) red[w] = sum;
+  __syncthreads();
+  const double lse = mx + log((red[0] + red[1]) + (red[2] + red[3]));
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    prior[static_cast<int64_t>(blockIdx.x) * OUT + tid + 256 * r] = static_cast<float>(lv[r] - lse);
+}
+
 // X0 (bfloat16, rows padded to INP columns with zeros).
 __global__ void k_pack_input(const float* __restrict__ feat, int batch, bf16* __restrict__ x0) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -171,10 +224,13 @@ __global__ void k_pack_input(const float* __restrict__ feat, int batch, bf16* __
   x0[idx] = k < IN ? f2bf(feat[i * IN + k]) : static_cast<bf16>(0);
 }
 
-// Row-wise softmax of the logits; optionally cross-entropy against a target
-// distribution with its gradient dZ = (q - target) / batch (float32 and
-// bfloat16).  One block of 256 threads per row of OUT = 1024 logits.
+// Row-wise softmax of the logits plus the prior logits (when given);
+// optionally cross-entropy against a target distribution with its gradient
+// dZ = (q - target) / batch (float32 and bfloat16; the prior is a constant,
+// so the gradient is the same).  One block of 256 threads per row of
+// OUT = 1024 logits.
 __global__ __launch_bounds__(256) void k_softmax_xent(const float* __restrict__ z, int batch,
+                                                      const float* __restrict__ prior,
                                                       const float* __restrict__ target,
                                                       float* __restrict__ q_out,
                                                       float* __restrict__ dz, bf16* __restrict__ dzb,
@@ -188,6 +244,7 @@ __global__ __launch_bounds__(256) void k_softmax_xent(const float* __restrict__ 
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     v[r] = zr[tid + 256 * r];
+    if (prior) v[r] += prior[static_cast<int64_t>(i) * OUT + tid + 256 * r];
     mx = fmaxf(mx, v[r]);
   }
   for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
@@ -212,10 +269,11 @@ __global__ __launch_bounds__(256) void k_softmax_xent(const float* __restrict__ 
   for (int r = 0; r < 4; ++r) {
     const int j = tid + 256 * r;
     const float q = v[r] / s;
+    const float zj = zr[j] + (prior ? prior[static_cast<int64_t>(i) * OUT + j] : 0.f);
     if (q_out) q_out[static_cast<int64_t>(i) * OUT + j] = q;
     if (target) {
       const float t = target[static_cast<int64_t>(i) * OUT + j];
-      l -= t * (zr[j] - lse);
+      l -= t * (zj - lse);
       const float g = (q - t) / batch;
       dz[static_cast<int64_t>(i) * OUT + j] = g;
       dzb[static_cast<int64_t>(i) * OUT + j] = f2bf(g);
@@ -308,7 +366,30 @@ struct Ptrs {
   bf16* x0;
   float *a1, *a2, *z, *q, *dz, *dh2, *da2, *dh1, *da1, *loss;
   bf16 *h1, *h2, *dzb, *da2b, *da1b;
+  float* partial;
 };
+
+// Split of K (= the batch) for a weight-gradient GEMM with an M x N output:
+// enough blocks to cover the chip's 256 CUs once (at most 16 splits), chunks
+// of at least GK.  Returns the chunk length kc (a multiple of GK); the split
+// count is ceil(K / kc).
+int grad_chunk(int M, int N, int K) {
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int s = std::max(1, std::min(16, 256 / tiles));
+  s = std::min(s, std::max(1, K / GK));
+  return ((K + s - 1) / s + GK - 1) / GK * GK;
+}
+int64_t grad_partial_floats(int M, int N, int K) {
+  const int kc = grad_chunk(M, N, K);
+  const int s = (K + kc - 1) / kc;
+  return s > 1 ? static_cast<int64_t>(s) * M * N : 0;
+}
+// Largest partial buffer of the three weight gradients at this batch size
+// (the split count never falls as the batch grows).
+int64_t partial_floats(int32_t max_batch) {
+  return std::max(grad_partial_floats(H, OUT, max_batch),
+                  std::max(grad_partial_floats(H, H, max_batch), grad_partial_floats(INP, H, max_batch)));
+}
 
 void layout(int32_t max_batch, dtm_mlp_layout* L) {
   const int64_t B = max_batch;
@@ -351,6 +432,8 @@ void layout(int32_t max_batch, dtm_mlp_layout* L) {
   take(4 * B * H);              // da1
   take(2 * B * H);              // da1b
   take(4 * B);                  // loss
+  // split-K partial products of the weight gradients
+  L->partial = take(4 * partial_floats(max_batch));
   L->total = off;
 }
 
@@ -392,6 +475,7 @@ Ptrs pointers(void* ws, int32_t max_batch) {
   P.da1 = reinterpret_cast<float*>(take(4 * B * H));
   P.da1b = reinterpret_cast<bf16*>(take(2 * B * H));
   P.loss = reinterpret_cast<float*>(take(4 * B));
+  P.partial = reinterpret_cast<float*>(w + L.partial);
   return P;
 }
 
@@ -400,7 +484,27 @@ void gemm(int M, int N, int K, const bf16* A, int lda, const bf16* B, int ldb, f
           const float* bias, bf16* Hout, int ldh, hipStream_t st) {
   dim3 grid((N + 63) / 64, (M + 63) / 64);
   hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc,
-                     bias, Hout, ldh);
+                     bias, Hout, ldh, K);
+}
+
+// Weight gradient C (M x N, dense) = A^T B with K = the batch, K split over
+// blocks when the output alone has too few tiles to fill the chip; the
+// partial products go to `part` and are added in split order (the result
+// does not depend on timing).
+void gemm_grad(int M, int N, int K, const bf16* A, int lda, const bf16* B, int ldb, float* C, float* part,
+               hipStream_t st) {
+  const int kc = grad_chunk(M, N, K);
+  const int splits = (K + kc - 1) / kc;
+  if (splits == 1) {
+    gemm<true, false, EPI_STORE>(M, N, K, A, lda, B, ldb, C, N, nullptr, nullptr, 0, st);
+    return;
+  }
+  dim3 grid((N + 63) / 64, (M + 63) / 64, splits);
+  hipLaunchKernelGGL((k_gemm<true, false, EPI_STORE>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, part, N,
+                     nullptr, nullptr, 0, kc);
+  const int64_t mn = static_cast<int64_t>(M) * N;
+  hipLaunchKernelGGL(k_sum_splits, dim3(static_cast<unsigned>((mn + 255) / 256)), dim3(256), 0, st, part, splits,
+                     mn, C);
 }
 
 // Forward pass for `batch` rows of features; leaves every activation in the
@@ -450,41 +554,48 @@ int dtm_mlp_sync_bf16(void* ws, int32_t max_batch, dtm_stream_t stream) {
   return ok_launch();
 }
 
-int dtm_mlp_forward(void* ws, int32_t max_batch, const float* feat_dev, int32_t batch,
+int dtm_mlp_flux_prior(const dtm_scene* scenes_dev, int32_t n, float* prior_dev, dtm_stream_t stream) {
+  if (!scenes_dev || !prior_dev || n < 1) return DTM_EINVAL;
+  hipLaunchKernelGGL(k_flux_prior, dim3(n), dim3(256), 0, static_cast<hipStream_t>(stream), scenes_dev,
+                     prior_dev);
+  return ok_launch();
+}
+
+int dtm_mlp_forward(void* ws, int32_t max_batch, const float* feat_dev, const float* prior_dev, int32_t batch,
                     float* probs_dev, dtm_stream_t stream) {
   if (!ws || !feat_dev || !probs_dev || !batch_ok(batch, max_batch)) return DTM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Ptrs P = pointers(ws, max_batch);
   forward(P, feat_dev, batch, st);
-  hipLaunchKernelGGL(k_softmax_xent, dim3(batch), dim3(256), 0, st, P.z, batch, nullptr, probs_dev,
+  hipLaunchKernelGGL(k_softmax_xent, dim3(batch), dim3(256), 0, st, P.z, batch, prior_dev, nullptr, probs_dev,
                      nullptr, nullptr, nullptr);
   return ok_launch();
 }
 
-int dtm_mlp_backward(void* ws, int32_t max_batch, const float* feat_dev, const float* target_dev,
-                     int32_t batch, float* loss_dev, dtm_stream_t stream) {
+int dtm_mlp_backward(void* ws, int32_t max_batch, const float* feat_dev, const float* prior_dev,
+                     const float* target_dev, int32_t batch, float* loss_dev, dtm_stream_t stream) {
   if (!ws || !feat_dev || !target_dev || !batch_ok(batch, max_batch)) return DTM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Ptrs P = pointers(ws, max_batch);
   forward(P, feat_dev, batch, st);
-  hipLaunchKernelGGL(k_softmax_xent, dim3(batch), dim3(256), 0, st, P.z, batch, target_dev, P.q,
+  hipLaunchKernelGGL(k_softmax_xent, dim3(batch), dim3(256), 0, st, P.z, batch, prior_dev, target_dev, P.q,
                      P.dz, P.dzb, loss_dev ? loss_dev : P.loss);
   // layer 3: dW3 = H2^T dZ, db3 = sum dZ, dH2 = dZ W3^T
-  gemm<true, false, EPI_STORE>(H, OUT, batch, P.h2, H, P.dzb, OUT, P.gw3, OUT, nullptr, nullptr, 0, st);
+  gemm_grad(H, OUT, batch, P.h2, H, P.dzb, OUT, P.gw3, P.partial, st);
   hipLaunchKernelGGL(k_bias_grad, dim3((OUT + BG_COLS - 1) / BG_COLS), dim3(BG_THREADS), 0, st, P.dz, batch, OUT,
                      P.gb3);
   gemm<false, true, EPI_STORE>(batch, H, OUT, P.dzb, OUT, P.w3b, OUT, P.dh2, H, nullptr, nullptr, 0, st);
   hipLaunchKernelGGL(k_gelu_back, dim3((batch * H + 255) / 256), dim3(256), 0, st, P.dh2, P.a2,
                      batch * H, P.da2, P.da2b);
   // layer 2
-  gemm<true, false, EPI_STORE>(H, H, batch, P.h1, H, P.da2b, H, P.gw2, H, nullptr, nullptr, 0, st);
+  gemm_grad(H, H, batch, P.h1, H, P.da2b, H, P.gw2, P.partial, st);
   hipLaunchKernelGGL(k_bias_grad, dim3((H + BG_COLS - 1) / BG_COLS), dim3(BG_THREADS), 0, st, P.da2, batch, H,
                      P.gb2);
   gemm<false, true, EPI_STORE>(batch, H, H, P.da2b, H, P.w2b, H, P.dh1, H, nullptr, nullptr, 0, st);
   hipLaunchKernelGGL(k_gelu_back, dim3((batch * H + 255) / 256), dim3(256), 0, st, P.dh1, P.a1,
                      batch * H, P.da1, P.da1b);
   // layer 1
-  gemm<true, false, EPI_STORE>(INP, H, batch, P.x0, INP, P.da1b, H, P.gw1, H, nullptr, nullptr, 0, st);
+  gemm_grad(INP, H, batch, P.x0, INP, P.da1b, H, P.gw1, P.partial, st);
   hipLaunchKernelGGL(k_bias_grad, dim3((H + BG_COLS - 1) / BG_COLS), dim3(BG_THREADS), 0, st, P.da1, batch, H,
                      P.gb1);
   return ok_launch();

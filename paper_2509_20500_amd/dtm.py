@@ -61,7 +61,7 @@ SYMBOLS = [
     "dtm_plan_tiles", "dtm_plan_bind", "dtm_solve_batched", "dtm_build_base_batched",
     "dtm_apply_deadtime_shift_batched", "dtm_build_transition_batched",
     "dtm_graph_create", "dtm_graph_launch", "dtm_graph_destroy",
-    "dtm_mlp_workspace_layout", "dtm_mlp_features", "dtm_mlp_sync_bf16", "dtm_mlp_forward",
+    "dtm_mlp_workspace_layout", "dtm_mlp_features", "dtm_mlp_flux_prior", "dtm_mlp_sync_bf16", "dtm_mlp_forward",
     "dtm_mlp_backward", "dtm_mlp_adam", "dtm_mlp_gemm_bf16",
     "dtm_solve_factored_batched", "dtm_spectral_scratch_bytes", "dtm_spectral_batched",
     "dtm_mc_scratch_bytes", "dtm_mc_histograms", "dtm_stationary_pdf_noalloc",

@@ -6,9 +6,14 @@ and saves / restores checkpoints.
 Typical use::
 
     net = WarmStartMLP(max_batch=1024, seed=0)
-    net.fit(feat, targets, epochs=20)          # feat: P x 5, targets: P x 1024 (device)
-    x0 = net.predict(net.features(scenes))     # P x 1024 float32, rows sum to 1
-    plan.solve(pi, infos, x0=x0.reshape(-1))   # uniform fallback is automatic
+    feat, prior = net.features(scenes), net.flux_prior(scenes)
+    net.fit(feat, targets, epochs=20, prior=prior)   # targets: P x 1024 (device)
+    x0 = net.predict(feat, prior)                    # P x 1024 float32, rows sum to 1
+    plan.solve(pi, infos, x0=x0.reshape(-1))         # uniform fallback is automatic
+
+With ``prior`` (the log of the flux start lambda / sum(lambda), see
+``dtm_mlp_flux_prior``) the network's logits are added to it, so it learns a
+correction to the solver's flux start; without it, the whole PDF.
 """
 from __future__ import annotations
 
@@ -27,7 +32,7 @@ class Layout(ctypes.Structure):
     _fields_ = [
         ("params", ctypes.c_size_t), ("params_bf16", ctypes.c_size_t), ("grads", ctypes.c_size_t),
         ("adam_m", ctypes.c_size_t), ("adam_v", ctypes.c_size_t), ("act", ctypes.c_size_t),
-        ("total", ctypes.c_size_t),
+        ("partial", ctypes.c_size_t), ("total", ctypes.c_size_t),
         ("off_w1", ctypes.c_int64), ("off_b1", ctypes.c_int64), ("off_w2", ctypes.c_int64),
         ("off_b2", ctypes.c_int64), ("off_w3", ctypes.c_int64), ("off_b3", ctypes.c_int64),
         ("n_params", ctypes.c_int64), ("max_batch", ctypes.c_int32), ("reserved", ctypes.c_int32),
@@ -49,8 +54,9 @@ def _bind():
         "dtm_mlp_workspace_layout": (ctypes.c_int, [_I32, ctypes.POINTER(Layout)]),
         "dtm_mlp_features": (ctypes.c_int, [_P, _I32, _P, _P]),
         "dtm_mlp_sync_bf16": (ctypes.c_int, [_P, _I32, _P]),
-        "dtm_mlp_forward": (ctypes.c_int, [_P, _I32, _P, _I32, _P, _P]),
-        "dtm_mlp_backward": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _P, _P]),
+        "dtm_mlp_flux_prior": (ctypes.c_int, [_P, _I32, _P, _P]),
+        "dtm_mlp_forward": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _P, _P]),
+        "dtm_mlp_backward": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I32, _P, _P]),
         "dtm_mlp_adam": (ctypes.c_int, [_P, _I32, _F, _F, _F, _F, _I32, _P]),
         "dtm_mlp_gemm_bf16": (ctypes.c_int, [_I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _I32, _P,
                                              _I32, _P]),
@@ -119,7 +125,10 @@ def solve_targets(scenes, dtype="f32", chunk=16384, solve_opts=None, x0=None):
 
 
 class WarmStartMLP:
-    def __init__(self, max_batch=1024, seed=0, device="cuda"):
+    """zero_output: start with a zero output layer, so that with a prior the
+    untrained network predicts the prior itself (the flux start)."""
+
+    def __init__(self, max_batch=1024, seed=0, device="cuda", zero_output=False):
         import torch
         if not 1 <= max_batch <= MAX_BATCH:
             raise ValueError("max_batch out of range")
@@ -128,7 +137,7 @@ class WarmStartMLP:
         self.L = layout(max_batch)
         self.ws = torch.zeros(self.L.total, dtype=torch.uint8, device=device)
         self.step = 0
-        self.init_weights(seed)
+        self.init_weights(seed, zero_output)
 
     # ---- views into the workspace -------------------------------------------
     def _f32(self, byte_off, n):
@@ -151,9 +160,10 @@ class WarmStartMLP:
             "W3": flat[L.off_w3:L.off_b3].view(HIDDEN, OUT), "b3": flat[L.off_b3:L.n_params],
         }
 
-    def init_weights(self, seed):
-        """Uniform(+-1/sqrt(fan_in)) weights, zero biases, zero Adam moments
-        (seeded NumPy PCG64); padded input rows of W1 stay zero."""
+    def init_weights(self, seed, zero_output=False):
+        """Uniform(+-1/sqrt(fan_in)) weights (W3 zero with zero_output), zero
+        biases, zero Adam moments (seeded NumPy PCG64); padded input rows of
+        W1 stay zero."""
         import torch
         rng = np.random.default_rng(seed)
         flat = np.zeros(self.L.n_params, dtype=np.float32)
@@ -163,6 +173,8 @@ class WarmStartMLP:
             w = np.zeros((rows, cols), dtype=np.float32)
             a = 1.0 / math.sqrt(fan_in)
             w[:fan_in] = rng.uniform(-a, a, (fan_in, cols))
+            if zero_output and off == L.off_w3:
+                w[:] = 0.0
             flat[off:off + rows * cols] = w.ravel()
         self.params.copy_(torch.from_numpy(flat))
         self._f32(self.L.adam_m, self.L.n_params).zero_()
@@ -185,22 +197,36 @@ class WarmStartMLP:
                   "dtm_mlp_features")
         return feat
 
-    def predict(self, feat, stream=None):
-        """softmax(network(feat)) for any number of rows, in max_batch chunks."""
+    def flux_prior(self, scenes, stream=None):
+        """log(lambda_j / sum lambda) at the 1024 bin centres of each scene
+        (P x 1024 float32 on the device), computed on the GPU."""
+        import torch
+        arr = np.ascontiguousarray(scenes)
+        raw = torch.from_numpy(arr.view(np.uint8).copy()).to(self.ws.device)
+        prior = torch.empty((arr.size, OUT), dtype=torch.float32, device=self.ws.device)
+        dtm.check(_bind().dtm_mlp_flux_prior(raw.data_ptr(), arr.size, prior.data_ptr(), dtm._stream(stream)),
+                  "dtm_mlp_flux_prior")
+        return prior
+
+    def predict(self, feat, prior=None, stream=None):
+        """softmax(network(feat) + prior) for any number of rows, in max_batch
+        chunks (prior: P x 1024 float32, or None)."""
         import torch
         P = feat.shape[0]
         out = torch.empty((P, OUT), dtype=torch.float32, device=self.ws.device)
         for a in range(0, P, self.max_batch):
             b = min(P, a + self.max_batch)
             dtm.check(_bind().dtm_mlp_forward(self.ws.data_ptr(), self.max_batch, feat[a:b].data_ptr(),
+                                              None if prior is None else prior[a:b].data_ptr(),
                                               b - a, out[a:b].data_ptr(), dtm._stream(stream)),
                       "dtm_mlp_forward")
         return out
 
-    def backward(self, feat, target, loss=None, stream=None):
+    def backward(self, feat, target, loss=None, prior=None, stream=None):
         """Gradients of the mean cross-entropy into ``grads`` (one batch)."""
         B = feat.shape[0]
         dtm.check(_bind().dtm_mlp_backward(self.ws.data_ptr(), self.max_batch, feat.data_ptr(),
+                                           None if prior is None else prior.data_ptr(),
                                            target.data_ptr(), B, None if loss is None else loss.data_ptr(),
                                            dtm._stream(stream)), "dtm_mlp_backward")
 
@@ -209,9 +235,10 @@ class WarmStartMLP:
         dtm.check(_bind().dtm_mlp_adam(self.ws.data_ptr(), self.max_batch, lr, beta1, beta2, eps, self.step,
                                        dtm._stream(stream)), "dtm_mlp_adam")
 
-    def fit(self, feat, target, epochs=20, lr=1e-3, seed=0, log=None):
+    def fit(self, feat, target, epochs=20, lr=1e-3, seed=0, log=None, prior=None):
         """Adam with cosine-decayed learning rate over shuffled mini-batches
-        of max_batch rows; returns the mean loss of each epoch."""
+        of max_batch rows (prior: P x 1024 prior logits, or None); returns the
+        mean loss of each epoch."""
         import torch
         P = feat.shape[0]
         B = self.max_batch
@@ -230,7 +257,8 @@ class WarmStartMLP:
                 idx = perm[b * B:(b + 1) * B]
                 xb = feat.index_select(0, idx).contiguous()
                 tb = target.index_select(0, idx).contiguous()
-                self.backward(xb, tb, loss)
+                pb = None if prior is None else prior.index_select(0, idx).contiguous()
+                self.backward(xb, tb, loss, prior=pb)
                 t = self.step / max(1, total - 1)
                 self.adam(lr * 0.5 * (1.0 + math.cos(math.pi * min(1.0, t))))
                 acc += loss.double().mean()

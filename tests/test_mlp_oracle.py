@@ -55,3 +55,49 @@ def test_gradients_match_finite_differences():
             fd = (lp - lm) / (2 * h)
             an = G[name].reshape(-1)[idx]
             assert abs(fd - an) <= 1e-6 * max(1e-3, abs(an)) + 1e-9, (name, idx, fd, an)
+
+
+def test_gradients_with_prior_match_finite_differences():
+    """The prior is a constant shift of the logits: the chain rule is the
+    same, only Q moves."""
+    rng = np.random.default_rng(4)
+    P = _params(rng)
+    X = rng.normal(size=(2, mlp.IN))
+    prior = rng.normal(0, 2.0, size=(2, mlp.OUT))
+    T = rng.uniform(size=(2, mlp.OUT))
+    T /= T.sum(axis=1, keepdims=True)
+    G = mlp.grads(P, X, T, prior)
+    h = 1e-6
+    for name, arr in P.items():
+        flat = arr.reshape(-1)
+        for idx in rng.choice(flat.size, 6, replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = mlp.loss(P, X, T, prior)
+            flat[idx] = old - h
+            lm = mlp.loss(P, X, T, prior)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = G[name].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * max(1e-3, abs(an)) + 1e-9, (name, idx, fd, an)
+    # a prior constant along a row changes nothing
+    Q0, _ = mlp.forward(P, X)
+    Q1, _ = mlp.forward(P, X, np.full((2, mlp.OUT), 3.7))
+    assert np.allclose(Q0, Q1, atol=1e-15)
+
+
+def test_flux_prior_special_cases():
+    # pure background: the flux is constant, the prior uniform
+    s = sc.scene(period=80.0, dead_time=30.0, center=20.0, sigma=0.5, signal=0.0, background=0.7)
+    assert np.allclose(mlp.flux_prior(s), -np.log(mlp.OUT), atol=1e-13)
+    # no background: a sampled Gaussian whose height S / (sigma sqrt(2 pi))
+    # drops out, so the prior does not depend on S
+    a = mlp.flux_prior(sc.scene(period=100.0, center=40.0, sigma=2.0, signal=0.3, background=0.0))
+    b = mlp.flux_prior(sc.scene(period=100.0, center=40.0, sigma=2.0, signal=3.0, background=0.0))
+    assert np.allclose(a, b, atol=1e-12)
+    z = ((np.arange(mlp.OUT) + 0.5) * 100.0 / mlp.OUT - 40.0) / 2.0
+    ref = -0.5 * z * z - np.log(np.exp(-0.5 * z * z).sum())
+    assert np.allclose(a, ref, atol=1e-12)
+    # every prior is a log-distribution
+    for s in sc.batched_uniform(8, seed=12):
+        assert abs(np.exp(mlp.flux_prior(s)).sum() - 1.0) < 1e-12
