@@ -894,8 +894,10 @@ def main():
     ap.add_argument("--fused-max-bins", type=int, default=0, help="largest n of the one-block solver (0 = default)")
     ap.add_argument("--band-rows", type=int, default=0, help="rows per banded work item (0 = default)")
     ap.add_argument("--band-cpt", type=int, default=0, help="column vectors per thread, banded (0 = default)")
-    ap.add_argument("--band-sweeps", type=int, default=0,
-                    help="dense sweeps launched for banded pixels before the float64 continuation (0 = default)")
+    ap.add_argument("--independent-paths", type=int, default=0, choices=[0, 1],
+                    help="1: one-block and banded pixels sweep without waiting for each other's builds")
+    ap.add_argument("--dense-sweeps", type=int, default=0,
+                    help="sweeps of a pixel's dense matrix before the float64 continuation (0 = default)")
     ap.add_argument("--variant", default="paper",
                     choices=["paper", "nearest", "bin_mean", "bin_integral", "interp"],
                     help="discretisation of the model (interp needs --solver factored)")
@@ -931,9 +933,10 @@ def main():
         scenes = sc.batched_uniform(n_pixels=args.pixels or 4096)
     sopts = dtm.opts(tol=1e-6)
     tune_report = None
-    if args.threads or args.unroll or args.band_rows or args.band_cpt or args.fused_max_bins or args.band_sweeps:
-        tiles = dtm.tiles(args.threads, args.unroll, args.fused_max_bins, args.band_rows, args.band_sweeps,
-                          args.band_cpt)
+    if (args.threads or args.unroll or args.band_rows or args.band_cpt or args.fused_max_bins or args.dense_sweeps
+            or args.independent_paths):
+        tiles = dtm.tiles(args.threads, args.unroll, args.fused_max_bins, args.band_rows, args.dense_sweeps,
+                          args.band_cpt, args.independent_paths)
     elif args.autotune:
         from paper_2509_20500_amd.autotune import autotune
         tiles, tune_report = autotune(scenes, args.dtype, sopts)
@@ -981,8 +984,12 @@ def main():
     n = scenes["n_bins"].astype(np.float64)
     es = 4 if args.dtype == "f32" else 8
     # algorithmic bytes: each matrix written once; every sweep after the
-    # first (taken while the matrix is built) reads it once
-    alg_bytes = float(np.sum(es * n * n * info["iterations"]))
+    # first (taken while the matrix is built) reads it once.  A pixel
+    # continued in float64 past its dense sweeps reads its matrix only in
+    # those sweeps (the continuation uses the factored product)
+    dense_passes = np.where((info["flags"] & dtm.DTM_INFO_CONTINUED) != 0,
+                            np.minimum(info["iterations"], plan.tiles.dense_sweeps), info["iterations"])
+    alg_bytes = float(np.sum(es * n * n * dense_passes))
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     value = plan.n_pixels / (ms_step * 1e-3)
     # factored sweeps: about 12 float64 operations per bin per sweep
@@ -1103,6 +1110,7 @@ def main():
                        "min": int(info["iterations"].min())},
         "all_converged": bool(np.all(info["status"] == 0)),
         "refined_pixels": int(np.sum((info["flags"] & dtm.DTM_INFO_REFINED) != 0)),
+        "continued_pixels": int(np.sum((info["flags"] & dtm.DTM_INFO_CONTINUED) != 0)),
         "max_residual_l1": float(info["residual_l1"].max()),
         "l1_vs_oracle_max": l1_report["max"],
         "l1_vs_oracle": l1_report,

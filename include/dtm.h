@@ -154,9 +154,9 @@ typedef struct dtm_solve_opts {
 #define DTM_INFO_CHECKED       0x4 /* residual_l1 comes from a float64 check sweep       */
 #define DTM_INFO_STALLED       0x8 /* changes stopped shrinking at the precision floor   */
 #define DTM_INFO_REFINED      0x10 /* float32 could not certify: re-solved in float64    */
-#define DTM_INFO_CONTINUED    0x20 /* banded pixel still running after the launched
-                                      sweeps: finished in float64 on the factored
-                                      product of the same matrix                   */
+#define DTM_INFO_CONTINUED    0x20 /* still running after the tile's dense_sweeps:
+                                      finished in float64 on the factored product
+                                      of the same matrix                           */
 typedef struct dtm_solve_info {
   int32_t iterations;  /* sweeps performed (each reads the matrix once)         */
   int32_t status;
@@ -266,15 +266,21 @@ typedef struct dtm_tile_config {
   int32_t fused_max_bins;  /* pixels with n_b above this take the banded path (>= 2)    */
   int32_t band_rows;       /* rows per workgroup in the banded sweep, multiple of 16,
                               at most 8192 (0 = 1024)                                  */
-  int32_t band_sweeps;     /* dense sweeps launched for banded pixels (<= max_iter;
-                              0 = min(max_iter, 64)); a banded pixel still running
-                              after them continues from its iterate in float64 with
-                              the factored product (see dtm_solve_factored_batched)
-                              up to max_iter sweeps in all (DTM_INFO_CONTINUED)       */
+  int32_t dense_sweeps;    /* sweeps of a pixel's dense matrix (<= max_iter; 0 =
+                              min(max_iter, 32)); a pixel still running after them
+                              continues from its iterate in float64 with the factored
+                              product of the same matrix (see
+                              dtm_solve_factored_batched) up to max_iter sweeps in all
+                              (DTM_INFO_CONTINUED).  The banded path launches this many
+                              sweeps whatever the pixels need                          */
   int32_t band_cpt;        /* column vectors per thread in the banded sweep: 1, 2 or 4
                               (0 = 1); a workgroup covers 256 x band_cpt x (4 float /
                               2 double) columns of its rows                            */
-  int32_t reserved[2];     /* must be 0                                                 */
+  int32_t independent_paths; /* plans with both kinds of pixels: 0 = every matrix is
+                              written before any is swept (the two paths wait for each
+                              other's builds), 1 = each path sweeps as soon as its own
+                              matrices are written                                     */
+  int32_t reserved;        /* must be 0                                                 */
 } dtm_tile_config;
 
 typedef struct dtm_plan dtm_plan; /* opaque host object */
@@ -311,8 +317,9 @@ int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes,
  * iteration with the plan's stop rule, float64 residual check.  Pixels up to
  * fused_max_bins take one workgroup each in two launches: every matrix is
  * written (with the first sweep taken on the way), then the remaining sweeps
- * read them; larger pixels take the banded launches (band_sweeps dense
- * sweeps, then the float64 continuation for those still running).  Writes pi
+ * read them; larger pixels take the banded launches.  A pixel still running
+ * after dense_sweeps sweeps goes on in float64 on the factored product of the
+ * same matrix (DTM_INFO_CONTINUED).  Writes pi
  * packed by pi_offsets (dtype of the plan) and one dtm_solve_info per pixel
  * to infos_dev (device memory, plan order = input order).  x0_packed_dev
  * (packed like pi, dtype of the plan) seeds the iteration; NULL = uniform.

@@ -33,16 +33,18 @@ def candidates(scenes):
     """The search space, pruned to shapes that differ for these scenes."""
     n_max = int(np.max(scenes["n_bins"]))
     out, seen = [], set()
-    for threads, unroll, fmax, band, cpt in itertools.product((256, 512), (4, 8), (1024, 2048, 4096),
-                                                              (256, 1024, 8192), (1, 4)):
+    # dense_sweeps: 0 = the default budget (32 sweeps), 12 = slowly mixing
+    # pixels finish on the float64 factored product after twelve dense sweeps
+    for threads, unroll, fmax, band, cpt, dense in itertools.product((256, 512), (4, 8), (1024, 2048, 4096),
+                                                                     (256, 1024, 8192), (1, 4), (0, 12)):
         eff_fmax = min(fmax, n_max)
         big = n_max > fmax
-        sig = (threads, unroll, eff_fmax, band if big else 0, cpt if big else 0)
+        sig = (threads, unroll, eff_fmax, band if big else 0, cpt if big else 0, dense)
         if sig in seen:
             continue
         seen.add(sig)
         out.append(dtm.tiles(fused_threads=threads, fused_unroll=unroll, fused_max_bins=fmax,
-                             band_rows=band, band_cpt=cpt))
+                             band_rows=band, band_cpt=cpt, dense_sweeps=dense))
     return out
 
 
@@ -88,7 +90,8 @@ def autotune(scenes, dtype, solve_opts=None, cache_path=DEFAULT_CACHE, reps=3, v
     if key in cache:
         c = cache[key]["tiles"]
         return dtm.tiles(**c), {"cached": True, **cache[key]}
-    cands = candidates(scenes)
+    max_iter = (solve_opts or dtm.opts()).max_iter
+    cands = [t for t in candidates(scenes) if t.dense_sweeps <= max_iter]
     need = 0
     for t in cands:
         p = dtm.Plan(scenes, dtype, solve_opts, t)

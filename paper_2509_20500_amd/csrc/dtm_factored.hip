@@ -167,8 +167,8 @@ __device__ StopState power(const PixelMeta& m, const Vecs& V, double c, const TI
   return st;
 }
 
-// Banded pixels of the dense solver that used all their launched sweeps
-// without stopping: the power iteration goes on from the pixel's current
+// Pixels of the dense solver that used their dense sweeps (the tile's
+// dense_sweeps) without stopping: the power iteration goes on from the pixel's current
 // iterate with the factored product of the same matrix, every sweep in
 // float64, until the stop rule ends it or max_iter sweeps since the start
 // (or the warm start's restart) have been taken.  Pixels that stopped
@@ -176,14 +176,14 @@ __device__ StopState power(const PixelMeta& m, const Vecs& V, double c, const TI
 // the continued iterate.  Writes pi and the pixel's report, flagged
 // DTM_INFO_CONTINUED.
 template <typename T>
-__global__ __launch_bounds__(BT) void k_band_tail(const PixelMeta* __restrict__ metas,
-                                                  const int32_t* __restrict__ big,
+__global__ __launch_bounds__(BT) void k_dense_tail(const PixelMeta* __restrict__ metas,
+                                                  const int32_t* __restrict__ sel,
                                                   double* __restrict__ fact, int64_t vec_elems,
                                                   const T* __restrict__ xbuf, SolveState* __restrict__ states,
                                                   T* __restrict__ pi_packed, dtm_solve_info* __restrict__ infos,
                                                   KOpts o) {
   __shared__ double red[3 * BT / kWave];
-  const int q = big[blockIdx.x];
+  const int q = sel[blockIdx.x];
   const PixelMeta m = metas[q];
   const StopState prev = states[q].s;
   if (prev.done) return;
@@ -1052,21 +1052,21 @@ using namespace dtm;
 
 namespace dtm {
 
-int launch_band_tail(const dtm_plan* plan, void* pi, dtm_solve_info* infos, void* stream) {
-  const int nbig = static_cast<int>(plan->big_sel.size());
-  if (nbig == 0) return DTM_OK;
+int launch_dense_tail(const dtm_plan* plan, int banded, void* pi, dtm_solve_info* infos, void* stream) {
+  const int count = static_cast<int>(banded ? plan->big_sel.size() : plan->small_sel.size());
+  if (count == 0) return DTM_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(plan->ws);
   const PixelMeta* metas = reinterpret_cast<const PixelMeta*>(w + plan->off_meta);
-  const int32_t* big = reinterpret_cast<const int32_t*>(w + plan->off_big);
+  const int32_t* sel = reinterpret_cast<const int32_t*>(w + (banded ? plan->off_big : plan->off_small));
   double* fact = reinterpret_cast<double*>(w + plan->off_fact);
   SolveState* states = reinterpret_cast<SolveState*>(w + plan->off_state);
   if (plan->dt == DTM_F32)
-    hipLaunchKernelGGL((fact::k_band_tail<float>), dim3(nbig), dim3(fact::BT), 0, st, metas, big, fact,
+    hipLaunchKernelGGL((fact::k_dense_tail<float>), dim3(count), dim3(fact::BT), 0, st, metas, sel, fact,
                        plan->vec_elems, reinterpret_cast<const float*>(w + plan->off_xbuf), states,
                        static_cast<float*>(pi), infos, plan->kopts);
   else
-    hipLaunchKernelGGL((fact::k_band_tail<double>), dim3(nbig), dim3(fact::BT), 0, st, metas, big, fact,
+    hipLaunchKernelGGL((fact::k_dense_tail<double>), dim3(count), dim3(fact::BT), 0, st, metas, sel, fact,
                        plan->vec_elems, reinterpret_cast<const double*>(w + plan->off_xbuf), states,
                        static_cast<double*>(pi), infos, plan->kopts);
   return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP;

@@ -246,13 +246,14 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   if (tc.fused_unroll == 0) tc.fused_unroll = 8;
   if (tc.fused_max_bins == 0) tc.fused_max_bins = 2048;
   if (tc.band_rows == 0) tc.band_rows = 1024;
-  if (tc.band_sweeps == 0) tc.band_sweeps = std::min(ko.max_iter, 64);
+  if (tc.dense_sweeps == 0) tc.dense_sweeps = std::min(ko.max_iter, 32);
   if (tc.band_cpt == 0) tc.band_cpt = 1;
   if ((tc.fused_threads != 256 && tc.fused_threads != 512) ||
       (tc.fused_unroll != 2 && tc.fused_unroll != 4 && tc.fused_unroll != 8) ||
       tc.fused_max_bins < 2 || tc.band_rows < 16 || tc.band_rows % 16 != 0 || tc.band_rows > 8192 ||
-      tc.band_sweeps < 1 || tc.band_sweeps > ko.max_iter ||
-      (tc.band_cpt != 1 && tc.band_cpt != 2 && tc.band_cpt != 4) || tc.reserved[0] || tc.reserved[1]) {
+      tc.dense_sweeps < 1 || tc.dense_sweeps > ko.max_iter ||
+      (tc.band_cpt != 1 && tc.band_cpt != 2 && tc.band_cpt != 4) ||
+      (tc.independent_paths != 0 && tc.independent_paths != 1) || tc.reserved) {
     delete plan;
     return DTM_EINVAL;
   }
@@ -360,6 +361,9 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
       const int32_t cblocks = (m.n + colw - 1) / colw;
       for (int32_t b = 0; b < m.bands; ++b)
         for (int32_t cb = 0; cb < cblocks; ++cb) plan->items.push_back(BandItem{q, b, cb, 0});
+      // the combine's column blocks (stage 1) and where the pixel's start
+      plan->cbase.push_back(static_cast<int32_t>(plan->citems.size()));
+      for (int32_t cb = 0; cb < cblocks; ++cb) plan->citems.push_back(BandItem{q, 0, cb, 0});
     }
   }
   plan->part_elems = acc_part;
@@ -385,6 +389,14 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   off = align_up(off + sizeof(int32_t) * (plan->big_sel.size() + 1), 256);
   plan->off_items = off;
   off = align_up(off + sizeof(BandItem) * (plan->items.size() + 1), 256);
+  plan->off_citems = off;
+  off = align_up(off + sizeof(BandItem) * (plan->citems.size() + 1), 256);
+  plan->off_cbase = off;
+  off = align_up(off + sizeof(int32_t) * (plan->cbase.size() + 1), 256);
+  plan->off_bsum = off;
+  off = align_up(off + 16 * (plan->citems.size() + 1), 256);
+  plan->off_ybuf = off;
+  off = align_up(off + 8 * acc_vec, 256);
   plan->off_xbuf = off;
   off = align_up(off + es * acc_vec, 256);
   plan->off_dprev = off;

@@ -97,9 +97,10 @@ int shift_bins(const dtm_scene& s, int32_t* l);
 void model_shift(const dtm_scene& s, int32_t model, int32_t* l, double* frac);
 int32_t model_lam_mode(int32_t model);
 int fill_opts(const dtm_solve_opts* opt, KOpts* k, int32_t* check_every);
-// Float64 continuation of the banded pixels of a bound plan whose launched
-// sweeps ran out (dtm_factored.hip; launch only, on the hipStream_t stream).
-int launch_band_tail(const dtm_plan* plan, void* pi, dtm_solve_info* infos, void* stream);
+// Float64 continuation of the pixels of a bound plan still running after
+// their dense sweeps: the one-block pixels (banded = 0) or the banded ones
+// (banded = 1) (dtm_factored.hip; launch only, on the hipStream_t stream).
+int launch_dense_tail(const dtm_plan* plan, int banded, void* pi, dtm_solve_info* infos, void* stream);
 constexpr int32_t padded_ld(int32_t n, dtm_dtype dt) {
   const int32_t vec = dt == DTM_F32 ? 4 : 2;  // 16 bytes
   return (n + vec - 1) / vec * vec;
@@ -160,12 +161,17 @@ struct dtm_plan {
   // pixels of the fused one-block kernel and of the banded multi-block path
   std::vector<int32_t> small_sel, big_sel;
   std::vector<dtm::BandItem> items;
+  // banded combine, stage 1: one item per column block of each banded pixel
+  // (band 0), and each banded pixel's first column block in that list
+  std::vector<dtm::BandItem> citems;
+  std::vector<int32_t> cbase;
   int32_t max_n_small, max_ld_small, max_n_big, max_ld_big;
   int32_t band_threads, band_cpt;  // banded sweep block size and column chunks per thread
   int64_t part_elems;              // doubles of band partial sums
   // workspace layout, byte offsets
   size_t off_meta, off_pool, off_colf, off_invs, off_scal, off_state, total_bytes;
   size_t off_small, off_big, off_items, off_xbuf, off_dprev, off_part, off_fact;
+  size_t off_citems, off_cbase, off_bsum, off_ybuf;
   void* ws;            // bound workspace (device), or nullptr
   size_t ws_bytes;
   // created at bind: a second stream (default priority) and two events that

@@ -367,7 +367,9 @@ __global__ __launch_bounds__(BT) void k_solve_sweeps(const PixelMeta* __restrict
                                                      T* __restrict__ pi_packed,
                                                      dtm_solve_info* __restrict__ infos,
                                                      const int32_t* __restrict__ sel,
-                                                     KOpts o, int lds_ld) {
+                                                     KOpts o, int lds_ld, int dense_cap,
+                                                     T* __restrict__ xbuf,
+                                                     SolveState* __restrict__ states) {
   constexpr int VN = Vec<T>::n;
   constexpr int UE = (U * CPT <= 8) ? U : (8 / CPT > 0 ? 8 / CPT : 1);
   extern __shared__ __align__(16) unsigned char smem[];
@@ -460,6 +462,19 @@ __global__ __launch_bounds__(BT) void k_solve_sweeps(const PixelMeta* __restrict
     }
     __syncthreads();
     if (st.done) break;
+    if (st.total_iter >= dense_cap) {
+      // out of dense sweeps: the iterate and the stop state go to the
+      // float64 continuation on the factored product
+      for (int j = tid; j < n; j += BT) xbuf[m.vec_off + j] = xs[j];
+      if (tid == 0) {
+        SolveState out;
+        out.s = st;
+        out.sum_y = 0.0;
+        out.pad = 0.0;
+        states[pq] = out;
+      }
+      return;
+    }
 
     // ---- a4: next sweep (a5: float64 check sweep when due) --------------
     have_check = st.check_next != 0;
@@ -480,7 +495,10 @@ __global__ __launch_bounds__(BT) void k_solve_sweeps(const PixelMeta* __restrict
 
   // ---- outputs --------------------------------------------------------------
   for (int j = tid; j < n; j += BT) pi_packed[m.pi_off + j] = xs[j];
-  if (tid == 0) infos[m.index] = make_info(st);
+  if (tid == 0) {
+    infos[m.index] = make_info(st);
+    states[pq].s.done = 1;  // nothing for the continuation
+  }
 }
 
 // ============================================================================
@@ -673,14 +691,61 @@ __device__ inline void band_sums(const double* __restrict__ p, int64_t ld, int b
     for (int u = 0; u < U; ++u) y[u] += p[static_cast<int64_t>(b) * ld + jc[u]];
 }
 
+// The combine of a banded sweep in two launches, so that it is spread over
+// the chip rather than one block per pixel (a pixel of 8192 bins has 8 x
+// 8192 partial sums).  Stage 1, one block per column block of a banded
+// pixel: y_j = the band partial sums of column j added in band order (eight
+// loads in flight), stored in ybuf, and the block's sums of y and |y - x|.
 template <typename T, int BT>
-__global__ __launch_bounds__(BT) void k_band_combine(const PixelMeta* __restrict__ metas,
-                                                     const int32_t* __restrict__ big,
-                                                     const double* __restrict__ part,
-                                                     T* __restrict__ xbuf, double* __restrict__ dprev,
-                                                     SolveState* __restrict__ states,
-                                                     T* __restrict__ pi_packed,
-                                                     dtm_solve_info* __restrict__ infos, KOpts o) {
+__global__ __launch_bounds__(BT) void k_band_colsum(const PixelMeta* __restrict__ metas,
+                                                    const BandItem* __restrict__ citems,
+                                                    const double* __restrict__ part,
+                                                    const T* __restrict__ xbuf,
+                                                    const SolveState* __restrict__ states,
+                                                    double* __restrict__ ybuf, double* __restrict__ bsum,
+                                                    int colw) {
+  __shared__ double red[3 * BT / kWave];
+  const BandItem it = citems[blockIdx.x];
+  const PixelMeta m = metas[it.meta];
+  if (states[it.meta].s.done) return;  // the same for every block of the pixel
+  const double* pp = part + m.part_off;
+  const T* x = xbuf + m.vec_off;
+  double* y = ybuf + m.vec_off;
+  const int c0 = it.colblock * colw, c1 = min(c0 + colw, m.n);
+  constexpr int UC = 4;
+  double sy = 0.0, rs = 0.0;
+  for (int j0 = c0 + static_cast<int>(threadIdx.x); j0 < c1; j0 += UC * BT) {
+    double yv[UC];
+    band_sums<UC, BT>(pp, m.ld, m.bands, j0, c1, yv);
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int j = j0 + BT * u;
+      if (j < c1) {
+        y[j] = yv[u];
+        sy += yv[u];
+        rs += fabs(yv[u] - static_cast<double>(x[j]));
+      }
+    }
+  }
+  block_sum2<BT>(sy, rs, red);
+  if (threadIdx.x == 0) {
+    bsum[2 * blockIdx.x] = sy;
+    bsum[2 * blockIdx.x + 1] = rs;
+  }
+}
+
+// Stage 2, one block per banded pixel: sum y and the residual from the
+// column blocks' sums (in column-block order), then the new iterate
+// y / sum y, its change, and the stop rule.
+template <typename T, int BT>
+__global__ __launch_bounds__(BT) void k_band_finish(const PixelMeta* __restrict__ metas,
+                                                    const int32_t* __restrict__ big,
+                                                    const int32_t* __restrict__ cbase,
+                                                    const double* __restrict__ ybuf,
+                                                    const double* __restrict__ bsum, T* __restrict__ xbuf,
+                                                    double* __restrict__ dprev, SolveState* __restrict__ states,
+                                                    T* __restrict__ pi_packed, dtm_solve_info* __restrict__ infos,
+                                                    KOpts o, int colw) {
   __shared__ double red[3 * BT / kWave];
   const int q = big[blockIdx.x];
   const PixelMeta m = metas[q];
@@ -688,42 +753,40 @@ __global__ __launch_bounds__(BT) void k_band_combine(const PixelMeta* __restrict
   if (s.done) return;
   const bool was_check = s.check_next != 0;
   const int n = m.n;
-  const double* pp = part + m.part_off;
+  const int nb = (n + colw - 1) / colw;
+  const double* bs = bsum + 2 * static_cast<int64_t>(cbase[m.big]);
+  double sy = 0.0, rs = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    sy += bs[2 * b];
+    rs += bs[2 * b + 1];
+  }
+  const double inv = 1.0 / sy;
+  const double* y = ybuf + m.vec_off;
   T* x = xbuf + m.vec_off;
   double* dp = dprev + m.vec_off;
-  // Columns j = tid, tid + BT, ... in that order (four at a time, so that
-  // their band loads are in flight together).
+  // columns j = tid, tid + BT, ... in that order, four loaded at a time
   constexpr int UC = 4;
-  double sy = 0.0, rs = 0.0;
-  for (int j0 = threadIdx.x; j0 < n; j0 += UC * BT) {
-    double y[UC];
-    band_sums<UC, BT>(pp, m.ld, m.bands, j0, n, y);
-#pragma unroll
-    for (int u = 0; u < UC; ++u) {
-      const int j = j0 + BT * u;
-      if (j < n) {
-        sy += y[u];
-        rs += fabs(y[u] - static_cast<double>(x[j]));
-      }
-    }
-  }
-  block_sum2<BT>(sy, rs, red);
-  const double inv = 1.0 / sy;
   double ch = 0.0, dd = 0.0, ddp = 0.0;
   for (int j0 = threadIdx.x; j0 < n; j0 += UC * BT) {
-    double y[UC];
-    band_sums<UC, BT>(pp, m.ld, m.bands, j0, n, y);
+    double yv[UC], xv[UC], pv[UC];
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int j = min(j0 + BT * u, n - 1);
+      yv[u] = y[j];
+      xv[u] = static_cast<double>(x[j]);
+      pv[u] = dp[j];
+    }
 #pragma unroll
     for (int u = 0; u < UC; ++u) {
       const int j = j0 + BT * u;
       if (j < n) {
-        const T xn = static_cast<T>(y[u] * inv);
-        const double dj = static_cast<double>(xn) - static_cast<double>(x[j]);
+        const T xn = static_cast<T>(yv[u] * inv);
+        const double dj = static_cast<double>(xn) - xv[u];
         ch += fabs(dj);
         dd += dj * dj;
-        ddp += dj * dp[j];
+        ddp += dj * pv[u];
         dp[j] = dj;
-        x[j] = xn;  // thread-private index: read above by this thread only
+        x[j] = xn;  // each thread owns its j: no other thread reads it in this launch
       }
     }
   }
@@ -1216,7 +1279,7 @@ int launch_fused_cpt(const dtm_plan* plan, int phase, int unroll, const PixelMet
   const size_t lds_sweeps = sizeof(T) * static_cast<size_t>(lds_ld) + red;
   auto build = k_solve_build<T, BT, CPT>;
   void (*sweeps)(const PixelMeta*, const T*, const T*, const double*, T*, dtm_solve_info*, const int32_t*,
-                 KOpts, int) = nullptr;
+                 KOpts, int, int, T*, SolveState*) = nullptr;
   switch (unroll) {
     case 2: sweeps = k_solve_sweeps<T, BT, CPT, 2>; break;
     case 4: sweeps = k_solve_sweeps<T, BT, CPT, 4>; break;
@@ -1241,7 +1304,9 @@ int launch_fused_cpt(const dtm_plan* plan, int phase, int unroll, const PixelMet
                        lds_ld, plan->kopts.start_flux);
   else
     hipLaunchKernelGGL(sweeps, dim3(count), dim3(BT), lds_sweeps, st, metas, pool, x0, y1, pi, infos, sel,
-                       plan->kopts, lds_ld);
+                       plan->kopts, lds_ld,
+                       plan->tiles.dense_sweeps < plan->kopts.max_iter ? plan->tiles.dense_sweeps : INT32_MAX,
+                       reinterpret_cast<T*>(w + plan->off_xbuf), reinterpret_cast<SolveState*>(w + plan->off_state));
   return last_launch();
 }
 
@@ -1287,7 +1352,7 @@ int launch_refine(const dtm_plan* plan, const PixelMeta* metas, T* pi, dtm_solve
 
 // Banded path: k_band_init (launched by the caller before the one-block
 // solver is forked off, so that it does not queue behind that solver's
-// long-running blocks), then band_sweeps x (sweep over all items, combine).
+// long-running blocks), then dense_sweeps x (sweep over all items, combine).
 template <typename T>
 int launch_band_init(const dtm_plan* plan, const PixelMeta* metas, const T* x0, hipStream_t st) {
   constexpr int BT = 256;
@@ -1316,6 +1381,12 @@ int launch_banded(const dtm_plan* plan, int t0, int t1, const PixelMeta* metas, 
   SolveState* states = reinterpret_cast<SolveState*>(w + plan->off_state);
   const int nbig = static_cast<int>(plan->big_sel.size());
   const int nitems = static_cast<int>(plan->items.size());
+  const BandItem* citems = reinterpret_cast<const BandItem*>(w + plan->off_citems);
+  const int32_t* cbase = reinterpret_cast<const int32_t*>(w + plan->off_cbase);
+  double* bsum = reinterpret_cast<double*>(w + plan->off_bsum);
+  double* ybuf = reinterpret_cast<double*>(w + plan->off_ybuf);
+  const int ncitems = static_cast<int>(plan->citems.size());
+  const int colw = plan->band_threads * Vec<T>::n * plan->band_cpt;
   const size_t lds = sizeof(T) * static_cast<size_t>(plan->tiles.band_rows);
   int rc = DTM_OK;
   void (*sweep)(const PixelMeta*, const BandItem*, const T*, const double*, const T*, T*, const T*,
@@ -1328,8 +1399,10 @@ int launch_banded(const dtm_plan* plan, int t0, int t1, const PixelMeta* metas, 
   for (int t = t0; t < t1; ++t) {
     hipLaunchKernelGGL(sweep, dim3(nitems), dim3(BT), lds, st, metas, items, colf, scal, invs, pool,
                        xbuf, states, part, plan->tiles.band_rows, t == 0 ? 1 : 0);
-    hipLaunchKernelGGL((k_band_combine<T, BT>), dim3(nbig), dim3(BT), 0, st, metas, big, part, xbuf,
-                       dprev, states, pi, infos, plan->kopts);
+    hipLaunchKernelGGL((k_band_colsum<T, BT>), dim3(ncitems), dim3(BT), 0, st, metas, citems, part, xbuf,
+                       states, ybuf, bsum, colw);
+    hipLaunchKernelGGL((k_band_finish<T, BT>), dim3(nbig), dim3(BT), 0, st, metas, big, cbase, ybuf, bsum, xbuf,
+                       dprev, states, pi, infos, plan->kopts, colw);
     rc = last_launch();
     if (rc) return rc;
   }
@@ -1400,11 +1473,11 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
     if (rc) return rc;
   }
   if (nbig > 0) {
-    rc = launch_banded<T>(plan, 0, std::min(1, plan->tiles.band_sweeps), metas, colf, scal, invs, pool, pit, infos,
+    rc = launch_banded<T>(plan, 0, std::min(1, plan->tiles.dense_sweeps), metas, colf, scal, invs, pool, pit, infos,
                           st);
     if (rc) return rc;
   }
-  if (fork) {
+  if (fork && !plan->tiles.independent_paths) {
     hipEvent_t small_built = static_cast<hipEvent_t>(plan->ev_join);
     hipEvent_t big_built = static_cast<hipEvent_t>(plan->ev_fork);
     if (hipEventRecord(small_built, fst) != hipSuccess || hipEventRecord(big_built, st) != hipSuccess ||
@@ -1414,12 +1487,17 @@ int batched_solve(const dtm_plan* plan, const void* x0, void* pi, dtm_solve_info
   if (nsmall > 0) {
     rc = one_block(1);
     if (rc) return rc;
+    // one-block pixels still running after dense_sweeps go on in float64
+    if (plan->tiles.dense_sweeps < plan->kopts.max_iter) {
+      rc = launch_dense_tail(plan, 0, pit, infos, fst);
+      if (rc) return rc;
+    }
   }
   if (nbig > 0) {
-    rc = launch_banded<T>(plan, 1, plan->tiles.band_sweeps, metas, colf, scal, invs, pool, pit, infos, st);
+    rc = launch_banded<T>(plan, 1, plan->tiles.dense_sweeps, metas, colf, scal, invs, pool, pit, infos, st);
     if (rc) return rc;
     // pixels still running after the launched sweeps go on in float64
-    rc = launch_band_tail(plan, pit, infos, st);
+    rc = launch_dense_tail(plan, 1, pit, infos, st);
     if (rc) return rc;
   }
   if (fork) {
@@ -1626,6 +1704,12 @@ int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes, d
   if (!plan->items.empty() &&
       hipMemcpyAsync(w + plan->off_items, plan->items.data(), sizeof(BandItem) * plan->items.size(),
                      hipMemcpyHostToDevice, st) != hipSuccess)
+    return DTM_EHIP;
+  if (!plan->citems.empty() &&
+      (hipMemcpyAsync(w + plan->off_citems, plan->citems.data(), sizeof(BandItem) * plan->citems.size(),
+                      hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemcpyAsync(w + plan->off_cbase, plan->cbase.data(), sizeof(int32_t) * plan->cbase.size(),
+                      hipMemcpyHostToDevice, st) != hipSuccess))
     return DTM_EHIP;
   if (hipStreamSynchronize(st) != hipSuccess) return DTM_EHIP;
   if (!plan->aux_stream) {

@@ -215,13 +215,16 @@ def test_tile_config_defaults_and_limits(d):
     assert (t.band_rows, t.band_cpt) == (1024, 1)
     plan.close()
     for bad in (d.tiles(band_cpt=3), d.tiles(band_cpt=8), d.tiles(band_rows=8208), d.tiles(band_rows=24),
-                d.tiles(fused_unroll=16)):
+                d.tiles(fused_unroll=16), d.tiles(independent_paths=2)):
         with pytest.raises(d.DtmError):
             d.Plan(scenes, "f32", tiles=bad)
     t = d.tiles(band_rows=512, band_cpt=2)
-    t.reserved[1] = 1
+    t.reserved = 1
     with pytest.raises(d.DtmError):
         d.Plan(scenes, "f32", tiles=t)
+    plan = d.Plan(scenes, "f32", tiles=d.tiles(independent_paths=1))
+    assert plan.tiles.independent_paths == 1
+    plan.close()
 
 
 def test_model_shift_matches_oracle_variants(d):

@@ -1,10 +1,11 @@
-"""Banded pixels whose launched sweeps run out go on in float64 with the
-factored product of the same matrix, instead of ending unconverged.
+"""Pixels still running after their dense sweeps (the tile's dense_sweeps)
+go on in float64 with the factored product of the same matrix, instead of
+ending unconverged: banded pixels and one-block pixels alike.
 
 * The corners of the paper's Section 4 grid where the spectral gap is
   smallest (S = B = 10 and S = B = 9 at t_d = 75 and 95 ns; |lambda_2| up to
   about 0.87, a hundred sweeps and more to 1e-6) at N = 4096 and 8192, in a
-  default float32 plan (banded path above 2048 bins, 64 launched sweeps),
+  default float32 plan (banded path above 2048 bins, 32 dense sweeps),
   eager and replayed as a HIP graph: every pixel ends DTM_OK within 1e-6 in
   L1 of the float64 reference (the dense oracle at 4096 bins; at 8192 bins
   power iteration with the O(n) factorised product, pinned against the
@@ -12,6 +13,9 @@ factored product of the same matrix, instead of ending unconverged.
 * The banded pixels of the uneven batch with only three launched sweeps,
   so that most finish in the continuation: all DTM_OK and within 1e-6 of
   the float64 reference.
+* One-block pixels (the headline batch's N = 1024, and a plan mixing both
+  paths, eager and graph-replayed) with three dense sweeps: every pixel
+  DTM_OK within 1e-6 of the oracle, the continued ones flagged.
 * max_iter reached inside the continuation ends DTM_ENOTCONV with the last
   iterate (a probability vector) as pi.
 """
@@ -84,8 +88,8 @@ def test_slow_banded_pixels_continue_to_the_tolerance(slow_refs, graph):
     got, info = _solve(scenes, o, graph=graph)
     assert np.all(info["status"] == 0), info
     cont = (info["flags"] & d.DTM_INFO_CONTINUED) != 0
-    assert np.any(cont), info["iterations"]  # some need more than the 64 launched sweeps
-    assert np.all(info["iterations"][cont] > 64)
+    assert np.any(cont), info["iterations"]  # some need more than the 32 dense sweeps
+    assert np.all(info["iterations"][cont] > 32)
     l1 = np.array([np.abs(g - r).sum() for g, r in zip(got, refs)])
     print(f"graph={graph}: sweeps {info['iterations'].tolist()}, continued {int(cont.sum())}, "
           f"max L1 {l1.max():.3e}", flush=True)
@@ -96,7 +100,7 @@ def test_uneven_banded_pixels_with_three_launched_sweeps():
     d = lib()
     scenes = sc.batched_uneven()
     scenes = scenes[scenes["n_bins"] > 2048]
-    got, info = _solve(scenes, d.opts(tol=1e-6), tiles=d.tiles(band_sweeps=3))
+    got, info = _solve(scenes, d.opts(tol=1e-6), tiles=d.tiles(dense_sweeps=3))
     assert np.all(info["status"] == 0), info[info["status"] != 0]
     cont = (info["flags"] & d.DTM_INFO_CONTINUED) != 0
     assert cont.mean() > 0.5  # the others stop within the three launched sweeps
@@ -112,8 +116,42 @@ def test_uneven_banded_pixels_with_three_launched_sweeps():
 def test_max_iter_inside_the_continuation():
     d = lib()
     scenes = sc.scene(dead_time=75.0, center=30.0, sigma=0.5, signal=10.0, background=10.0, n_bins=4096)
-    got, info = _solve(scenes, d.opts(tol=1e-6, max_iter=12), tiles=d.tiles(band_sweeps=4))
+    got, info = _solve(scenes, d.opts(tol=1e-6, max_iter=12), tiles=d.tiles(dense_sweeps=4))
     assert info["status"][0] == d.DTM_ENOTCONV
     assert info["flags"][0] & d.DTM_INFO_CONTINUED
     assert info["iterations"][0] == 12
     assert np.all(got[0] >= 0) and abs(got[0].sum() - 1.0) < 1e-5
+
+
+def test_one_block_pixels_with_three_dense_sweeps():
+    d = lib()
+    scenes = sc.batched_uniform(256, seed=141)
+    got, info = _solve(scenes, d.opts(tol=1e-6), tiles=d.tiles(dense_sweeps=3))
+    assert np.all(info["status"] == 0), info[info["status"] != 0]
+    cont = (info["flags"] & d.DTM_INFO_CONTINUED) != 0
+    assert cont.mean() > 0.5 and np.all(info["iterations"][cont] > 3)
+    l1 = opool.l1_many(scenes, got)
+    print(f"one-block: {int(cont.sum())} of {scenes.size} continued, max L1 {l1.max():.3e}", flush=True)
+    assert l1.max() <= TOL_F32
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_both_paths_continue_in_one_plan(graph):
+    d = lib()
+    scenes = sc.batched_uneven(64, seed=142)
+    o = d.opts(tol=1e-6)
+    o.flags |= d.DTM_FLAG_START_FLUX
+    got, info = _solve(scenes, o, tiles=d.tiles(dense_sweeps=3, fused_max_bins=1024), graph=graph)
+    assert np.all(info["status"] == 0), info[info["status"] != 0]
+    cont = (info["flags"] & d.DTM_INFO_CONTINUED) != 0
+    n = scenes["n_bins"]
+    assert np.any(cont & (n <= 1024)) and np.any(cont & (n > 1024))
+    small = np.flatnonzero(n <= 2048)
+    l1 = opool.l1_many(scenes[small], [got[p] for p in small])
+    worst = float(l1.max())
+    for p in np.flatnonzero(n > 2048):
+        ref, ok = factored_power(scenes[p])
+        assert ok
+        worst = max(worst, float(np.abs(got[p] - ref).sum()))
+    print(f"graph={graph}: {int(cont.sum())} of {scenes.size} continued, max L1 {worst:.3e}", flush=True)
+    assert worst <= TOL_F32
