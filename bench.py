@@ -896,6 +896,8 @@ def main():
     ap.add_argument("--band-cpt", type=int, default=0, help="column vectors per thread, banded (0 = default)")
     ap.add_argument("--independent-paths", type=int, default=0, choices=[0, 1],
                     help="1: one-block and banded pixels sweep without waiting for each other's builds")
+    ap.add_argument("--fused-blocks", type=int, default=0,
+                    help="persistent workgroups of the one-block sweeps (0 = one per pixel)")
     ap.add_argument("--dense-sweeps", type=int, default=0,
                     help="sweeps of a pixel's dense matrix before the float64 continuation (0 = default)")
     ap.add_argument("--variant", default="paper",
@@ -934,9 +936,9 @@ def main():
     sopts = dtm.opts(tol=1e-6)
     tune_report = None
     if (args.threads or args.unroll or args.band_rows or args.band_cpt or args.fused_max_bins or args.dense_sweeps
-            or args.independent_paths):
+            or args.independent_paths or args.fused_blocks):
         tiles = dtm.tiles(args.threads, args.unroll, args.fused_max_bins, args.band_rows, args.dense_sweeps,
-                          args.band_cpt, args.independent_paths)
+                          args.band_cpt, args.independent_paths, args.fused_blocks)
     elif args.autotune:
         from paper_2509_20500_amd.autotune import autotune
         tiles, tune_report = autotune(scenes, args.dtype, sopts)

@@ -280,7 +280,10 @@ typedef struct dtm_tile_config {
                               written before any is swept (the two paths wait for each
                               other's builds), 1 = each path sweeps as soon as its own
                               matrices are written                                     */
-  int32_t reserved;        /* must be 0                                                 */
+  int32_t fused_blocks;    /* one-block sweeps: 0 = one workgroup per pixel; k > 0 = k
+                              persistent workgroups, each taking the next pixel in
+                              launch order from a counter (so the banded launches of
+                              a mixed plan keep the CUs the k workgroups leave)         */
 } dtm_tile_config;
 
 typedef struct dtm_plan dtm_plan; /* opaque host object */

@@ -34,17 +34,22 @@ def candidates(scenes):
     n_max = int(np.max(scenes["n_bins"]))
     out, seen = [], set()
     # dense_sweeps: 0 = the default budget (32 sweeps), 12 = slowly mixing
-    # pixels finish on the float64 factored product after twelve dense sweeps
-    for threads, unroll, fmax, band, cpt, dense in itertools.product((256, 512), (4, 8), (1024, 2048, 4096),
-                                                                     (256, 1024, 8192), (1, 4), (0, 12)):
+    # pixels finish on the float64 factored product after twelve dense sweeps;
+    # fused_blocks: 0 = one workgroup per one-block pixel, 128 = persistent
+    # workgroups (only differs when banded pixels share the plan)
+    n_min = int(np.min(scenes["n_bins"]))
+    for threads, unroll, fmax, band, cpt, dense, blocks in itertools.product(
+            (256, 512), (4, 8), (1024, 2048, 4096), (1024, 8192), (1, 4), (0, 12), (0, 128)):
         eff_fmax = min(fmax, n_max)
         big = n_max > fmax
-        sig = (threads, unroll, eff_fmax, band if big else 0, cpt if big else 0, dense)
+        mixed = big and n_min <= fmax
+        sig = (threads, unroll, eff_fmax, band if big else 0, cpt if big else 0, dense, blocks if mixed else 0)
         if sig in seen:
             continue
         seen.add(sig)
         out.append(dtm.tiles(fused_threads=threads, fused_unroll=unroll, fused_max_bins=fmax,
-                             band_rows=band, band_cpt=cpt, dense_sweeps=dense))
+                             band_rows=band, band_cpt=cpt, dense_sweeps=dense,
+                             fused_blocks=blocks if mixed else 0))
     return out
 
 

@@ -294,9 +294,12 @@ __global__ __launch_bounds__(BT) void k_solve_build(const PixelMeta* __restrict_
                                                     const T* __restrict__ x0_packed,
                                                     double* __restrict__ y1,
                                                     const int32_t* __restrict__ sel, int lds_ld,
-                                                    int start_flux) {
+                                                    int start_flux, int* __restrict__ queue) {
   using V = typename Vec<T>::type;
   constexpr int VN = Vec<T>::n;
+  // the persistent sweep launch that follows on this stream takes pixels
+  // from this counter
+  if (queue && blockIdx.x == 0 && threadIdx.x == 0) *queue = 0;
   extern __shared__ __align__(16) unsigned char smem[];
   T* g = reinterpret_cast<T*>(smem);
   T* xs = g + lds_ld;
@@ -369,14 +372,17 @@ __global__ __launch_bounds__(BT) void k_solve_sweeps(const PixelMeta* __restrict
                                                      const int32_t* __restrict__ sel,
                                                      KOpts o, int lds_ld, int dense_cap,
                                                      T* __restrict__ xbuf,
-                                                     SolveState* __restrict__ states) {
+                                                     SolveState* __restrict__ states,
+                                                     int* __restrict__ queue, int count) {
   constexpr int VN = Vec<T>::n;
   constexpr int UE = (U * CPT <= 8) ? U : (8 / CPT > 0 ? 8 / CPT : 1);
   extern __shared__ __align__(16) unsigned char smem[];
   T* xs = reinterpret_cast<T*>(smem);
   double* red = reinterpret_cast<double*>(xs + lds_ld);
+  __shared__ int next_pixel;
 
-  const int pq = sel[blockIdx.x];
+  // one pixel from its first-sweep sums to its stop (or its dense budget)
+  const auto solve = [&](const int pq) {
   const PixelMeta m = metas[pq];
   const int n = m.n;
   const int64_t ld = m.ld;
@@ -498,6 +504,22 @@ __global__ __launch_bounds__(BT) void k_solve_sweeps(const PixelMeta* __restrict
   if (tid == 0) {
     infos[m.index] = make_info(st);
     states[pq].s.done = 1;  // nothing for the continuation
+  }
+  };
+
+  if (!queue) {  // one workgroup per pixel
+    solve(sel[blockIdx.x]);
+    return;
+  }
+  // persistent workgroups: each takes the next pixel in launch order until
+  // the queue is past the last one (every workgroup reaches that exit)
+  for (;;) {
+    __syncthreads();  // the previous pixel's reads of LDS and of next_pixel are done
+    if (threadIdx.x == 0) next_pixel = atomicAdd(queue, 1);
+    __syncthreads();
+    const int idx = next_pixel;
+    if (idx >= count) break;
+    solve(sel[idx]);
   }
 }
 
@@ -1279,7 +1301,7 @@ int launch_fused_cpt(const dtm_plan* plan, int phase, int unroll, const PixelMet
   const size_t lds_sweeps = sizeof(T) * static_cast<size_t>(lds_ld) + red;
   auto build = k_solve_build<T, BT, CPT>;
   void (*sweeps)(const PixelMeta*, const T*, const T*, const double*, T*, dtm_solve_info*, const int32_t*,
-                 KOpts, int, int, T*, SolveState*) = nullptr;
+                 KOpts, int, int, T*, SolveState*, int*, int) = nullptr;
   switch (unroll) {
     case 2: sweeps = k_solve_sweeps<T, BT, CPT, 2>; break;
     case 4: sweeps = k_solve_sweeps<T, BT, CPT, 4>; break;
@@ -1299,14 +1321,19 @@ int launch_fused_cpt(const dtm_plan* plan, int phase, int unroll, const PixelMet
   // previous differences (disjoint pixels) and the tables kernel as scratch
   // (finished before this launch)
   double* y1 = reinterpret_cast<double*>(w + plan->off_dprev);
+  // persistent sweep workgroups (tile fused_blocks > 0) take pixels from a
+  // counter that the build launch resets
+  const int persistent = plan->tiles.fused_blocks > 0 && plan->tiles.fused_blocks < count;
+  int* queue = persistent ? reinterpret_cast<int*>(w + plan->off_queue) : nullptr;
   if (phase == 0)
     hipLaunchKernelGGL(build, dim3(count), dim3(BT), lds_build, st, metas, colf, invs, scal, pool, x0, y1, sel,
-                       lds_ld, plan->kopts.start_flux);
+                       lds_ld, plan->kopts.start_flux, queue);
   else
-    hipLaunchKernelGGL(sweeps, dim3(count), dim3(BT), lds_sweeps, st, metas, pool, x0, y1, pi, infos, sel,
-                       plan->kopts, lds_ld,
+    hipLaunchKernelGGL(sweeps, dim3(persistent ? plan->tiles.fused_blocks : count), dim3(BT), lds_sweeps, st,
+                       metas, pool, x0, y1, pi, infos, sel, plan->kopts, lds_ld,
                        plan->tiles.dense_sweeps < plan->kopts.max_iter ? plan->tiles.dense_sweeps : INT32_MAX,
-                       reinterpret_cast<T*>(w + plan->off_xbuf), reinterpret_cast<SolveState*>(w + plan->off_state));
+                       reinterpret_cast<T*>(w + plan->off_xbuf), reinterpret_cast<SolveState*>(w + plan->off_state),
+                       queue, count);
   return last_launch();
 }
 

@@ -99,20 +99,20 @@ class TileConfig(ctypes.Structure):
         ("fused_threads", ctypes.c_int32), ("fused_unroll", ctypes.c_int32),
         ("fused_max_bins", ctypes.c_int32), ("band_rows", ctypes.c_int32),
         ("dense_sweeps", ctypes.c_int32), ("band_cpt", ctypes.c_int32), ("independent_paths", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("fused_blocks", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {"fused_threads": self.fused_threads, "fused_unroll": self.fused_unroll,
                 "fused_max_bins": self.fused_max_bins, "band_rows": self.band_rows,
                 "dense_sweeps": self.dense_sweeps, "band_cpt": self.band_cpt,
-                "independent_paths": self.independent_paths}
+                "independent_paths": self.independent_paths, "fused_blocks": self.fused_blocks}
 
 
 def tiles(fused_threads=0, fused_unroll=0, fused_max_bins=0, band_rows=0, dense_sweeps=0, band_cpt=0,
-          independent_paths=0):
+          independent_paths=0, fused_blocks=0):
     return TileConfig(fused_threads, fused_unroll, fused_max_bins, band_rows, dense_sweeps, band_cpt,
-                      independent_paths, 0)
+                      independent_paths, fused_blocks)
 
 
 SPECTRAL_INFO_DTYPE = np.dtype([

@@ -218,8 +218,7 @@ def test_tile_config_defaults_and_limits(d):
                 d.tiles(fused_unroll=16), d.tiles(independent_paths=2)):
         with pytest.raises(d.DtmError):
             d.Plan(scenes, "f32", tiles=bad)
-    t = d.tiles(band_rows=512, band_cpt=2)
-    t.reserved = 1
+    t = d.tiles(band_rows=512, band_cpt=2, fused_blocks=-1)
     with pytest.raises(d.DtmError):
         d.Plan(scenes, "f32", tiles=t)
     plan = d.Plan(scenes, "f32", tiles=d.tiles(independent_paths=1))

@@ -101,3 +101,31 @@ def test_independent_paths_give_the_same_bits():
         else:
             assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
     assert np.all(d.infos_to_numpy(ref[1])["status"] == 0)
+
+
+@pytest.mark.parametrize("blocks", [1, 7, 64])
+def test_persistent_one_block_workgroups_give_the_same_bits(blocks):
+    """A few persistent workgroups taking pixels from a counter run the same
+    per-pixel code as one workgroup per pixel: the same bits, eager and
+    replayed twice as a graph (the build launch resets the counter)."""
+    d = lib()
+    scenes = np.concatenate([sc.batched_uneven(40, seed=114), sc.random_small(24, seed=115)])
+    _, plan, ws, pi, infos = _setup(scenes, "f32", d.tiles(dense_sweeps=6))
+    plan.solve(pi, infos)
+    torch.cuda.synchronize()
+    ref = (pi.clone(), infos.clone())
+    plan.close()
+    _, plan, ws, pi, infos = _setup(scenes, "f32", d.tiles(dense_sweeps=6, fused_blocks=blocks))
+    plan.solve(pi, infos)
+    torch.cuda.synchronize()
+    assert torch.equal(pi, ref[0]) and torch.equal(infos, ref[1])
+    g = plan.graph(pi, infos)
+    for _ in range(2):
+        pi.fill_(float("nan"))
+        infos.zero_()
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(pi, ref[0]) and torch.equal(infos, ref[1])
+    g.close()
+    plan.close()
+    assert np.all(d.infos_to_numpy(ref[1])["status"] == 0)
