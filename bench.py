@@ -84,6 +84,11 @@ def profile_record(tag, kernel, workload, files):
     return None
 
 
+def progress(msg):
+    """A phase line on stderr (the JSON result alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def _mc_oracle_one(rec):
     import numpy as np
 
@@ -885,6 +890,8 @@ def main():
                     help="pixels compared with the float64 oracle after timing: 0 = every pixel (default "
                          "for the uniform batch), k > 0 = k sampled pixels (uniform batch) or k pixels of "
                          "each size (uneven batch, default 4)")
+    ap.add_argument("--check-workers", type=int, default=0,
+                    help="host processes of the oracle check (0 = one per core up to 16; 1 = in this process)")
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--single-sample", type=int, default=256,
                     help="pixels timed on the plain single-pixel GPU path (0 = skip)")
@@ -969,6 +976,7 @@ def main():
     else:
         step = graph.launch if graph else (lambda: plan.solve(pi, infos))
 
+    progress(f"plan of {plan.n_pixels} pixels bound; {args.warmup} warmup steps")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -981,6 +989,7 @@ def main():
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
     ms_step = ms / args.steps
+    progress(f"{args.steps} timed steps: {ms_step:.3f} ms per step")
 
     info = dtm.infos_to_numpy(infos)
     n = scenes["n_bins"].astype(np.float64)
@@ -1024,9 +1033,10 @@ def main():
         sample = (np.sort(rng.choice(plan.n_pixels, min(per, plan.n_pixels), replace=False)) if per > 0
                   else np.arange(plan.n_pixels))
         sample_desc = f"{sample.size} sampled pixels" if per > 0 else "every pixel"
+    progress(f"oracle check of {sample.size} pixels")
     t_check = time.perf_counter()
     if args.variant == "paper":
-        l1s = opool.l1_many(scenes[sample], [vecs[p] for p in sample])
+        l1s = opool.l1_many(scenes[sample], [vecs[p] for p in sample], workers=args.check_workers or None)
     else:
         from oracle import variants as ovar
         shift_lam = {"nearest": ("nearest", "point"), "bin_mean": ("ceil", "bin_mean"),
@@ -1036,6 +1046,7 @@ def main():
         l1s = np.array([float(np.abs(vecs[p] - odtm.stationary_solve(
             ovar.transition_matrix_variant(scenes[p], *shift_lam))).sum()) for p in sample])
     t_check = time.perf_counter() - t_check
+    progress(f"oracle check done in {t_check:.1f} s")
     l1_report = {"max": float(l1s.max()), "median": float(np.median(l1s)), "pixels": int(sample.size),
                  "of": int(plan.n_pixels), "sample": sample_desc,
                  "oracle": "float64 dense build + LAPACK solve per pixel", "wall_s": t_check}
@@ -1137,6 +1148,7 @@ def main():
         out["plain_single_pixel_gpu"] = plain_single_pixel(scenes, args.single_sample)
         out["plain_single_pixel_gpu"]["batched_speedup"] = value / out["plain_single_pixel_gpu"]["pixels_per_s"]
     if not args.no_cpu_baseline and not uneven and not factored:
+        progress(f"CPU oracle baseline on {args.cpu_sample} pixels")
         out["cpu_baseline"] = cpu_baseline(scenes, args.cpu_sample)
     print(json.dumps(out), flush=True)
 

@@ -46,6 +46,10 @@ def default_workers():
 
 
 def _run(fn, tasks, workers):
+    """fn over tasks in worker processes; workers == 1 runs them in this
+    process (no child processes, e.g. under a profiler that follows them)."""
+    if workers == 1:
+        return [fn(t) for t in tasks]
     import multiprocessing as mp
     saved = {v: os.environ.get(v) for v in _BLAS_VARS}
     for v in _BLAS_VARS:

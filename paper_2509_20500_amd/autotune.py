@@ -35,11 +35,11 @@ def candidates(scenes):
     out, seen = [], set()
     # dense_sweeps: 0 = the default budget (32 sweeps), 12 = slowly mixing
     # pixels finish on the float64 factored product after twelve dense sweeps;
-    # fused_blocks: 0 = one workgroup per one-block pixel, 128 = persistent
-    # workgroups (only differs when banded pixels share the plan)
+    # fused_blocks: 0 = one workgroup per one-block pixel, 96 or 128 =
+    # persistent workgroups (only differs when banded pixels share the plan)
     n_min = int(np.min(scenes["n_bins"]))
     for threads, unroll, fmax, band, cpt, dense, blocks in itertools.product(
-            (256, 512), (4, 8), (1024, 2048, 4096), (1024, 8192), (1, 4), (0, 12), (0, 128)):
+            (256, 512), (4, 8), (1024, 2048, 4096), (1024, 8192), (1, 4), (0, 12), (0, 96, 128)):
         eff_fmax = min(fmax, n_max)
         big = n_max > fmax
         mixed = big and n_min <= fmax

@@ -522,6 +522,87 @@ __device__ void deflated(const PixelMeta& m, const Vecs& V, double c, const doub
   __syncthreads();
 }
 
+// Exclusive prefix sums over the block, in thread order, of N values at
+// once (one barrier round for all); tot gets the N totals.  red holds
+// N * BT / 64 doubles.
+template <int N>
+__device__ inline void block_exclusive_scan_n(double (&v)[N], double (&tot)[N], double* red) {
+  constexpr int NW = BT / kWave;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  double x[N], excl[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    x[q] = v[q];
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const double y = __shfl_up(x[q], off, kWave);
+      if (lane >= off) x[q] += y;
+    }
+    excl[q] = __shfl_up(x[q], 1, kWave);
+    if (lane == 0) excl[q] = 0.0;
+  }
+  __syncthreads();
+  if (lane == kWave - 1) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) red[q * NW + w] = x[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double base = 0.0, t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      if (i < w) base += red[q * NW + i];
+      t += red[q * NW + i];
+    }
+    v[q] = base + excl[q];
+    tot[q] = t;
+  }
+}
+
+// The deflated operator on the first cnt of N vectors at once: Y[i] =
+// X[i] P~ - s[i] pi, each product by the factored form of apply(), all N
+// prefix scans in one block scan.  Y[i] must not alias any X.  Ends with a
+// block barrier.
+template <int N>
+__device__ void deflated_n(const PixelMeta& m, const Vecs& V, double c, double* const (&X)[N],
+                           const double (&s)[N], double* const (&Y)[N], int cnt, double* red) {
+  const int n = m.n;
+  int j0, j1;
+  chunk_of(n, j0, j1);
+  double cs[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) cs[q] = 0.0;
+  for (int k = j0; k < j1; ++k) {
+    int i = k - m.l;
+    if (i < 0) i += n;
+    const int i2 = i == 0 ? n - 1 : i - 1;
+    const double ik = V.invs[k];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      if (q < cnt) {
+        const double xk = m.frac == 0.0 ? X[q][i] : (1.0 - m.frac) * X[q][i] + m.frac * X[q][i2];
+        const double u = xk * ik;
+        Y[q][k] = u;
+        cs[q] += u;
+      }
+    }
+  }
+  double tot[N];
+  block_exclusive_scan_n<N>(cs, tot, red);
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    if (q < cnt) {
+      double U = cs[q];
+      for (int j = j0; j < j1; ++j) {
+        U += Y[q][j];
+        Y[q][j] = V.g[j] * (c * tot[q] + (1.0 - c) * U) - s[q] * V.x[j];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Sums of N values over the block (every thread gets all of them), one
 // barrier round for all; red holds N * BT / 64 doubles.
 template <int N>
@@ -743,9 +824,7 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
         }
     }
     block_sum_n<KSUB>(sums, red);
-#pragma unroll
-    for (int i = 0; i < KSUB; ++i)
-      if (i < ke) deflated(m, V, c, Q[i], sums[i], W[i], red);
+    deflated_n<KSUB>(m, V, c, Q, sums, W, ke, red);
   }
   double re = 0.0, im = 0.0, l3 = 0.0, change = 0.0, prev_re = 2.0, prev_im = 2.0, prev_l3 = 2.0;
   int it = 0, settled = 0, flags = 0;
@@ -804,9 +883,7 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
       __syncthreads();
     }
     // W = A Q
-#pragma unroll
-    for (int i = 0; i < KSUB; ++i)
-      if (i < ke) deflated(m, V, c, Q[i], s[i], W[i], red);
+    deflated_n<KSUB>(m, V, c, Q, s, W, ke, red);
     // Rayleigh-Ritz every eighth step until the Ritz values have nearly
     // settled, then every step
     if (!fine && it + 1 < next_rr && it + 1 < max_iter) continue;
