@@ -118,7 +118,9 @@ struct SingleLayout {
 constexpr SingleLayout single_layout(int32_t n, dtm_dtype dt) {
   SingleLayout L{};
   L.ld = padded_ld(n, dt);
-  const int32_t want = (n + 63) / 64;
+  // bands of about 32 rows up to 2048 bins (a 1000-bin matrix is swept by 64
+  // workgroups), of about 64 rows above
+  const int32_t want = n <= 2048 ? (n + 31) / 32 : (n + 63) / 64;
   L.bands = want < 256 ? want : 256;
   L.band_rows = (n + L.bands - 1) / L.bands;
   L.bands = (n + L.band_rows - 1) / L.band_rows;

@@ -979,6 +979,51 @@ __global__ __launch_bounds__(BT) void k_solver_init(const T* x0, T* x, double* d
   }
 }
 
+// sum_{i0 <= i < i1} x_i P[i, j0 .. j0 + VN) in row order (float32
+// compensated into acc/cmp, or float64 into accd on a check sweep), with
+// sixteen rows' loads issued ahead of their adds: a small matrix is swept
+// by few workgroups, and with one load in flight per thread each would wait
+// on memory latency row after row.  The order of the additions, and so the
+// result, is that of the plain row loop.
+template <typename T, int VN>
+__device__ inline void band_dot(const T* __restrict__ P, int64_t ld, int i0, int i1, int j0,
+                                const T* __restrict__ x, bool check, T (&acc)[VN], T (&cmp)[VN],
+                                double (&accd)[VN]) {
+  using V = typename Vec<T>::type;
+  constexpr int U = 16;
+  int i = i0;
+  for (; i + U <= i1; i += U) {
+    V v[U];
+    T xi[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = *reinterpret_cast<const V*>(P + static_cast<int64_t>(i + u) * ld + j0);
+      xi[u] = x[i + u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (check) {
+#pragma unroll
+        for (int e = 0; e < VN; ++e) accd[e] += static_cast<double>(xi[u]) * static_cast<double>(v[u][e]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VN; ++e) comp_add(acc[e], cmp[e], xi[u] * v[u][e]);
+      }
+    }
+  }
+  for (; i < i1; ++i) {
+    const V v = *reinterpret_cast<const V*>(P + static_cast<int64_t>(i) * ld + j0);
+    const T xi = x[i];
+    if (check) {
+#pragma unroll
+      for (int e = 0; e < VN; ++e) accd[e] += static_cast<double>(xi) * static_cast<double>(v[e]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < VN; ++e) comp_add(acc[e], cmp[e], xi * v[e]);
+    }
+  }
+}
+
 // Partial sums part[b][j] = sum_{i in band b} x_i P[i, j] for the column
 // block blockIdx.x (BT * VN columns); float32 is compensated, the check
 // sweep is float64.
@@ -1004,18 +1049,7 @@ __global__ __launch_bounds__(BT) void k_sweep_band(const T* __restrict__ P, int 
     accd[e] = 0.0;
   }
   if (VN > 1 && ne == VN) {
-    using V = typename Vec<T>::type;
-    for (int i = i0; i < i1; ++i) {
-      const V v = *reinterpret_cast<const V*>(P + static_cast<int64_t>(i) * ld + j0);
-      const T xi = x[i];
-      if (check) {
-#pragma unroll
-        for (int e = 0; e < VN; ++e) accd[e] += static_cast<double>(xi) * static_cast<double>(v[e]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < VN; ++e) comp_add(acc[e], cmp[e], xi * v[e]);
-      }
-    }
+    band_dot<T, VN>(P, ld, i0, i1, j0, x, check, acc, cmp, accd);
   } else {
     for (int i = i0; i < i1; ++i) {
       const T xi = x[i];

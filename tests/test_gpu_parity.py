@@ -110,6 +110,31 @@ def test_single_pixel_n4096_dead_time_sweep(dt):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n", [2, 65, 2048, 2049, 2112])
+def test_single_pixel_band_shapes(dt, n):
+    """Up to 2048 bins the single-pixel sweep takes bands of about 32 rows,
+    above about 64.  Both sides of the switch, ragged last bands and the
+    two-bin chain, against the oracle and with the iteration count of the
+    oracle's own power iteration; a second solve on the same workspace."""
+    d = lib()
+    s = sc.scene(dead_time=61.7, center=40.0, sigma=0.6, signal=2.0, background=0.3, n_bins=n)
+    P = _single_build(s, dt, "transition")
+    pi = torch.empty(n, dtype=tdtype(dt), device="cuda")
+    ws = d.workspace(n, dt)
+    tol = TOL_F64 if dt == "f64" else TOL_F32
+    o = d.opts(tol=1e-12, stop_rule=d.DTM_STOP_CHANGE) if dt == "f64" else d.opts(tol=tol)
+    for _ in range(2):
+        pi.fill_(float("nan"))
+        info = d.stationary_pdf(P, pi, ws, o)
+        assert info.status == d.DTM_OK
+        err = np.abs(pi.cpu().numpy() - oracle_pi(s)).sum()
+        assert err <= tol, (n, err, info.iterations)
+    if dt == "f64":
+        _, it_ref, _ = odtm.stationary_power(odtm.transition_matrix(s), tol_change=1e-12)
+        assert abs(info.iterations - it_ref) <= 3
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_single_pixel_on_unaligned_stride(dt):
     """A caller's matrix with an odd row stride takes the scalar path."""
     d = lib()
