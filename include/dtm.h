@@ -461,9 +461,15 @@ int dtm_build_transition_batched(const dtm_plan* plan, void* P_packed_dev,
  * iteration (dtm_solve_batched's x0; the solver's float64 residual decides,
  * uniform is the fallback):
  *   features phi (5, see dtm_mlp_features) -> Linear(5, 256) -> GELU
- *   -> Linear(256, 256) -> GELU -> Linear(256, 1024) -> (+ prior logits)
- *   -> softmax,
+ *   -> Linear(256, 256) -> GELU -> Linear(256, 1024) -> (rotate by the
+ *   pulse bin) -> (+ prior logits) -> softmax,
  * the optional prior being the log of the flux start (dtm_mlp_flux_prior).
+ * With a pulse bin k per row (dtm_mlp_features' shift output), the
+ * network's output m is the logit of bin (m + k) mod 1024: it works in a
+ * frame centred on the laser pulse.  The model is periodic in the arrival
+ * time, so moving the pulse by whole bins rotates pi (up to the Gaussian's
+ * tail beyond the period's ends); in that frame pi depends on the scene
+ * only through S, B, sigma, t_d and the pulse's offset within its bin.
  * GELU is the erf form.  GEMMs use bfloat16 operands with float32
  * accumulation on the matrix cores; everything else is float32.  All state
  * lives in a caller-owned workspace described by dtm_mlp_layout: float32
@@ -488,9 +494,14 @@ typedef struct dtm_mlp_layout {
 
 int dtm_mlp_workspace_layout(int32_t max_batch, dtm_mlp_layout* layout_out);
 /* Features of n device scenes into feat_dev (n x 5 float32):
- * 2 tau/t_r - 1, sigma [ns], 2 (ln S - ln 0.05)/ln 100 - 1,
- * 2 (ln B - ln 0.01)/ln 100 - 1, (t_d mod t_r)/t_r. */
-int dtm_mlp_features(const dtm_scene* scenes_dev, int32_t n, float* feat_dev, dtm_stream_t stream);
+ * 2 u, sigma [ns], 2 (ln S - ln 0.05)/ln 100 - 1,
+ * 2 (ln B - ln 0.01)/ln 100 - 1, (t_d mod t_r)/t_r,
+ * where the pulse bin is k = floor(tau / (t_r / 1024)) and
+ * u = tau / (t_r / 1024) - k - 1/2 in [-1/2, 1/2) is the pulse's offset from
+ * that bin's centre (both in float64).  shift_dev (n int32, may be NULL)
+ * receives k. */
+int dtm_mlp_features(const dtm_scene* scenes_dev, int32_t n, float* feat_dev, int32_t* shift_dev,
+                     dtm_stream_t stream);
 /* Refresh the bfloat16 copies after writing the float32 parameters. */
 int dtm_mlp_sync_bf16(void* workspace_dev, int32_t max_batch, dtm_stream_t stream);
 /* Prior logits for the network's output (n x 1024 float32):
@@ -499,17 +510,20 @@ int dtm_mlp_sync_bf16(void* workspace_dev, int32_t max_batch, dtm_stream_t strea
  * solver's flux start (DTM_FLAG_START_FLUX).  With it the network learns a
  * correction to that start rather than the whole PDF. */
 int dtm_mlp_flux_prior(const dtm_scene* scenes_dev, int32_t n, float* prior_dev, dtm_stream_t stream);
-/* probs_dev (batch x 1024 float32) = softmax(network(feat_dev) + prior_dev);
- * prior_dev (batch x 1024 float32) may be NULL (no prior). */
+/* probs_dev (batch x 1024 float32) = softmax(rotate(network(feat_dev), k)
+ * + prior_dev): probs_dev[i][j] uses the network's output (j - k_i) mod 1024
+ * with k_i = shift_dev[i] (taken mod 1024).  prior_dev (batch x 1024 float32)
+ * and shift_dev (batch int32) may each be NULL (no prior; k = 0). */
 int dtm_mlp_forward(void* workspace_dev, int32_t max_batch, const float* feat_dev, const float* prior_dev,
-                    int32_t batch, float* probs_dev, dtm_stream_t stream);
-/* Forward (with the same optional prior), cross-entropy
+                    const int32_t* shift_dev, int32_t batch, float* probs_dev, dtm_stream_t stream);
+/* Forward (with the same optional prior and shift), cross-entropy
  * -sum_j target_j log q_j per row (loss_dev, may be NULL), and the gradients
  * of the mean loss into the workspace's grads.  The weight gradients split
  * the batch over blocks when their outputs have few tiles; the partial
  * products are added in a fixed order, so results are reproducible. */
 int dtm_mlp_backward(void* workspace_dev, int32_t max_batch, const float* feat_dev, const float* prior_dev,
-                     const float* target_dev, int32_t batch, float* loss_dev, dtm_stream_t stream);
+                     const int32_t* shift_dev, const float* target_dev, int32_t batch, float* loss_dev,
+                     dtm_stream_t stream);
 /* One Adam step (bias-corrected, step >= 1) on every parameter. */
 int dtm_mlp_adam(void* workspace_dev, int32_t max_batch, float lr, float beta1, float beta2,
                  float eps, int32_t step, dtm_stream_t stream);

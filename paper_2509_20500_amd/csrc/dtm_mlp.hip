@@ -163,14 +163,22 @@ __global__ void k_sum_splits(const float* __restrict__ part, int splits, int64_t
 }
 
 // Features of a scene, fixed affine maps onto about [-1, 1]:
-//   2 tau / t_r - 1, sigma / 1 ns, 2 (ln S - ln 0.05) / ln 100 - 1,
-//   2 (ln B - ln 0.01) / ln 100 - 1, (t_d mod t_r) / t_r.
-__global__ void k_features(const dtm_scene* __restrict__ scenes, int n, float* __restrict__ feat) {
+//   2 u, sigma / 1 ns, 2 (ln S - ln 0.05) / ln 100 - 1,
+//   2 (ln B - ln 0.01) / ln 100 - 1, (t_d mod t_r) / t_r,
+// with the pulse bin k = floor(tau / (t_r / OUT)) (written to shift) and u
+// the pulse's offset from that bin's centre, in [-1/2, 1/2).  The output
+// layer works in the frame of bin k (k_softmax_xent rotates it), so the
+// pulse's absolute position is not a feature.
+__global__ void k_features(const dtm_scene* __restrict__ scenes, int n, float* __restrict__ feat,
+                           int32_t* __restrict__ shift) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const dtm_scene s = scenes[p];
   const double l100 = log(100.0);
-  feat[p * IN + 0] = static_cast<float>(2.0 * s.pulse_center_ns / s.period_ns - 1.0);
+  const double pos = s.pulse_center_ns / (s.period_ns / OUT);
+  const double k = floor(pos);
+  feat[p * IN + 0] = static_cast<float>(2.0 * (pos - k - 0.5));
+  if (shift) shift[p] = static_cast<int32_t>(k);
   feat[p * IN + 1] = static_cast<float>(s.pulse_sigma_ns);
   feat[p * IN + 2] = static_cast<float>(2.0 * (log(fmax(s.signal_flux, 1e-30)) - log(0.05)) / l100 - 1.0);
   feat[p * IN + 3] = static_cast<float>(2.0 * (log(fmax(s.background_flux, 1e-30)) - log(0.01)) / l100 - 1.0);
@@ -224,13 +232,15 @@ __global__ void k_pack_input(const float* __restrict__ feat, int batch, bf16* __
   x0[idx] = k < IN ? f2bf(feat[i * IN + k]) : static_cast<bf16>(0);
 }
 
-// Row-wise softmax of the logits plus the prior logits (when given);
-// optionally cross-entropy against a target distribution with its gradient
-// dZ = (q - target) / batch (float32 and bfloat16; the prior is a constant,
-// so the gradient is the same).  One block of 256 threads per row of
-// OUT = 1024 logits.
+// Row-wise softmax of the logits, rotated by the row's pulse bin k (bin j
+// takes logit (j - k) mod OUT; k = 0 without shift), plus the prior logits
+// (when given); optionally cross-entropy against a target distribution with
+// its gradient dZ = (q - target) / batch written back at the rotated
+// positions (float32 and bfloat16; the prior is a constant, so the gradient
+// is the same).  One block of 256 threads per row of OUT = 1024 logits.
 __global__ __launch_bounds__(256) void k_softmax_xent(const float* __restrict__ z, int batch,
                                                       const float* __restrict__ prior,
+                                                      const int32_t* __restrict__ shift,
                                                       const float* __restrict__ target,
                                                       float* __restrict__ q_out,
                                                       float* __restrict__ dz, bf16* __restrict__ dzb,
@@ -238,12 +248,13 @@ __global__ __launch_bounds__(256) void k_softmax_xent(const float* __restrict__ 
   __shared__ float red[4];
   const int i = blockIdx.x;
   const float* zr = z + static_cast<int64_t>(i) * OUT;
+  const int k = shift ? shift[i] : 0;
   const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
   float v[4];
   float mx = -INFINITY;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    v[r] = zr[tid + 256 * r];
+    v[r] = zr[(tid + 256 * r - k) & (OUT - 1)];
     if (prior) v[r] += prior[static_cast<int64_t>(i) * OUT + tid + 256 * r];
     mx = fmaxf(mx, v[r]);
   }
@@ -268,15 +279,16 @@ __global__ __launch_bounds__(256) void k_softmax_xent(const float* __restrict__ 
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int j = tid + 256 * r;
+    const int m = (j - k) & (OUT - 1);
     const float q = v[r] / s;
-    const float zj = zr[j] + (prior ? prior[static_cast<int64_t>(i) * OUT + j] : 0.f);
+    const float zj = zr[m] + (prior ? prior[static_cast<int64_t>(i) * OUT + j] : 0.f);
     if (q_out) q_out[static_cast<int64_t>(i) * OUT + j] = q;
     if (target) {
       const float t = target[static_cast<int64_t>(i) * OUT + j];
       l -= t * (zj - lse);
       const float g = (q - t) / batch;
-      dz[static_cast<int64_t>(i) * OUT + j] = g;
-      dzb[static_cast<int64_t>(i) * OUT + j] = f2bf(g);
+      dz[static_cast<int64_t>(i) * OUT + m] = g;
+      dzb[static_cast<int64_t>(i) * OUT + m] = f2bf(g);
     }
   }
   if (target) {
@@ -537,10 +549,11 @@ int dtm_mlp_workspace_layout(int32_t max_batch, dtm_mlp_layout* out) {
   return DTM_OK;
 }
 
-int dtm_mlp_features(const dtm_scene* scenes_dev, int32_t n, float* feat_dev, dtm_stream_t stream) {
+int dtm_mlp_features(const dtm_scene* scenes_dev, int32_t n, float* feat_dev, int32_t* shift_dev,
+                     dtm_stream_t stream) {
   if (!scenes_dev || !feat_dev || n < 1) return DTM_EINVAL;
   hipLaunchKernelGGL(k_features, dim3((n + 255) / 256), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), scenes_dev, n, feat_dev);
+                     static_cast<hipStream_t>(stream), scenes_dev, n, feat_dev, shift_dev);
   return ok_launch();
 }
 
@@ -561,25 +574,26 @@ int dtm_mlp_flux_prior(const dtm_scene* scenes_dev, int32_t n, float* prior_dev,
   return ok_launch();
 }
 
-int dtm_mlp_forward(void* ws, int32_t max_batch, const float* feat_dev, const float* prior_dev, int32_t batch,
-                    float* probs_dev, dtm_stream_t stream) {
+int dtm_mlp_forward(void* ws, int32_t max_batch, const float* feat_dev, const float* prior_dev,
+                    const int32_t* shift_dev, int32_t batch, float* probs_dev, dtm_stream_t stream) {
   if (!ws || !feat_dev || !probs_dev || !batch_ok(batch, max_batch)) return DTM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Ptrs P = pointers(ws, max_batch);
   forward(P, feat_dev, batch, st);
-  hipLaunchKernelGGL(k_softmax_xent, dim3(batch), dim3(256), 0, st, P.z, batch, prior_dev, nullptr, probs_dev,
-                     nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL(k_softmax_xent, dim3(batch), dim3(256), 0, st, P.z, batch, prior_dev, shift_dev, nullptr,
+                     probs_dev, nullptr, nullptr, nullptr);
   return ok_launch();
 }
 
 int dtm_mlp_backward(void* ws, int32_t max_batch, const float* feat_dev, const float* prior_dev,
-                     const float* target_dev, int32_t batch, float* loss_dev, dtm_stream_t stream) {
+                     const int32_t* shift_dev, const float* target_dev, int32_t batch, float* loss_dev,
+                     dtm_stream_t stream) {
   if (!ws || !feat_dev || !target_dev || !batch_ok(batch, max_batch)) return DTM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Ptrs P = pointers(ws, max_batch);
   forward(P, feat_dev, batch, st);
-  hipLaunchKernelGGL(k_softmax_xent, dim3(batch), dim3(256), 0, st, P.z, batch, prior_dev, target_dev, P.q,
-                     P.dz, P.dzb, loss_dev ? loss_dev : P.loss);
+  hipLaunchKernelGGL(k_softmax_xent, dim3(batch), dim3(256), 0, st, P.z, batch, prior_dev, shift_dev, target_dev,
+                     P.q, P.dz, P.dzb, loss_dev ? loss_dev : P.loss);
   // layer 3: dW3 = H2^T dZ, db3 = sum dZ, dH2 = dZ W3^T
   gemm_grad(H, OUT, batch, P.h2, H, P.dzb, OUT, P.gw3, P.partial, st);
   hipLaunchKernelGGL(k_bias_grad, dim3((OUT + BG_COLS - 1) / BG_COLS), dim3(BG_THREADS), 0, st, P.dz, batch, OUT,

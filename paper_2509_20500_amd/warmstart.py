@@ -6,14 +6,16 @@ and saves / restores checkpoints.
 Typical use::
 
     net = WarmStartMLP(max_batch=1024, seed=0)
-    feat, prior = net.features(scenes), net.flux_prior(scenes)
-    net.fit(feat, targets, epochs=20, prior=prior)   # targets: P x 1024 (device)
-    x0 = net.predict(feat, prior)                    # P x 1024 float32, rows sum to 1
+    (feat, shift), prior = net.features(scenes), net.flux_prior(scenes)
+    net.fit(feat, targets, epochs=20, prior=prior, shift=shift)   # targets: P x 1024 (device)
+    x0 = net.predict(feat, prior, shift)             # P x 1024 float32, rows sum to 1
     plan.solve(pi, infos, x0=x0.reshape(-1))         # uniform fallback is automatic
 
 With ``prior`` (the log of the flux start lambda / sum(lambda), see
 ``dtm_mlp_flux_prior``) the network's logits are added to it, so it learns a
-correction to the solver's flux start; without it, the whole PDF.
+correction to the solver's flux start; without it, the whole PDF.  With
+``shift`` (each scene's pulse bin) the network's outputs are rotated to
+start at that bin, so it learns in a frame centred on the pulse.
 """
 from __future__ import annotations
 
@@ -52,11 +54,11 @@ def _bind():
     L = dtm.lib()
     sig = {
         "dtm_mlp_workspace_layout": (ctypes.c_int, [_I32, ctypes.POINTER(Layout)]),
-        "dtm_mlp_features": (ctypes.c_int, [_P, _I32, _P, _P]),
+        "dtm_mlp_features": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
         "dtm_mlp_sync_bf16": (ctypes.c_int, [_P, _I32, _P]),
         "dtm_mlp_flux_prior": (ctypes.c_int, [_P, _I32, _P, _P]),
-        "dtm_mlp_forward": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _P, _P]),
-        "dtm_mlp_backward": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I32, _P, _P]),
+        "dtm_mlp_forward": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I32, _P, _P]),
+        "dtm_mlp_backward": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _I32, _P, _P]),
         "dtm_mlp_adam": (ctypes.c_int, [_P, _I32, _F, _F, _F, _F, _I32, _P]),
         "dtm_mlp_gemm_bf16": (ctypes.c_int, [_I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _I32, _P,
                                              _I32, _P]),
@@ -188,14 +190,16 @@ class WarmStartMLP:
 
     # ---- network ----------------------------------------------------------------
     def features(self, scenes, stream=None):
-        """phi of each scene (P x 5 float32 on the device), computed on the GPU."""
+        """(phi of each scene as P x 5 float32, each scene's pulse bin as P
+        int32), both on the device and computed on the GPU."""
         import torch
         arr = np.ascontiguousarray(scenes)
         raw = torch.from_numpy(arr.view(np.uint8).copy()).to(self.ws.device)
         feat = torch.empty((arr.size, IN), dtype=torch.float32, device=self.ws.device)
-        dtm.check(_bind().dtm_mlp_features(raw.data_ptr(), arr.size, feat.data_ptr(), dtm._stream(stream)),
-                  "dtm_mlp_features")
-        return feat
+        shift = torch.empty(arr.size, dtype=torch.int32, device=self.ws.device)
+        dtm.check(_bind().dtm_mlp_features(raw.data_ptr(), arr.size, feat.data_ptr(), shift.data_ptr(),
+                                           dtm._stream(stream)), "dtm_mlp_features")
+        return feat, shift
 
     def flux_prior(self, scenes, stream=None):
         """log(lambda_j / sum lambda) at the 1024 bin centres of each scene
@@ -208,9 +212,10 @@ class WarmStartMLP:
                   "dtm_mlp_flux_prior")
         return prior
 
-    def predict(self, feat, prior=None, stream=None):
-        """softmax(network(feat) + prior) for any number of rows, in max_batch
-        chunks (prior: P x 1024 float32, or None)."""
+    def predict(self, feat, prior=None, shift=None, stream=None):
+        """softmax(rotate(network(feat), shift) + prior) for any number of
+        rows, in max_batch chunks (prior: P x 1024 float32, shift: P int32;
+        either may be None)."""
         import torch
         P = feat.shape[0]
         out = torch.empty((P, OUT), dtype=torch.float32, device=self.ws.device)
@@ -218,15 +223,17 @@ class WarmStartMLP:
             b = min(P, a + self.max_batch)
             dtm.check(_bind().dtm_mlp_forward(self.ws.data_ptr(), self.max_batch, feat[a:b].data_ptr(),
                                               None if prior is None else prior[a:b].data_ptr(),
+                                              None if shift is None else shift[a:b].data_ptr(),
                                               b - a, out[a:b].data_ptr(), dtm._stream(stream)),
                       "dtm_mlp_forward")
         return out
 
-    def backward(self, feat, target, loss=None, prior=None, stream=None):
+    def backward(self, feat, target, loss=None, prior=None, shift=None, stream=None):
         """Gradients of the mean cross-entropy into ``grads`` (one batch)."""
         B = feat.shape[0]
         dtm.check(_bind().dtm_mlp_backward(self.ws.data_ptr(), self.max_batch, feat.data_ptr(),
                                            None if prior is None else prior.data_ptr(),
+                                           None if shift is None else shift.data_ptr(),
                                            target.data_ptr(), B, None if loss is None else loss.data_ptr(),
                                            dtm._stream(stream)), "dtm_mlp_backward")
 
@@ -235,10 +242,10 @@ class WarmStartMLP:
         dtm.check(_bind().dtm_mlp_adam(self.ws.data_ptr(), self.max_batch, lr, beta1, beta2, eps, self.step,
                                        dtm._stream(stream)), "dtm_mlp_adam")
 
-    def fit(self, feat, target, epochs=20, lr=1e-3, seed=0, log=None, prior=None):
+    def fit(self, feat, target, epochs=20, lr=1e-3, seed=0, log=None, prior=None, shift=None):
         """Adam with cosine-decayed learning rate over shuffled mini-batches
-        of max_batch rows (prior: P x 1024 prior logits, or None); returns the
-        mean loss of each epoch."""
+        of max_batch rows (prior: P x 1024 prior logits, shift: P pulse bins;
+        either may be None); returns the mean loss of each epoch."""
         import torch
         P = feat.shape[0]
         B = self.max_batch
@@ -258,7 +265,8 @@ class WarmStartMLP:
                 xb = feat.index_select(0, idx).contiguous()
                 tb = target.index_select(0, idx).contiguous()
                 pb = None if prior is None else prior.index_select(0, idx).contiguous()
-                self.backward(xb, tb, loss, prior=pb)
+                sb = None if shift is None else shift.index_select(0, idx).contiguous()
+                self.backward(xb, tb, loss, prior=pb, shift=sb)
                 t = self.step / max(1, total - 1)
                 self.adam(lr * 0.5 * (1.0 + math.cos(math.pi * min(1.0, t))))
                 acc += loss.double().mean()

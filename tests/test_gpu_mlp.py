@@ -58,11 +58,15 @@ def _oracle_params(net):
 
 
 def test_features_match_oracle():
+    """Features to float32 rounding; the pulse bins exactly (both sides
+    divide in float64), including a pulse on a bin edge."""
     net = _net()
-    scenes = np.concatenate([sc.batched_uniform(20, seed=7), sc.batched_uneven(20, seed=8)])
-    f = net.features(scenes).cpu().numpy()
+    scenes = np.concatenate([sc.batched_uniform(20, seed=7), sc.batched_uneven(20, seed=8),
+                             sc.scene(period=50.0, center=25.0), sc.scene(period=100.0, center=0.0)])
+    f, k = net.features(scenes)
     ref = np.stack([omlp.features(s) for s in scenes])
-    assert np.max(np.abs(f - ref)) < 1e-6
+    assert np.max(np.abs(f.cpu().numpy() - ref)) < 1e-6
+    assert np.array_equal(k.cpu().numpy(), [omlp.pulse_bin(s) for s in scenes])
 
 
 def test_flux_prior_matches_oracle():
@@ -82,33 +86,36 @@ def test_flux_prior_matches_oracle():
     assert np.all(np.isfinite(g)) and np.all(g[~ok] < -690.0)
 
 
-@pytest.mark.parametrize("with_prior", [False, True])
-def test_forward_and_gradients_match_oracle(with_prior):
+@pytest.mark.parametrize("with_prior,with_shift", [(False, False), (True, False), (True, True)])
+def test_forward_and_gradients_match_oracle(with_prior, with_shift):
     """Batch 300: the weight gradients split the batch over blocks (K = 300
-    in chunks of 64 to 128 rows) and add the partial products."""
+    in chunks of 64 to 128 rows) and add the partial products; with the
+    pulse-bin rotation, each bin's error goes back to the output it took."""
     net = _net(seed=1, max_batch=300)
     rng = np.random.default_rng(2)
     B = 300
     scenes = sc.batched_uniform(B, seed=9)
-    feat = net.features(scenes)
+    feat, shift = net.features(scenes)
     prior = net.flux_prior(scenes) if with_prior else None
+    shift = shift if with_shift else None
     T = rng.uniform(size=(B, omlp.OUT)).astype(np.float32)
     T /= T.sum(axis=1, keepdims=True)
     target = torch.from_numpy(T).cuda()
-    q = net.predict(feat, prior).cpu().numpy()
+    q = net.predict(feat, prior, shift).cpu().numpy()
     P = _oracle_params(net)
     X = bf16_bits(feat.cpu().numpy())[1]
     po = None if prior is None else prior.cpu().numpy().astype(np.float64)
-    Qo, _ = omlp.forward(P, X, po)
+    ko = None if shift is None else shift.cpu().numpy()
+    Qo, _ = omlp.forward(P, X, po, ko)
     assert np.max(np.abs(q - Qo)) <= 2e-2 * np.max(Qo)
     assert np.allclose(q.sum(axis=1), 1.0, atol=1e-5)
     loss = torch.empty(B, dtype=torch.float32, device="cuda")
-    net.backward(feat, target, loss, prior=prior)
+    net.backward(feat, target, loss, prior=prior, shift=shift)
     torch.cuda.synchronize()
     lo = -(T * np.log(Qo)).sum(axis=1)
     assert np.max(np.abs(loss.cpu().numpy() - lo)) <= 1e-2 * np.max(np.abs(lo))
     G = net.tensors(net.grads.detach().cpu())
-    Go = omlp.grads(P, X, T.astype(np.float64), po)
+    Go = omlp.grads(P, X, T.astype(np.float64), po, ko)
     for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
         g = G[k].numpy().astype(np.float64)
         if k == "W1":
@@ -121,7 +128,7 @@ def test_forward_and_gradients_match_oracle(with_prior):
 def test_adam_step_matches_formula():
     net = _net(seed=2)
     scenes = sc.batched_uniform(32, seed=10)
-    feat = net.features(scenes)
+    feat, _ = net.features(scenes)
     T = torch.full((32, omlp.OUT), 1.0 / omlp.OUT, device="cuda")
     w0 = net.params.detach().cpu().numpy().astype(np.float64)
     net.backward(feat, T)
@@ -137,7 +144,7 @@ def test_adam_step_matches_formula():
 
 def test_checkpoint_round_trip(tmp_path):
     net = _net(seed=3)
-    feat = net.features(sc.batched_uniform(64, seed=11))
+    feat, _ = net.features(sc.batched_uniform(64, seed=11))
     T = torch.full((64, omlp.OUT), 1.0 / omlp.OUT, device="cuda")
     for _ in range(3):
         net.backward(feat, T)
@@ -156,11 +163,11 @@ def test_checkpoint_round_trip(tmp_path):
 
 def test_trained_warm_start_saves_sweeps():
     """Train on PDFs the solver itself produces (uniform-workload sampling),
-    the network correcting the flux start (its logits added to the log of
-    lambda / sum(lambda)), then solve held-out pixels from the network's
-    prediction: fewer sweeps than from the flux start (the method's own
-    start without the network) and than from uniform, same accuracy against
-    the oracle."""
+    the network correcting the flux start (its logits, in the frame of the
+    pulse bin, added to the log of lambda / sum(lambda)), then solve held-out
+    pixels from the network's prediction: fewer sweeps than from the flux
+    start (the method's own start without the network) and than from
+    uniform, same accuracy against the oracle."""
     d = lib()
     from paper_2509_20500_amd.warmstart import WarmStartMLP
     train = sc.warm_start_train(n_pixels=16384, seed=5)
@@ -169,12 +176,13 @@ def test_trained_warm_start_saves_sweeps():
     targets = torch.from_numpy(pi_t.astype(np.float32).reshape(-1, omlp.OUT)).cuda()
     targets /= targets.sum(dim=1, keepdim=True)
     net = WarmStartMLP(max_batch=1024, seed=0, zero_output=True)
-    feat = net.features(train)
+    feat, shift = net.features(train)
     prior = net.flux_prior(train)
-    hist = net.fit(feat, targets, epochs=30, lr=2e-3, prior=prior)
+    hist = net.fit(feat, targets, epochs=30, lr=2e-3, prior=prior, shift=shift)
     assert hist[-1] < hist[0]
     held = sc.warm_start_eval(n_pixels=512, seed=6)
-    x0 = net.predict(net.features(held), net.flux_prior(held)).reshape(-1)
+    feat_h, shift_h = net.features(held)
+    x0 = net.predict(feat_h, net.flux_prior(held), shift_h).reshape(-1)
     flux = d.opts(tol=1e-6)
     flux.flags |= d.DTM_FLAG_START_FLUX
     pi_u, info_u, off = run_batched(held, "f32")
