@@ -142,7 +142,9 @@ typedef struct dtm_solve_opts {
   double tol_l1;       /* target L1 distance (rule 1) or change threshold (rule 0) */
   double safety;       /* rule 1: fraction of tol_l1 the bound must reach (0,1]   */
   int32_t max_iter;    /* sweeps, >= 1                                             */
-  int32_t check_every; /* single-pixel path: host polls every this many sweeps    */
+  int32_t check_every; /* single-pixel path: host polls after this many sweeps, then
+                          after the sweeps the stop rule predicts are left (at
+                          least 1, at most 4 check_every)                          */
   int32_t stop_rule;   /* DTM_STOP_CHANGE or DTM_STOP_BOUND                        */
   int32_t flags;       /* DTM_FLAG_*                                               */
 } dtm_solve_opts;

@@ -1264,6 +1264,21 @@ int single_build(const dtm_scene* s, dtm_dtype dt, void* P, int64_t ld, void* ws
                          reinterpret_cast<T*>(w + L.off_invs), static_cast<T*>(P), ld, shifted, 0, st);
 }
 
+// Sweeps until the stop rule is predicted to end a pixel, from the state
+// the host last read: the change shrinks by the estimated contraction per
+// sweep, the rule fires once the change passes its test, and a check sweep
+// follows.  Only schedules the next poll; the device decides convergence.
+int predicted_sweeps(const StopState& s, const KOpts& o) {
+  const bool bound = o.stop_rule != DTM_STOP_CHANGE;
+  const double need = bound ? o.safety * o.tol : o.tol;
+  const double have = bound ? s.c1 * s.gain * (o.final_check ? s.contr : 1.0) : s.c1;
+  const int check = o.final_check ? 1 : 0;
+  if (s.check_next) return 1;
+  if (!(have > need)) return 1 + check;
+  if (!(s.contr > 0.0) || s.contr >= 0.999) return 1 << 20;
+  return static_cast<int>(std::min(std::ceil(std::log(need / have) / std::log(s.contr)), 1e6)) + check;
+}
+
 template <typename T>
 int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_every, const T* x0,
                  T* pi, void* ws, dtm_solve_info* info, hipStream_t st, dtm_dtype dt) {
@@ -1286,10 +1301,12 @@ int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_e
   SolveState hs;
   // Each three launches are one sweep; after `done` they return at once.
   // The stop rule ends every solve within 2 * max_iter sweeps (one restart).
+  // The host polls after check_every sweeps, then after as many as the stop
+  // rule's estimates predict are left (at least one, at most 4 check_every).
   const int max_sweeps = 2 * ko.max_iter + 2;
-  int launched = 0;
+  int launched = 0, chunk = check_every;
   for (;;) {
-    for (int r = 0; r < check_every && launched < max_sweeps; ++r, ++launched) {
+    for (int r = 0; r < chunk && launched < max_sweeps; ++r, ++launched) {
       if (vec)
         hipLaunchKernelGGL((k_sweep_band<T, kBT, VN>), grid, dim3(kBT), 0, st, P, n, ld, x, state,
                            part, static_cast<int64_t>(L.ld), L.band_rows);
@@ -1306,6 +1323,7 @@ int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_e
     if (hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess) return DTM_EHIP;
     if (hipStreamSynchronize(st) != hipSuccess) return DTM_EHIP;
     if (hs.s.done || launched >= max_sweeps) break;
+    chunk = std::max(1, std::min(predicted_sweeps(hs.s, ko), 4 * check_every));
   }
   if (!hs.s.done) {
     hs.s.status = DTM_ENOTCONV;
