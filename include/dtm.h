@@ -519,13 +519,17 @@ int dtm_mlp_flux_prior(const dtm_scene* scenes_dev, int32_t n, float* prior_dev,
 int dtm_mlp_forward(void* workspace_dev, int32_t max_batch, const float* feat_dev, const float* prior_dev,
                     const int32_t* shift_dev, int32_t batch, float* probs_dev, dtm_stream_t stream);
 /* Forward (with the same optional prior and shift), cross-entropy
- * -sum_j target_j log q_j per row (loss_dev, may be NULL), and the gradients
- * of the mean loss into the workspace's grads.  The weight gradients split
- * the batch over blocks when their outputs have few tiles; the partial
- * products are added in a fixed order, so results are reproducible. */
+ * -sum_j target_j log q_j per row (loss_dev, batch floats, may be NULL), and
+ * the gradients of the mean loss into the workspace's grads.  rows_dev
+ * (batch int32, may be NULL) makes batch row i the row rows_dev[i] of
+ * feat_dev, prior_dev, shift_dev and target_dev (a shuffled mini-batch read
+ * in place; the caller guarantees the indices are rows of those arrays);
+ * NULL takes rows 0 .. batch-1.  The weight gradients split the batch over
+ * blocks when their outputs have few tiles; the partial products are added
+ * in a fixed order, so results are reproducible. */
 int dtm_mlp_backward(void* workspace_dev, int32_t max_batch, const float* feat_dev, const float* prior_dev,
-                     const int32_t* shift_dev, const float* target_dev, int32_t batch, float* loss_dev,
-                     dtm_stream_t stream);
+                     const int32_t* shift_dev, const float* target_dev, const int32_t* rows_dev, int32_t batch,
+                     float* loss_dev, dtm_stream_t stream);
 /* One Adam step (bias-corrected, step >= 1) on every parameter. */
 int dtm_mlp_adam(void* workspace_dev, int32_t max_batch, float lr, float beta1, float beta2,
                  float eps, int32_t step, dtm_stream_t stream);

@@ -225,11 +225,14 @@ __global__ __launch_bounds__(256) void k_flux_prior(const dtm_scene* __restrict_
 }
 
 // X0 (bfloat16, rows padded to INP columns with zeros).
-__global__ void k_pack_input(const float* __restrict__ feat, int batch, bf16* __restrict__ x0) {
+// X0 row i = the features of row rows[i] (row i without rows).
+__global__ void k_pack_input(const float* __restrict__ feat, const int32_t* __restrict__ rows, int batch,
+                             bf16* __restrict__ x0) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= batch * INP) return;
   const int i = idx / INP, k = idx % INP;
-  x0[idx] = k < IN ? f2bf(feat[i * IN + k]) : static_cast<bf16>(0);
+  const int64_t r = rows ? rows[i] : i;
+  x0[idx] = k < IN ? f2bf(feat[r * IN + k]) : static_cast<bf16>(0);
 }
 
 // Row-wise softmax of the logits, rotated by the row's pulse bin k (bin j
@@ -237,25 +240,29 @@ __global__ void k_pack_input(const float* __restrict__ feat, int batch, bf16* __
 // (when given); optionally cross-entropy against a target distribution with
 // its gradient dZ = (q - target) / batch written back at the rotated
 // positions (float32 and bfloat16; the prior is a constant, so the gradient
-// is the same).  One block of 256 threads per row of OUT = 1024 logits.
+// is the same).  The prior, pulse bin and target of batch row i are those
+// of row rows[i] (row i without rows).  One block of 256 threads per row of
+// OUT = 1024 logits.
 __global__ __launch_bounds__(256) void k_softmax_xent(const float* __restrict__ z, int batch,
                                                       const float* __restrict__ prior,
                                                       const int32_t* __restrict__ shift,
                                                       const float* __restrict__ target,
+                                                      const int32_t* __restrict__ rows,
                                                       float* __restrict__ q_out,
                                                       float* __restrict__ dz, bf16* __restrict__ dzb,
                                                       float* __restrict__ loss) {
   __shared__ float red[4];
   const int i = blockIdx.x;
+  const int64_t src = rows ? rows[i] : i;
   const float* zr = z + static_cast<int64_t>(i) * OUT;
-  const int k = shift ? shift[i] : 0;
+  const int k = shift ? shift[src] : 0;
   const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
   float v[4];
   float mx = -INFINITY;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     v[r] = zr[(tid + 256 * r - k) & (OUT - 1)];
-    if (prior) v[r] += prior[static_cast<int64_t>(i) * OUT + tid + 256 * r];
+    if (prior) v[r] += prior[src * OUT + tid + 256 * r];
     mx = fmaxf(mx, v[r]);
   }
   for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
@@ -281,10 +288,10 @@ __global__ __launch_bounds__(256) void k_softmax_xent(const float* __restrict__ 
     const int j = tid + 256 * r;
     const int m = (j - k) & (OUT - 1);
     const float q = v[r] / s;
-    const float zj = zr[m] + (prior ? prior[static_cast<int64_t>(i) * OUT + j] : 0.f);
+    const float zj = zr[m] + (prior ? prior[src * OUT + j] : 0.f);
     if (q_out) q_out[static_cast<int64_t>(i) * OUT + j] = q;
     if (target) {
-      const float t = target[static_cast<int64_t>(i) * OUT + j];
+      const float t = target[src * OUT + j];
       l -= t * (zj - lse);
       const float g = (q - t) / batch;
       dz[static_cast<int64_t>(i) * OUT + m] = g;
@@ -521,8 +528,8 @@ void gemm_grad(int M, int N, int K, const bf16* A, int lda, const bf16* B, int l
 
 // Forward pass for `batch` rows of features; leaves every activation in the
 // workspace.
-void forward(const Ptrs& P, const float* feat, int batch, hipStream_t st) {
-  hipLaunchKernelGGL(k_pack_input, dim3((batch * INP + 255) / 256), dim3(256), 0, st, feat, batch, P.x0);
+void forward(const Ptrs& P, const float* feat, const int32_t* rows, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_input, dim3((batch * INP + 255) / 256), dim3(256), 0, st, feat, rows, batch, P.x0);
   gemm<false, false, EPI_BIAS_GELU>(batch, H, INP, P.x0, INP, P.w1b, H, P.a1, H, P.b1, P.h1, H, st);
   gemm<false, false, EPI_BIAS_GELU>(batch, H, H, P.h1, H, P.w2b, H, P.a2, H, P.b2, P.h2, H, st);
   gemm<false, false, EPI_BIAS>(batch, OUT, H, P.h2, H, P.w3b, OUT, P.z, OUT, P.b3, nullptr, 0, st);
@@ -579,21 +586,21 @@ int dtm_mlp_forward(void* ws, int32_t max_batch, const float* feat_dev, const fl
   if (!ws || !feat_dev || !probs_dev || !batch_ok(batch, max_batch)) return DTM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Ptrs P = pointers(ws, max_batch);
-  forward(P, feat_dev, batch, st);
+  forward(P, feat_dev, nullptr, batch, st);
   hipLaunchKernelGGL(k_softmax_xent, dim3(batch), dim3(256), 0, st, P.z, batch, prior_dev, shift_dev, nullptr,
-                     probs_dev, nullptr, nullptr, nullptr);
+                     nullptr, probs_dev, nullptr, nullptr, nullptr);
   return ok_launch();
 }
 
 int dtm_mlp_backward(void* ws, int32_t max_batch, const float* feat_dev, const float* prior_dev,
-                     const int32_t* shift_dev, const float* target_dev, int32_t batch, float* loss_dev,
-                     dtm_stream_t stream) {
+                     const int32_t* shift_dev, const float* target_dev, const int32_t* rows_dev, int32_t batch,
+                     float* loss_dev, dtm_stream_t stream) {
   if (!ws || !feat_dev || !target_dev || !batch_ok(batch, max_batch)) return DTM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Ptrs P = pointers(ws, max_batch);
-  forward(P, feat_dev, batch, st);
+  forward(P, feat_dev, rows_dev, batch, st);
   hipLaunchKernelGGL(k_softmax_xent, dim3(batch), dim3(256), 0, st, P.z, batch, prior_dev, shift_dev, target_dev,
-                     P.q, P.dz, P.dzb, loss_dev ? loss_dev : P.loss);
+                     rows_dev, P.q, P.dz, P.dzb, loss_dev ? loss_dev : P.loss);
   // layer 3: dW3 = H2^T dZ, db3 = sum dZ, dH2 = dZ W3^T
   gemm_grad(H, OUT, batch, P.h2, H, P.dzb, OUT, P.gw3, P.partial, st);
   hipLaunchKernelGGL(k_bias_grad, dim3((OUT + BG_COLS - 1) / BG_COLS), dim3(BG_THREADS), 0, st, P.dz, batch, OUT,

@@ -58,7 +58,7 @@ def _bind():
         "dtm_mlp_sync_bf16": (ctypes.c_int, [_P, _I32, _P]),
         "dtm_mlp_flux_prior": (ctypes.c_int, [_P, _I32, _P, _P]),
         "dtm_mlp_forward": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I32, _P, _P]),
-        "dtm_mlp_backward": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _I32, _P, _P]),
+        "dtm_mlp_backward": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, _P, _P]),
         "dtm_mlp_adam": (ctypes.c_int, [_P, _I32, _F, _F, _F, _F, _I32, _P]),
         "dtm_mlp_gemm_bf16": (ctypes.c_int, [_I32, _I32, _I32, _P, _I32, _I32, _P, _I32, _I32, _P,
                                              _I32, _P]),
@@ -228,13 +228,16 @@ class WarmStartMLP:
                       "dtm_mlp_forward")
         return out
 
-    def backward(self, feat, target, loss=None, prior=None, shift=None, stream=None):
-        """Gradients of the mean cross-entropy into ``grads`` (one batch)."""
-        B = feat.shape[0]
+    def backward(self, feat, target, loss=None, prior=None, shift=None, rows=None, stream=None):
+        """Gradients of the mean cross-entropy into ``grads`` (one batch: the
+        rows ``rows`` (int32 on the device) of feat, target, prior and shift,
+        or all of their rows)."""
+        B = feat.shape[0] if rows is None else rows.shape[0]
         dtm.check(_bind().dtm_mlp_backward(self.ws.data_ptr(), self.max_batch, feat.data_ptr(),
                                            None if prior is None else prior.data_ptr(),
                                            None if shift is None else shift.data_ptr(),
-                                           target.data_ptr(), B, None if loss is None else loss.data_ptr(),
+                                           target.data_ptr(), None if rows is None else rows.data_ptr(),
+                                           B, None if loss is None else loss.data_ptr(),
                                            dtm._stream(stream)), "dtm_mlp_backward")
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
@@ -255,22 +258,18 @@ class WarmStartMLP:
         total = epochs * nb
         g = torch.Generator(device="cpu")
         g.manual_seed(seed)
-        loss = torch.empty(B, dtype=torch.float32, device=self.ws.device)
+        loss = torch.empty(nb * B, dtype=torch.float32, device=self.ws.device)
         hist = []
         for ep in range(epochs):
-            perm = torch.randperm(P, generator=g).to(self.ws.device)
-            acc = torch.zeros((), dtype=torch.float64, device=self.ws.device)
+            # the shuffle is drawn on the host; the library reads each
+            # mini-batch's rows in place
+            perm = torch.randperm(P, generator=g).to(dtype=torch.int32, device=self.ws.device)
             for b in range(nb):
-                idx = perm[b * B:(b + 1) * B]
-                xb = feat.index_select(0, idx).contiguous()
-                tb = target.index_select(0, idx).contiguous()
-                pb = None if prior is None else prior.index_select(0, idx).contiguous()
-                sb = None if shift is None else shift.index_select(0, idx).contiguous()
-                self.backward(xb, tb, loss, prior=pb, shift=sb)
+                self.backward(feat, target, loss[b * B:(b + 1) * B], prior=prior, shift=shift,
+                              rows=perm[b * B:(b + 1) * B])
                 t = self.step / max(1, total - 1)
                 self.adam(lr * 0.5 * (1.0 + math.cos(math.pi * min(1.0, t))))
-                acc += loss.double().mean()
-            hist.append(float(acc) / nb)
+            hist.append(float(loss.cpu().numpy().astype(np.float64).mean()))
             if log:
                 log(ep, hist[-1])
         return hist

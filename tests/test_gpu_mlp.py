@@ -125,6 +125,31 @@ def test_forward_and_gradients_match_oracle(with_prior, with_shift):
         assert rel < 3e-2, (k, rel)
 
 
+def test_backward_reads_shuffled_rows_in_place():
+    """A mini-batch named by row indices gives the same loss and gradients,
+    bit for bit, as the same rows gathered beforehand."""
+    net = _net(seed=4, max_batch=256)
+    scenes = sc.batched_uniform(600, seed=12)
+    feat, shift = net.features(scenes)
+    prior = net.flux_prior(scenes)
+    rng = np.random.default_rng(3)
+    T = rng.uniform(size=(600, omlp.OUT)).astype(np.float32)
+    T /= T.sum(axis=1, keepdims=True)
+    target = torch.from_numpy(T).cuda()
+    idx = torch.from_numpy(rng.permutation(600)[:256].astype(np.int32)).cuda()
+    loss_a = torch.empty(256, dtype=torch.float32, device="cuda")
+    net.backward(feat, target, loss_a, prior=prior, shift=shift, rows=idx)
+    torch.cuda.synchronize()
+    ga = net.grads.detach().clone()
+    il = idx.long()
+    loss_b = torch.empty(256, dtype=torch.float32, device="cuda")
+    net.backward(feat[il].contiguous(), target[il].contiguous(), loss_b, prior=prior[il].contiguous(),
+                 shift=shift[il].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(loss_a, loss_b)
+    assert torch.equal(ga, net.grads)
+
+
 def test_adam_step_matches_formula():
     net = _net(seed=2)
     scenes = sc.batched_uniform(32, seed=10)
