@@ -365,7 +365,9 @@ int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, 
  * the search stops when lambda_2 has moved by at most 1e-13 (1 + |lambda_2|)
  * and |lambda_3| by at most 1e-11 (1 + |lambda_2|) in two successive steps; max_steps also caps
  * the steps of this search (DTM_SPECTRAL_UNSETTLED when reached).  Uses the
- * factored operator (O(n) per step per vector).  The mixing search advances
+ * factored operator (O(n) per step per vector).  The mixing search runs on
+ * the plan's second stream beside the lambda_2 search, both after pi, and is
+ * joined back into `stream` before the call returns.  It advances
  * every start state: for plans whose pixels have at most 1024 bins on chip
  * (the call then only launches); above that in the scratch (2 n^2 float64
  * per pixel), and the call then copies the per-pixel scratch offsets from

@@ -773,12 +773,33 @@ __device__ inline double start_pattern(int i, int j) {
 // annihilates (its orthogonalised norm below 1e-14 of its norm) stays zero.
 // IN_LDS: the NVEC vectors live in LDS (n <= kSpecLdsMaxN); g, 1/S and pi
 // are copied to the workspace at the end for the mixing search.
+// First stage of the spectral analysis, one block per pixel: the float64
+// tables and pi (power iteration on the factored product) into the scratch,
+// c = e^{-Lambda} into scal_out, and the pixel's mixing steps set to -1 (the
+// mixing search merges its result into them).  The subspace search and the
+// mixing search both start from these and run side by side.
+__global__ __launch_bounds__(BT) void k_spectral_pi(const PixelMeta* __restrict__ metas,
+                                                    double* __restrict__ fact, int64_t vec_elems,
+                                                    double* __restrict__ scal_out,
+                                                    dtm_spectral_info* __restrict__ out, KOpts o) {
+  __shared__ double red[3 * BT / kWave];
+  const PixelMeta m = metas[blockIdx.x];
+  const Vecs V = vecs(fact, vec_elems, m);
+  const double c = tables(m, V, red);
+  power<double>(m, V, c, static_cast<const double*>(nullptr), o, red);  // pi -> V.x
+  if (threadIdx.x == 0) {
+    scal_out[blockIdx.x] = c;
+    out[m.index].mixing_steps = -1;
+  }
+}
+
+// The lambda_2 search, from the tables, pi and c of k_spectral_pi.  Writes
+// every field of the pixel's report but mixing_steps.
 template <bool IN_LDS>
 __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ metas,
                                                  double* __restrict__ fact, int64_t vec_elems,
-                                                 double* __restrict__ scal_out,
-                                                 dtm_spectral_info* __restrict__ out, KOpts o,
-                                                 int max_iter) {
+                                                 const double* __restrict__ scal,
+                                                 dtm_spectral_info* __restrict__ out, int max_iter) {
   __shared__ double red[KSUB * KSUB * BT / kWave];
   __shared__ double hs[KSUB * KSUB], har[KSUB * KSUB], hai[KSUB * KSUB], er[KSUB], ei[KSUB];
   __shared__ int eig_ok;
@@ -805,11 +826,17 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
       W[i] = base + (5 + KSUB + i) * stride;
     }
   }
-  const double c = tables(m, V, red);
-  if (threadIdx.x == 0) scal_out[blockIdx.x] = c;
-  power<double>(m, V, c, static_cast<const double*>(nullptr), o, red);  // pi -> V.x
+  const double c = scal[blockIdx.x];
   int j0, j1;
   chunk_of(n, j0, j1);
+  if constexpr (IN_LDS) {
+    for (int j = j0; j < j1; ++j) {
+      V.g[j] = G.g[j];
+      V.invs[j] = G.invs[j];
+      V.x[j] = G.x[j];
+    }
+    __syncthreads();
+  }
   const int ke = min(KSUB, n - 1);
   {
     double sums[KSUB];
@@ -938,15 +965,9 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
   if (settled < 2) flags |= DTM_SPECTRAL_UNSETTLED;
   if (!all_ok) flags |= DTM_SPECTRAL_UNSETTLED;
   if (l3 >= (1.0 - 1e-9) * hypot(re, im) && l3 > 0.0) flags |= DTM_SPECTRAL_TIED;
-  if constexpr (IN_LDS) {
-    for (int j = j0; j < j1; ++j) {
-      G.g[j] = V.g[j];
-      G.invs[j] = V.invs[j];
-      G.x[j] = V.x[j];
-    }
-  }
   if (threadIdx.x == 0) {
-    dtm_spectral_info si;
+    // field by field: the mixing search may be merging into mixing_steps
+    dtm_spectral_info& si = out[m.index];
     si.lambda2_re = re;
     si.lambda2_im = im;
     si.lambda2_abs = hypot(re, im);
@@ -954,10 +975,8 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
     si.lambda3_abs = l3;
     si.ritz_change = change;
     si.iterations = min(it + 1, max_iter);
-    si.mixing_steps = -1;
     si.flags = flags;
     si.reserved = 0;
-    out[m.index] = si;
   }
 }
 
@@ -971,7 +990,7 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
 // the largest over its states of the first step within eps: each block stops
 // when all its states are within eps and merges its step by atomicMax (a
 // block that runs out of steps posts max_steps + 1, read as "not reached").
-// Requires the tables and pi in V and mixing_steps = -1 (from k_spectral).
+// Requires the tables and pi in V and mixing_steps = -1 (from k_spectral_pi).
 __global__ __launch_bounds__(BT) void k_mixing(const PixelMeta* __restrict__ metas,
                                                double* __restrict__ fact, int64_t vec_elems,
                                                double* __restrict__ mix, const int64_t* __restrict__ mix_off,
@@ -1265,21 +1284,40 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
   o.safety = 1.0;
   o.stop_rule = DTM_STOP_BOUND;
   o.pad = 0;
+  if (with_mix && static_cast<double>(plan->n_pixels) * ((plan->max_n + 3) / 4) >= 2147483647.0)
+    return DTM_EINVAL;
+  hipLaunchKernelGGL(fact::k_spectral_pi, dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas, fact, plan->vec_elems,
+                     scal, out_dev, o);
+  if (hipGetLastError() != hipSuccess) return DTM_EHIP;
+  // the lambda_2 search on the caller's stream and the mixing search on the
+  // plan's second stream, side by side (the search keeps one workgroup per
+  // pixel busy for its whole run; the mixing workgroups fill the rest)
+  hipStream_t mst = st;
+  if (with_mix) {
+    mst = static_cast<hipStream_t>(plan->aux_stream);
+    if (hipEventRecord(static_cast<hipEvent_t>(plan->ev_fork), st) != hipSuccess ||
+        hipStreamWaitEvent(mst, static_cast<hipEvent_t>(plan->ev_fork), 0) != hipSuccess)
+      return DTM_EHIP;
+  }
   if (plan->max_n <= fact::kSpecLdsMaxN) {
     const size_t lds = fact::NVEC * sizeof(double) * static_cast<size_t>(plan->max_n);
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(fact::k_spectral<true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
       return DTM_EHIP;
     hipLaunchKernelGGL(fact::k_spectral<true>, dim3(plan->n_pixels), dim3(fact::BT), lds, st, metas, fact,
-                       plan->vec_elems, scal, out_dev, o, max_steps);
+                       plan->vec_elems, scal, out_dev, max_steps);
   } else {
     hipLaunchKernelGGL(fact::k_spectral<false>, dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas, fact,
-                       plan->vec_elems, scal, out_dev, o, max_steps);
+                       plan->vec_elems, scal, out_dev, max_steps);
   }
   if (hipGetLastError() != hipSuccess) return DTM_EHIP;
   if (!with_mix) return DTM_OK;
-  // k_spectral left g, 1/S, pi and c in the scratch
-  if (static_cast<double>(plan->n_pixels) * ((plan->max_n + 3) / 4) >= 2147483647.0) return DTM_EINVAL;
+  const auto join = [&]() {
+    if (hipEventRecord(static_cast<hipEvent_t>(plan->ev_join), mst) != hipSuccess ||
+        hipStreamWaitEvent(st, static_cast<hipEvent_t>(plan->ev_join), 0) != hipSuccess)
+      return DTM_EHIP;
+    return DTM_OK;
+  };
   if (plan->max_n <= 1024) {
     // one wavefront per start state, four per block; E bins per lane
     const int E = plan->max_n <= 256 ? 4 : plan->max_n <= 512 ? 8 : 16;
@@ -1287,18 +1325,19 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
     const dim3 grid(static_cast<unsigned>(plan->n_pixels) * static_cast<unsigned>(sb));
     const size_t lds = sizeof(double) * 4 * kWave * (E + 1);
     if (E == 4)
-      hipLaunchKernelGGL(fact::k_mixing_wave<4>, grid, dim3(fact::BT), lds, st, metas, fact, plan->vec_elems, scal,
+      hipLaunchKernelGGL(fact::k_mixing_wave<4>, grid, dim3(fact::BT), lds, mst, metas, fact, plan->vec_elems, scal,
                          out_dev, mixing_eps, max_steps, sb);
     else if (E == 8)
-      hipLaunchKernelGGL(fact::k_mixing_wave<8>, grid, dim3(fact::BT), lds, st, metas, fact, plan->vec_elems, scal,
+      hipLaunchKernelGGL(fact::k_mixing_wave<8>, grid, dim3(fact::BT), lds, mst, metas, fact, plan->vec_elems, scal,
                          out_dev, mixing_eps, max_steps, sb);
     else
-      hipLaunchKernelGGL(fact::k_mixing_wave<16>, grid, dim3(fact::BT), lds, st, metas, fact, plan->vec_elems,
+      hipLaunchKernelGGL(fact::k_mixing_wave<16>, grid, dim3(fact::BT), lds, mst, metas, fact, plan->vec_elems,
                          scal, out_dev, mixing_eps, max_steps, sb);
     if (hipGetLastError() != hipSuccess) return DTM_EHIP;
-    hipLaunchKernelGGL(fact::k_mixing_final, dim3((plan->n_pixels + fact::BT - 1) / fact::BT), dim3(fact::BT), 0, st,
-                       metas, plan->n_pixels, out_dev, max_steps);
-    return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP;
+    hipLaunchKernelGGL(fact::k_mixing_final, dim3((plan->n_pixels + fact::BT - 1) / fact::BT), dim3(fact::BT), 0,
+                       mst, metas, plan->n_pixels, out_dev, max_steps);
+    if (hipGetLastError() != hipSuccess) return DTM_EHIP;
+    return join();
   }
   // larger pixels: the n x n blocks of start-state distributions live in the
   // scratch, at per-pixel offsets copied from the host
@@ -1311,19 +1350,21 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
   double* mixbuf = reinterpret_cast<double*>(s + off);
   off += align256(8 * mix);
   int64_t* mix_off = reinterpret_cast<int64_t*>(s + off);
-  if (hipMemcpyAsync(mix_off, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice, st) !=
+  if (hipMemcpyAsync(mix_off, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice, mst) !=
       hipSuccess)
     return DTM_EHIP;
   {
     const int sb = (plan->max_n + fact::BT - 1) / fact::BT;
     hipLaunchKernelGGL(fact::k_mixing, dim3(static_cast<unsigned>(plan->n_pixels) * static_cast<unsigned>(sb)),
-                       dim3(fact::BT), 0, st, metas, fact, plan->vec_elems, mixbuf, mix_off, scal, out_dev,
+                       dim3(fact::BT), 0, mst, metas, fact, plan->vec_elems, mixbuf, mix_off, scal, out_dev,
                        mixing_eps, max_steps, sb);
   }
   if (hipGetLastError() != hipSuccess) return DTM_EHIP;
-  hipLaunchKernelGGL(fact::k_mixing_final, dim3((plan->n_pixels + fact::BT - 1) / fact::BT), dim3(fact::BT), 0, st,
+  hipLaunchKernelGGL(fact::k_mixing_final, dim3((plan->n_pixels + fact::BT - 1) / fact::BT), dim3(fact::BT), 0, mst,
                      metas, plan->n_pixels, out_dev, max_steps);
   if (hipGetLastError() != hipSuccess) return DTM_EHIP;
+  const int rc = join();
+  if (rc) return rc;
   // the offsets must outlive the asynchronous copy
   if (hipStreamSynchronize(st) != hipSuccess) return DTM_EHIP;
   return DTM_OK;
