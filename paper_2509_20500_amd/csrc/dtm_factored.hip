@@ -299,11 +299,22 @@ constexpr size_t lds_doubles() {
   return static_cast<size_t>(kWave) * (E + 1);
 }
 
-template <typename T, int E>
+// Where the spectral analysis wants a pixel's float64 tables and pi (the
+// vectors g, 1/S and x of its scratch, c per pixel) and its mixing steps
+// reset: set for the first stage of dtm_spectral_batched, null otherwise.
+struct SpecOut {
+  double* fact;
+  int64_t vec_elems;
+  double* scal;
+  dtm_spectral_info* out;
+};
+
+template <typename T, int E, bool SPEC = false>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void k_solve_factored_wave(const PixelMeta* __restrict__ metas, int n_pixels,
                                                             const T* __restrict__ x0_packed,
                                                             T* __restrict__ pi_packed,
-                                                            dtm_solve_info* __restrict__ infos, KOpts o) {
+                                                            dtm_solve_info* __restrict__ infos, KOpts o,
+                                                            SpecOut so) {
   extern __shared__ double lds_x[];
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int p = blockIdx.x * (BT / kWave) + wid;
@@ -501,10 +512,26 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     sync_wave();  // the new iterate is in xs before the next shifted reads
     if (st.done) break;
   }
+  if constexpr (SPEC) {
+    // the spectral analysis' first stage: tables and pi into its scratch
+    double* base = so.fact + m.vec_off;
 #pragma unroll
-  for (int e = 0; e < E; ++e)
-    if (j0 + e < n) pi_packed[m.pi_off + j0 + e] = static_cast<T>(xo[e]);
-  if (lane == 0) infos[m.index] = make_info(st);
+    for (int e = 0; e < E; ++e)
+      if (j0 + e < n) {
+        base[j0 + e] = g[e];
+        base[so.vec_elems + j0 + e] = inv[e];
+        base[2 * so.vec_elems + j0 + e] = xo[e];
+      }
+    if (lane == 0) {
+      so.scal[p] = c;
+      so.out[m.index].mixing_steps = -1;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (j0 + e < n) pi_packed[m.pi_off + j0 + e] = static_cast<T>(xo[e]);
+    if (lane == 0) infos[m.index] = make_info(st);
+  }
 }
 
 }  // namespace wave
@@ -1203,15 +1230,15 @@ int dtm_solve_factored_batched(const dtm_plan* plan, const void* x0_packed_dev, 
     if (plan->dt == DTM_F32) {
       const float* x0 = static_cast<const float*>(x0_packed_dev);
       float* pi = static_cast<float*>(pi_packed_dev);
-      if (E == 4) hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<float, 4>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o);
-      else if (E == 8) hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<float, 8>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o);
-      else hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<float, 16>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o);
+      if (E == 4) hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<float, 4>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o, fact::wave::SpecOut{});
+      else if (E == 8) hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<float, 8>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o, fact::wave::SpecOut{});
+      else hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<float, 16>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o, fact::wave::SpecOut{});
     } else {
       const double* x0 = static_cast<const double*>(x0_packed_dev);
       double* pi = static_cast<double*>(pi_packed_dev);
-      if (E == 4) hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<double, 4>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o);
-      else if (E == 8) hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<double, 8>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o);
-      else hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<double, 16>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o);
+      if (E == 4) hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<double, 4>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o, fact::wave::SpecOut{});
+      else if (E == 8) hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<double, 8>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o, fact::wave::SpecOut{});
+      else hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<double, 16>), grid, block, lds, st, metas, plan->n_pixels, x0, pi, infos_dev, o, fact::wave::SpecOut{});
     }
     return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP;
   }
@@ -1286,8 +1313,36 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
   o.pad = 0;
   if (with_mix && static_cast<double>(plan->n_pixels) * ((plan->max_n + 3) / 4) >= 2147483647.0)
     return DTM_EINVAL;
-  hipLaunchKernelGGL(fact::k_spectral_pi, dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas, fact, plan->vec_elems,
-                     scal, out_dev, o);
+  if (plan->max_n <= 1024) {
+    // tables and pi by the factored solver's wavefront kernel (one
+    // wavefront per pixel, E bins per lane), which then writes them to the
+    // scratch instead of returning pi
+    const int E = plan->max_n <= 256 ? 4 : plan->max_n <= 512 ? 8 : 16;
+    const dim3 grid((plan->n_pixels + 3) / 4), block(fact::BT);
+    const size_t lds = sizeof(double) * 4 * 2 * kWave * (E + 1);
+    const fact::wave::SpecOut so{fact, plan->vec_elems, scal, out_dev};
+    const void* kern = E == 4 ? reinterpret_cast<const void*>(fact::wave::k_solve_factored_wave<double, 4, true>)
+                       : E == 8 ? reinterpret_cast<const void*>(fact::wave::k_solve_factored_wave<double, 8, true>)
+                                : reinterpret_cast<const void*>(fact::wave::k_solve_factored_wave<double, 16, true>);
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+      return DTM_EHIP;
+    if (E == 4)
+      hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<double, 4, true>), grid, block, lds, st, metas,
+                         plan->n_pixels, static_cast<const double*>(nullptr), static_cast<double*>(nullptr),
+                         static_cast<dtm_solve_info*>(nullptr), o, so);
+    else if (E == 8)
+      hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<double, 8, true>), grid, block, lds, st, metas,
+                         plan->n_pixels, static_cast<const double*>(nullptr), static_cast<double*>(nullptr),
+                         static_cast<dtm_solve_info*>(nullptr), o, so);
+    else
+      hipLaunchKernelGGL((fact::wave::k_solve_factored_wave<double, 16, true>), grid, block, lds, st, metas,
+                         plan->n_pixels, static_cast<const double*>(nullptr), static_cast<double*>(nullptr),
+                         static_cast<dtm_solve_info*>(nullptr), o, so);
+  } else {
+    hipLaunchKernelGGL(fact::k_spectral_pi, dim3(plan->n_pixels), dim3(fact::BT), 0, st, metas, fact,
+                       plan->vec_elems, scal, out_dev, o);
+  }
   if (hipGetLastError() != hipSuccess) return DTM_EHIP;
   // the lambda_2 search on the caller's stream and the mixing search on the
   // plan's second stream, side by side (the search keeps one workgroup per
