@@ -24,6 +24,9 @@ constexpr int KSUB = 6;  // dimension of the subspace that the lambda_2 search i
 // float64 vectors of ld per pixel in the spectral scratch: the solver's five
 // (g, 1/S, pi, u, last difference), then the subspace basis Q and its image W
 constexpr int NVEC = 5 + 2 * KSUB;
+// of which the lambda_2 search keeps g, 1/S, pi and the basis and its image
+// in LDS (n <= kSpecLdsMaxN)
+constexpr int NVEC_LDS = 3 + 2 * KSUB;
 constexpr int kSpecLdsMaxN = 1024;  // largest n whose spectral vectors are kept in LDS
 
 // Chunk of bins owned by this thread (the layout of pixel_tables).
@@ -784,22 +787,6 @@ __device__ inline double start_pattern(int i, int j) {
   return 1.0 + 0.5 * sin((0.7 + 0.37 * i) * j + 0.3 * i) + ((j * 7919 + i * 104729) % 13) * 0.01;
 }
 
-// lambda_2 of the dead-time matrix (Section 4): orthogonal iteration on the
-// deflated operator A v = v P~ - (v . 1) pi with a KSUB-dimensional subspace
-// (min(KSUB, n - 1) vectors), each step
-//   Q = orthonormal basis of W (classical Gram-Schmidt, two passes),
-//   W = A Q,  H = Q^T W  (the Rayleigh quotient of the subspace),
-// whose eigenvalues (Ritz values) approach the KSUB eigenvalues of largest
-// modulus of A, i.e. lambda_2, lambda_3, ... of P~: the one of largest
-// modulus converges at the rate |lambda_{KSUB+2} / lambda_2| per step, so
-// eigenvalues close to lambda_2 in modulus (a near-tie with lambda_3) do not
-// slow it.  The Rayleigh-Ritz step is taken every eighth step until two of
-// them agree to 1e-9, then every step; the search stops when lambda_2 has
-// changed by at most 1e-13 (1 + |lambda_2|) and the next modulus by at most
-// 1e-11 (1 + |lambda_2|) in two successive steps, or after max_iter steps.  A basis vector that A
-// annihilates (its orthogonalised norm below 1e-14 of its norm) stays zero.
-// IN_LDS: the NVEC vectors live in LDS (n <= kSpecLdsMaxN); g, 1/S and pi
-// are copied to the workspace at the end for the mixing search.
 // First stage of the spectral analysis, one block per pixel: the float64
 // tables and pi (power iteration on the factored product) into the scratch,
 // c = e^{-Lambda} into scal_out, and the pixel's mixing steps set to -1 (the
@@ -820,8 +807,24 @@ __global__ __launch_bounds__(BT) void k_spectral_pi(const PixelMeta* __restrict_
   }
 }
 
-// The lambda_2 search, from the tables, pi and c of k_spectral_pi.  Writes
-// every field of the pixel's report but mixing_steps.
+// lambda_2 of the dead-time matrix (Section 4): orthogonal iteration on the
+// deflated operator A v = v P~ - (v . 1) pi with a KSUB-dimensional subspace
+// (min(KSUB, n - 1) vectors), each step
+//   Q = orthonormal basis of W (classical Gram-Schmidt, two passes),
+//   W = A Q,  H = Q^T W  (the Rayleigh quotient of the subspace),
+// whose eigenvalues (Ritz values) approach the KSUB eigenvalues of largest
+// modulus of A, i.e. lambda_2, lambda_3, ... of P~: the one of largest
+// modulus converges at the rate |lambda_{KSUB+2} / lambda_2| per step, so
+// eigenvalues close to lambda_2 in modulus (a near-tie with lambda_3) do not
+// slow it.  The Rayleigh-Ritz step is taken every eighth step until two of
+// them agree to 1e-9, then every step; the search stops when lambda_2 has
+// changed by at most 1e-13 (1 + |lambda_2|) and the next modulus by at most
+// 1e-11 (1 + |lambda_2|) in two successive steps, or after max_iter steps.  A basis vector that A
+// annihilates (its orthogonalised norm below 1e-14 of its norm) stays zero.
+// Starts from the tables, pi and c of the first stage (k_spectral_pi, or the
+// wavefront solver up to 1024 bins); writes every field of the pixel's
+// report but mixing_steps.  IN_LDS: g, 1/S, pi and the 2 KSUB subspace
+// vectors live in LDS (n <= kSpecLdsMaxN).
 template <bool IN_LDS>
 __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ metas,
                                                  double* __restrict__ fact, int64_t vec_elems,
@@ -840,17 +843,18 @@ __global__ __launch_bounds__(BT) void k_spectral(const PixelMeta* __restrict__ m
   {
     double* base = IN_LDS ? lds_vec : fact + m.vec_off;
     const int64_t stride = IN_LDS ? static_cast<int64_t>(n) : vec_elems;
+    // the search uses g, 1/S and pi of the solver's five vectors
+    const int first = IN_LDS ? 3 : 5;
     if constexpr (IN_LDS) {
       V.g = base;
       V.invs = base + stride;
       V.x = base + 2 * stride;
-      V.u = base + 3 * stride;
-      V.dp = base + 4 * stride;
+      V.u = V.dp = nullptr;
     }
 #pragma unroll
     for (int i = 0; i < KSUB; ++i) {
-      Q[i] = base + (5 + i) * stride;
-      W[i] = base + (5 + KSUB + i) * stride;
+      Q[i] = base + (first + i) * stride;
+      W[i] = base + (first + KSUB + i) * stride;
     }
   }
   const double c = scal[blockIdx.x];
@@ -1355,7 +1359,9 @@ int dtm_spectral_batched(const dtm_plan* plan, double mixing_eps, int32_t max_st
       return DTM_EHIP;
   }
   if (plan->max_n <= fact::kSpecLdsMaxN) {
-    const size_t lds = fact::NVEC * sizeof(double) * static_cast<size_t>(plan->max_n);
+    // 15 vectors of 1024 bins (120 KB) leave room on the CU for a
+    // workgroup of the mixing search running beside it
+    const size_t lds = fact::NVEC_LDS * sizeof(double) * static_cast<size_t>(plan->max_n);
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(fact::k_spectral<true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
       return DTM_EHIP;
