@@ -123,6 +123,24 @@ def batched_uneven(n_pixels=2048, seed=4, sizes=UNEVEN_SIZES, weights=UNEVEN_WEI
     return make_scenes(period, td, tau, sigma, sig, bg, n)
 
 
+def stress_n1024(n_pixels=2048, seed=7):
+    """Wide parameter draws at N=1024 over 100 ns, for every-pixel stop-rule
+    checks: dead time 100 ns x U[0, 3] with a quarter of the draws within
+    2 % of a whole number of periods (the nearly periodic, slowly mixing
+    chains), sigma U[0.1, 2] ns, depth U[5, 95], S log-uniform [0.01, 10],
+    B log-uniform [0.001, 10]."""
+    rng = np.random.default_rng(seed)
+    td = 100.0 * rng.uniform(0.0, 3.0, n_pixels)
+    near = rng.uniform(size=n_pixels) < 0.25
+    whole = rng.integers(1, 3, n_pixels) + rng.uniform(-0.02, 0.02, n_pixels)
+    td = np.where(near, 100.0 * whole, td)
+    sigma = rng.uniform(0.1, 2.0, n_pixels)
+    tau = rng.uniform(5.0, 95.0, n_pixels)
+    sig = _log_uniform(rng, 0.01, 10.0, n_pixels)
+    bg = _log_uniform(rng, 0.001, 10.0, n_pixels)
+    return make_scenes(100.0, td, tau, sigma, sig, bg, 1024)
+
+
 def warm_start_train(n_pixels=200_000, seed=5):
     return batched_uniform(n_pixels=n_pixels, seed=seed)
 

@@ -14,6 +14,9 @@
   every pixel above 2048 bins (the banded launches) against float64 power
   iteration with the O(n) factorised product of the same matrix, started
   from the uniform vector.
+* 2048 wide parameter draws at N = 1024 (dead time up to three periods,
+  a quarter within 2 % of a whole number of periods, S and B log-uniform
+  up to 10), float32 from both starts: all pixels.
 
 The oracle runs in a pool of host-core processes (``oracle.pool``).
 """
@@ -67,6 +70,24 @@ def test_section4_grid_every_pixel():
     worst = int(np.argmax(l1))
     print(f"Section 4 grid: max L1 {l1.max():.3e} (pixel {worst}), max sweeps "
           f"{info['iterations'].max()}, refined {int(np.sum(info['flags'] & 0x10 != 0))}", flush=True)
+    assert l1.max() <= TOL_F32, (worst, scenes[worst], l1[worst], info[worst])
+
+
+@pytest.mark.parametrize("flux", [True, False])
+def test_wide_scene_draws_every_pixel(flux):
+    """2048 wide draws at N = 1024 (dead times up to three periods, a
+    quarter of them within 2 % of a whole number of periods, S up to 10 and
+    B up to 10 photons per period): whatever the stop rule accepted, float32
+    from the flux start and from uniform, is within 1e-6 of the oracle."""
+    d = lib()
+    scenes = sc.stress_n1024()
+    pi, info, off = run_batched(scenes, "f32", solve_opts=_opts(flux))
+    assert np.all(info["status"] == 0), info[info["status"] != 0]
+    l1 = opool.l1_many(scenes, split(pi, off))
+    worst = int(np.argmax(l1))
+    print(f"wide draws ({'flux' if flux else 'uniform'} start): max L1 {l1.max():.3e} (pixel {worst}), "
+          f"sweeps mean {info['iterations'].mean():.2f} max {info['iterations'].max()}, "
+          f"{int(np.sum((info['flags'] & d.DTM_INFO_CONTINUED) != 0))} continued", flush=True)
     assert l1.max() <= TOL_F32, (worst, scenes[worst], l1[worst], info[worst])
 
 
