@@ -837,7 +837,7 @@ def warm_start_workload(args):
     start_l1 = float(np.mean([np.abs(x0n[off[p]:off[p + 1]] - pu[off[p]:off[p + 1]]).sum()
                               for p in range(len(held))]))
     n = held["n_bins"].astype(np.float64)
-    alg_w = float(np.sum(4 * n * n * iw["iterations"]))
+    alg_w = float(np.sum(4 * n * n * iw["dense_sweeps"]))
     fallbacks = int(np.sum((iw["flags"] & (dtm.DTM_INFO_RESTARTED | dtm.DTM_INFO_WARM_REJECTED)) != 0))
 
     def start_report(ms, info, key):
@@ -911,6 +911,9 @@ def main():
                     help="persistent workgroups of the one-block sweeps (0 = one per pixel)")
     ap.add_argument("--dense-sweeps", type=int, default=0,
                     help="sweeps of a pixel's dense matrix before the float64 continuation (0 = default)")
+    ap.add_argument("--band-min-items", type=int, default=0,
+                    help="banded sweeps stop, and their pixels continue in float64, once fewer work items "
+                         "than this are left (0 = never)")
     ap.add_argument("--variant", default="paper",
                     choices=["paper", "nearest", "bin_mean", "bin_integral", "interp"],
                     help="discretisation of the model (interp needs --solver factored)")
@@ -947,9 +950,9 @@ def main():
     sopts = dtm.opts(tol=1e-6)
     tune_report = None
     if (args.threads or args.unroll or args.band_rows or args.band_cpt or args.fused_max_bins or args.dense_sweeps
-            or args.independent_paths or args.fused_blocks):
+            or args.independent_paths or args.fused_blocks or args.band_min_items):
         tiles = dtm.tiles(args.threads, args.unroll, args.fused_max_bins, args.band_rows, args.dense_sweeps,
-                          args.band_cpt, args.independent_paths, args.fused_blocks)
+                          args.band_cpt, args.independent_paths, args.fused_blocks, args.band_min_items)
     elif args.autotune:
         from paper_2509_20500_amd.autotune import autotune
         tiles, tune_report = autotune(scenes, args.dtype, sopts)
@@ -1000,10 +1003,10 @@ def main():
     es = 4 if args.dtype == "f32" else 8
     # algorithmic bytes: each matrix written once; every sweep after the
     # first (taken while the matrix is built) reads it once.  A pixel
-    # continued in float64 past its dense sweeps reads its matrix only in
-    # those sweeps (the continuation uses the factored product)
-    dense_passes = np.where((info["flags"] & dtm.DTM_INFO_CONTINUED) != 0,
-                            np.minimum(info["iterations"], plan.tiles.dense_sweeps), info["iterations"])
+    # continued (or refined) in float64 reads its matrix only in the sweeps
+    # before (the float64 sweeps regenerate it from its tables): the
+    # report's dense_sweeps
+    dense_passes = info["dense_sweeps"]
     alg_bytes = float(np.sum(es * n * n * dense_passes))
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     value = plan.n_pixels / (ms_step * 1e-3)
@@ -1151,7 +1154,7 @@ def main():
     if not uneven and not factored and not graph and plan.n_pixels == 4096:
         # the same access pattern without arithmetic, for reading the roofline
         pc = pattern_ceiling(plan.n_pixels, 4 * 1024 * 1024 if args.dtype == "f32" else 8 * 1024 * 1024,
-                             float(info["iterations"].mean()) - 1.0)
+                             float(info["dense_sweeps"].mean()) - 1.0)
         pc["kernel_frac_of_pattern"] = achieved / pc["gbs"]
         out["pattern_ceiling"] = pc
     if args.calibrate:

@@ -163,7 +163,10 @@ typedef struct dtm_solve_info {
   int32_t iterations;  /* sweeps performed (each reads the matrix once)         */
   int32_t status;
   int32_t flags;       /* DTM_INFO_*                                            */
-  int32_t reserved;
+  int32_t dense_sweeps; /* sweeps that read the pixel's stored matrix: iterations,
+                           less the float64 sweeps of a DTM_INFO_CONTINUED or
+                           DTM_INFO_REFINED pixel (which regenerate the matrix
+                           from its tables); 0 from the factored solver        */
   double change_l1;    /* ||x_T - x_{T-1}||_1 of the last iterate             */
   double residual_l1;  /* ||x P~ - x||_1 of the input of the last sweep        */
   double rho_hat;      /* estimate of |lambda_2| from successive changes       */
@@ -286,6 +289,12 @@ typedef struct dtm_tile_config {
                               persistent workgroups, each taking the next pixel in
                               launch order from a counter (so the banded launches of
                               a mixed plan keep the CUs the k workgroups leave)         */
+  int32_t band_min_items;  /* banded path: once the pixels still running after a sweep
+                              have fewer than this many work items (row band x column
+                              block) in all, the remaining banded sweeps do nothing
+                              and those pixels continue in float64 as after
+                              dense_sweeps (DTM_INFO_CONTINUED): a sweep of so few
+                              items cannot keep HBM busy.  0 = never (>= 0)            */
 } dtm_tile_config;
 
 typedef struct dtm_plan dtm_plan; /* opaque host object */

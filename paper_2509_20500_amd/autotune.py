@@ -2,7 +2,9 @@
 
 Times candidate ``dtm_tile_config`` values on the caller's own scenes (all
 of them, or a fixed sample) through the C-ABI and keeps the fastest one that
-solves every pixel.  Results are cached as JSON, keyed by the device name,
+solves every pixel: first a grid of the one-block and banded launch shapes,
+then, for plans with banded pixels, the banded sweep's column vectors per
+thread and its hand-off threshold around the best of the grid.  Results are cached as JSON, keyed by the device name,
 the dtype, the solver options and the histogram of bin counts, so a workload
 is tuned once per machine.
 """
@@ -25,7 +27,7 @@ def _key(scenes, dtype, solve_opts, device_name):
     o = solve_opts or dtm.opts()
     raw = json.dumps({"dev": device_name, "dt": dtype, "n": n.tolist(), "c": cnt.tolist(),
                       "tol": o.tol_l1, "safety": o.safety, "max_iter": o.max_iter,
-                      "rule": o.stop_rule, "flags": o.flags})
+                      "rule": o.stop_rule, "flags": o.flags, "search": 2})
     return hashlib.sha1(raw.encode()).hexdigest()
 
 
@@ -38,8 +40,9 @@ def candidates(scenes):
     # fused_blocks: 0 = one workgroup per one-block pixel, 96 or 128 =
     # persistent workgroups (only differs when banded pixels share the plan)
     n_min = int(np.min(scenes["n_bins"]))
-    for threads, unroll, fmax, band, cpt, dense, blocks in itertools.product(
-            (256, 512), (4, 8), (1024, 2048, 4096), (1024, 8192), (1, 4), (0, 12), (0, 96, 128)):
+    cpt = 1  # the banded stage varies it
+    for threads, unroll, fmax, band, dense, blocks in itertools.product(
+            (256, 512), (4, 8), (1024, 2048, 4096), (1024, 8192), (0, 12), (0, 96, 128)):
         eff_fmax = min(fmax, n_max)
         big = n_max > fmax
         mixed = big and n_min <= fmax
@@ -50,6 +53,20 @@ def candidates(scenes):
         out.append(dtm.tiles(fused_threads=threads, fused_unroll=unroll, fused_max_bins=fmax,
                              band_rows=band, band_cpt=cpt, dense_sweeps=dense,
                              fused_blocks=blocks if mixed else 0))
+    return out
+
+
+def banded_candidates(scenes, best):
+    """Second stage, for plans with banded pixels: column vectors per thread
+    of the banded sweep (1, 2, 4) and the hand-off threshold band_min_items
+    (0 = never; 128 or 256 work items, below which a sweep's items cannot keep
+    HBM busy), around the best first-stage shape."""
+    if int(np.max(scenes["n_bins"])) <= best.fused_max_bins:
+        return []
+    out = []
+    for cpt, mi in itertools.product((1, 2, 4), (0, 128, 256)):
+        if (cpt, mi) != (best.band_cpt, best.band_min_items):
+            out.append(dtm.tiles(**{**best.as_dict(), "band_cpt": cpt, "band_min_items": mi}))
     return out
 
 
@@ -104,16 +121,32 @@ def autotune(scenes, dtype, solve_opts=None, cache_path=DEFAULT_CACHE, reps=3, v
         p.close()
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     results = []
-    for t in cands:
-        ms, _ = time_config(scenes, dtype, solve_opts, t, ws, reps)
-        results.append((ms, t.as_dict()))
-        if verbose:
-            print("autotune", t.as_dict(), ms, flush=True)
+
+    def run(cs):
+        for t in cs:
+            ms, _ = time_config(scenes, dtype, solve_opts, t, ws, reps)
+            results.append((ms, t.as_dict()))
+            if verbose:
+                print("autotune", t.as_dict(), ms, flush=True)
+
+    def best_of():
+        ok = [r for r in results if r[0] is not None]
+        if not ok:
+            raise RuntimeError("autotune: no candidate solved every pixel")
+        return min(ok, key=lambda r: r[0])
+
+    run(cands)
+    second = banded_candidates(scenes, dtm.tiles(**best_of()[1]))
+    if second:
+        p = dtm.Plan(scenes, dtype, solve_opts, second[0])
+        extra = p.workspace_bytes
+        p.close()
+        if extra > ws.numel():  # the hand-off counters do not change the size; column chunks may
+            del ws
+            ws = torch.empty(extra, dtype=torch.uint8, device="cuda")
+        run(second)
     del ws
-    ok = [r for r in results if r[0] is not None]
-    if not ok:
-        raise RuntimeError("autotune: no candidate solved every pixel")
-    best_ms, best = min(ok, key=lambda r: r[0])
+    best_ms, best = best_of()
     entry = {"tiles": best, "ms": best_ms, "device": dev,
              "tried": [{"tiles": t, "ms": ms} for ms, t in results]}
     if cache_path:

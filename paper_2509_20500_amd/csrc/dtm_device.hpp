@@ -392,7 +392,7 @@ __device__ inline dtm_solve_info make_info(const StopState& s) {
   info.iterations = s.total_iter;
   info.status = s.status;
   info.flags = s.flags;
-  info.reserved = 0;
+  info.dense_sweeps = s.total_iter;
   info.change_l1 = s.c1;
   info.residual_l1 = s.resid;
   info.rho_hat = s.rho;

@@ -213,7 +213,164 @@ __global__ __launch_bounds__(BT) void k_dense_tail(const PixelMeta* __restrict__
   }
   st.flags |= DTM_INFO_CONTINUED;
   if (threadIdx.x == 0) {
-    infos[m.index] = make_info(st);
+    dtm_solve_info info = make_info(st);
+    info.dense_sweeps = prev.total_iter;
+    infos[m.index] = info;
+    states[q].s = st;
+  }
+}
+
+// k_dense_tail for pixels of at most 512 E bins, by 512 threads: thread t
+// owns the ch = ceil(n / 512) bins from t ch on, and keeps their iterate,
+// product and last difference in registers, and g and 1/S too for E <= 8
+// (above, they are read from the workspace in every sweep: registers would
+// spill); only the iterate also goes to LDS (one pad slot after every E bins, so the lanes' strided reads
+// spread over the banks), for the shifted reads of the next product.  A sweep
+// is one LDS pass, one block scan and two block sums, against six passes over
+// global vectors in k_dense_tail.  Same steps, start and stop rule; sums in
+// 8 waves instead of 4, so the last bits may differ.
+constexpr int BTT = 512;
+
+template <int E>
+__device__ inline int tail_slot(int j) {
+  return j + j / E;
+}
+
+template <int E>
+constexpr size_t tail_lds_bytes() {
+  return sizeof(double) * (static_cast<size_t>(BTT) * E + BTT);
+}
+
+template <typename T, int E>
+__global__ __launch_bounds__(BTT) void k_dense_tail_reg(const PixelMeta* __restrict__ metas,
+                                                        const int32_t* __restrict__ sel,
+                                                        double* __restrict__ fact, int64_t vec_elems,
+                                                        const T* __restrict__ xbuf,
+                                                        SolveState* __restrict__ states,
+                                                        T* __restrict__ pi_packed,
+                                                        dtm_solve_info* __restrict__ infos, KOpts o) {
+  __shared__ double red[3 * BTT / kWave];
+  extern __shared__ double xs[];  // tail_lds_bytes<E>()
+  const int q = sel[blockIdx.x];
+  const PixelMeta m = metas[q];
+  const StopState prev = states[q].s;
+  if (prev.done) return;
+  const int n = m.n;
+  const int ch = (n + BTT - 1) / BTT;  // at most E (the launcher's choice of E)
+  const int j0 = min(static_cast<int>(threadIdx.x) * ch, n);
+  const int cnt = min(ch, n - j0);
+  StopState st = prev;
+  if (prev.iter >= o.max_iter) {  // no sweeps left: the last iterate is the answer
+    for (int e = 0; e < cnt; ++e) pi_packed[m.pi_off + j0 + e] = xbuf[m.vec_off + j0 + e];
+    st.done = 1;
+    st.status = DTM_ENOTCONV;
+  } else {
+    const Vecs V = vecs(fact, vec_elems, m);
+    // tables in the chunks of this block's 512 threads: each thread then
+    // reads back only the g and 1/S it wrote itself
+    const double Lam = pixel_tables<double, BTT>(m, V.g, nullptr, nullptr, red);
+    const double c = exp(-Lam);
+    row_normalisers<double, BTT>(n, V.g, c, V.u, V.invs, red);
+    constexpr bool RT = E <= 8;  // g and 1/S in registers
+    constexpr int ER = RT ? E : 1;
+    const double* gp = V.g + j0;
+    const double* ip = V.invs + j0;
+    double gv[ER], iv[ER], xv[E], dv[E], yv[E];
+    double sum = 0.0, bad = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const bool own = e < cnt;
+      if constexpr (RT) {
+        gv[e] = own ? gp[e] : 0.0;
+        iv[e] = own ? ip[e] : 0.0;
+      }
+      xv[e] = own ? static_cast<double>(xbuf[m.vec_off + j0 + e]) : 0.0;
+      if (own) {
+        if (!(xv[e] >= 0.0) || !isfinite(xv[e])) bad += 1.0;
+        else sum += xv[e];
+      }
+    }
+    block_sum2<BTT>(sum, bad, red);
+    // the iterate as power_start takes it: normalised, or uniform if unusable
+    const bool usable = bad == 0.0 && sum > 0.0 && isfinite(sum);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      xv[e] = usable ? xv[e] / sum : 1.0 / n;
+      dv[e] = 0.0;
+      if (e < cnt) xs[tail_slot<E>(j0 + e)] = xv[e];
+    }
+    __syncthreads();
+    // the remaining sweeps of this start (the iterate is not re-run from
+    // uniform when they run out, whatever the start was)
+    stop_init(st, 0, 0);
+    KOpts oc = o;
+    oc.max_iter = o.max_iter - prev.iter;
+    const int l = m.l;
+    const double f = m.frac;
+    for (;;) {
+      double cs = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (e < cnt) {
+          int i = j0 + e - l;
+          if (i < 0) i += n;
+          double xi = xs[tail_slot<E>(i)];
+          if (f != 0.0) xi = (1.0 - f) * xi + f * xs[tail_slot<E>(i == 0 ? n - 1 : i - 1)];
+          yv[e] = xi * (RT ? iv[e % ER] : ip[e]);
+          cs += yv[e];
+        }
+      }
+      double tot;
+      double U = block_exclusive_scan<BTT>(cs, red, tot);  // every read of xs is done after it
+      double sy = 0.0, rs = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (e < cnt) {
+          U += yv[e];
+          yv[e] = (RT ? gv[e % ER] : gp[e]) * (c * tot + (1.0 - c) * U);
+          sy += yv[e];
+          rs += fabs(yv[e] - xv[e]);
+        }
+      }
+      block_sum2<BTT>(sy, rs, red);
+      double chg = 0.0, dd = 0.0, ddp = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (e < cnt) {
+          const double xn = yv[e] / sy;
+          const double d = xn - xv[e];
+          chg += fabs(d);
+          dd += d * d;
+          ddp += d * dv[e];
+          dv[e] = d;
+          xv[e] = xn;
+          xs[tail_slot<E>(j0 + e)] = xn;
+        }
+      }
+      block_sum3<BTT>(chg, dd, ddp, red);  // its barriers publish the new xs
+      const bool restart = stop_update(st, oc, chg, dd, ddp, rs, true, 1.1102230246251565e-16);
+      if (restart) {  // the same on every thread: the sums are the block's
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          xv[e] = 1.0 / n;
+          dv[e] = 0.0;
+          if (e < cnt) xs[tail_slot<E>(j0 + e)] = xv[e];
+        }
+        __syncthreads();
+      }
+      if (st.done) break;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (e < cnt) pi_packed[m.pi_off + j0 + e] = static_cast<T>(xv[e]);
+    st.total_iter += prev.total_iter;
+    st.flags |= prev.flags & (DTM_INFO_WARM_REJECTED | DTM_INFO_RESTARTED);
+  }
+  st.flags |= DTM_INFO_CONTINUED;
+  if (threadIdx.x == 0) {
+    dtm_solve_info info = make_info(st);
+    info.dense_sweeps = prev.total_iter;
+    infos[m.index] = info;
     states[q].s = st;
   }
 }
@@ -243,7 +400,11 @@ __global__ __launch_bounds__(BT) void k_solve_factored(const PixelMeta* __restri
   int j0, j1;
   chunk_of(m.n, j0, j1);
   for (int j = j0; j < j1; ++j) pi_packed[m.pi_off + j] = static_cast<T>(V.x[j]);
-  if (threadIdx.x == 0) infos[m.index] = make_info(st);
+  if (threadIdx.x == 0) {
+    dtm_solve_info info = make_info(st);
+    info.dense_sweeps = 0;  // no matrix is stored
+    infos[m.index] = info;
+  }
 }
 
 // ============================================================================
@@ -533,7 +694,11 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
     for (int e = 0; e < E; ++e)
       if (j0 + e < n) pi_packed[m.pi_off + j0 + e] = static_cast<T>(xo[e]);
-    if (lane == 0) infos[m.index] = make_info(st);
+    if (lane == 0) {
+      dtm_solve_info info = make_info(st);
+      info.dense_sweeps = 0;  // no matrix is stored
+      infos[m.index] = info;
+    }
   }
 }
 
@@ -1179,6 +1344,34 @@ using namespace dtm;
 
 namespace dtm {
 
+template <typename T, int E>
+int launch_tail_reg_e(const dtm_plan* plan, int count, const PixelMeta* metas, const int32_t* sel, double* fact,
+                      SolveState* states, void* pi, dtm_solve_info* infos, hipStream_t st) {
+  auto kern = fact::k_dense_tail_reg<T, E>;
+  constexpr size_t lds = fact::tail_lds_bytes<E>();
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          static_cast<int>(lds)) != hipSuccess)
+    return DTM_EHIP;
+  const T* xbuf = reinterpret_cast<const T*>(static_cast<char*>(plan->ws) + plan->off_xbuf);
+  hipLaunchKernelGGL(kern, dim3(count), dim3(fact::BTT), lds, st, metas, sel, fact, plan->vec_elems, xbuf, states,
+                     static_cast<T*>(pi), infos, plan->kopts);
+  return hipGetLastError() == hipSuccess ? DTM_OK : DTM_EHIP;
+}
+
+// The continuation of pixels of at most 8192 bins, in 512-thread blocks
+// holding ceil(n / 512) <= e bins per thread in registers.
+template <typename T>
+int launch_tail_reg(const dtm_plan* plan, int e, int count, const PixelMeta* metas, const int32_t* sel,
+                    double* fact, SolveState* states, void* pi, dtm_solve_info* infos, hipStream_t st) {
+  switch (e) {
+    case 2: return launch_tail_reg_e<T, 2>(plan, count, metas, sel, fact, states, pi, infos, st);
+    case 4: return launch_tail_reg_e<T, 4>(plan, count, metas, sel, fact, states, pi, infos, st);
+    case 8: return launch_tail_reg_e<T, 8>(plan, count, metas, sel, fact, states, pi, infos, st);
+    default: return launch_tail_reg_e<T, 16>(plan, count, metas, sel, fact, states, pi, infos, st);
+  }
+}
+
 int launch_dense_tail(const dtm_plan* plan, int banded, void* pi, dtm_solve_info* infos, void* stream) {
   const int count = static_cast<int>(banded ? plan->big_sel.size() : plan->small_sel.size());
   if (count == 0) return DTM_OK;
@@ -1188,6 +1381,12 @@ int launch_dense_tail(const dtm_plan* plan, int banded, void* pi, dtm_solve_info
   const int32_t* sel = reinterpret_cast<const int32_t*>(w + (banded ? plan->off_big : plan->off_small));
   double* fact = reinterpret_cast<double*>(w + plan->off_fact);
   SolveState* states = reinterpret_cast<SolveState*>(w + plan->off_state);
+  const int max_n = banded ? plan->max_n_big : plan->max_n_small;
+  if (max_n <= fact::BTT * 16) {
+    const int e = max_n <= 2 * fact::BTT ? 2 : max_n <= 4 * fact::BTT ? 4 : max_n <= 8 * fact::BTT ? 8 : 16;
+    return plan->dt == DTM_F32 ? launch_tail_reg<float>(plan, e, count, metas, sel, fact, states, pi, infos, st)
+                               : launch_tail_reg<double>(plan, e, count, metas, sel, fact, states, pi, infos, st);
+  }
   if (plan->dt == DTM_F32)
     hipLaunchKernelGGL((fact::k_dense_tail<float>), dim3(count), dim3(fact::BT), 0, st, metas, sel, fact,
                        plan->vec_elems, reinterpret_cast<const float*>(w + plan->off_xbuf), states,

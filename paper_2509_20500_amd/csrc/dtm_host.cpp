@@ -238,6 +238,7 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   plan->dt = dt;
   plan->kopts = ko;
   plan->check_every = ce;
+  static_assert(sizeof(dtm_tile_config) == 36, "dtm_tile_config layout");
   dtm_tile_config tc;
   std::memset(&tc, 0, sizeof(tc));
   if (tiles) tc = *tiles;
@@ -253,7 +254,8 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
       tc.fused_max_bins < 2 || tc.band_rows < 16 || tc.band_rows % 16 != 0 || tc.band_rows > 8192 ||
       tc.dense_sweeps < 1 || tc.dense_sweeps > ko.max_iter ||
       (tc.band_cpt != 1 && tc.band_cpt != 2 && tc.band_cpt != 4) ||
-      (tc.independent_paths != 0 && tc.independent_paths != 1) || tc.fused_blocks < 0) {
+      (tc.independent_paths != 0 && tc.independent_paths != 1) || tc.fused_blocks < 0 ||
+      tc.band_min_items < 0) {
     delete plan;
     return DTM_EINVAL;
   }
@@ -391,6 +393,8 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   off = align_up(off + sizeof(BandItem) * (plan->items.size() + 1), 256);
   plan->off_queue = off;
   off = align_up(off + 256, 256);
+  plan->off_live = off;
+  off = align_up(off + sizeof(int32_t) * (static_cast<size_t>(plan->tiles.dense_sweeps) + 1), 256);
   plan->off_citems = off;
   off = align_up(off + sizeof(BandItem) * (plan->citems.size() + 1), 256);
   plan->off_cbase = off;

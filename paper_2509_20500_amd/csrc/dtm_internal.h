@@ -174,6 +174,7 @@ struct dtm_plan {
   size_t off_meta, off_pool, off_colf, off_invs, off_scal, off_state, total_bytes;
   size_t off_small, off_big, off_items, off_xbuf, off_dprev, off_part, off_fact;
   size_t off_citems, off_cbase, off_bsum, off_ybuf, off_queue;
+  size_t off_live;     // banded path: int32 per launched sweep, the work items still running after it
   void* ws;            // bound workspace (device), or nullptr
   size_t ws_bytes;
   // created at bind: a second stream (default priority) and two events that

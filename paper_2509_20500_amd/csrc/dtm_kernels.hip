@@ -532,13 +532,28 @@ __global__ __launch_bounds__(BT) void k_solve_sweeps(const PixelMeta* __restrict
 // the steps, so no block ever waits for another.
 // ============================================================================
 
+// Whether banded sweep t (and its combine) runs.  The first sweep, which
+// builds, always does; a later one only while the work items of the pixels
+// still running after the previous sweep (counted by k_band_finish in
+// live[t - 1]) number at least min_items, or always when min_items is 0.
+// Every workgroup of the three launches reads the same count, so a sweep
+// runs or is skipped as a whole, and once one is skipped every later one is
+// (no count is taken in a skipped sweep).
+__device__ inline bool band_sweep_runs(const int32_t* live, int t, int min_items) {
+  return t == 0 || min_items == 0 ||
+         __hip_atomic_load(live + t - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= min_items;
+}
+
 template <typename T, int BT>
 __global__ __launch_bounds__(BT) void k_band_init(const PixelMeta* __restrict__ metas,
                                                   const int32_t* __restrict__ big,
                                                   const T* __restrict__ x0_packed,
                                                   T* __restrict__ xbuf, double* __restrict__ dprev,
-                                                  SolveState* __restrict__ states, int start_flux) {
+                                                  SolveState* __restrict__ states, int start_flux,
+                                                  int32_t* __restrict__ live, int nsweeps) {
   __shared__ double red[3 * BT / kWave];
+  if (blockIdx.x == 0)
+    for (int t = threadIdx.x; t < nsweeps; t += BT) live[t] = 0;
   const int q = big[blockIdx.x];
   const PixelMeta m = metas[q];
   const int n = m.n;
@@ -584,7 +599,7 @@ __global__ __launch_bounds__(BT) void k_band_sweep(const PixelMeta* __restrict__
                                                    const T* __restrict__ xbuf,
                                                    const SolveState* __restrict__ states,
                                                    double* __restrict__ part, int band_rows,
-                                                   int first) {
+                                                   const int32_t* __restrict__ live, int t, int min_items) {
   using V = typename Vec<T>::type;
   constexpr int VN = Vec<T>::n;
   // 16 column vectors in flight per thread (twice the one-block solver's):
@@ -593,6 +608,8 @@ __global__ __launch_bounds__(BT) void k_band_sweep(const PixelMeta* __restrict__
   constexpr int UE = 16 / CPT;
   extern __shared__ __align__(16) unsigned char smem[];
   T* xs = reinterpret_cast<T*>(smem);
+  if (!band_sweep_runs(live, t, min_items)) return;
+  const bool first = t == 0;
   const BandItem it = items[blockIdx.x];
   const PixelMeta m = metas[it.meta];
   const StopState& st = states[it.meta].s;
@@ -725,8 +742,10 @@ __global__ __launch_bounds__(BT) void k_band_colsum(const PixelMeta* __restrict_
                                                     const T* __restrict__ xbuf,
                                                     const SolveState* __restrict__ states,
                                                     double* __restrict__ ybuf, double* __restrict__ bsum,
-                                                    int colw) {
+                                                    int colw, const int32_t* __restrict__ live, int t,
+                                                    int min_items) {
   __shared__ double red[3 * BT / kWave];
+  if (!band_sweep_runs(live, t, min_items)) return;
   const BandItem it = citems[blockIdx.x];
   const PixelMeta m = metas[it.meta];
   if (states[it.meta].s.done) return;  // the same for every block of the pixel
@@ -767,8 +786,10 @@ __global__ __launch_bounds__(BT) void k_band_finish(const PixelMeta* __restrict_
                                                     const double* __restrict__ bsum, T* __restrict__ xbuf,
                                                     double* __restrict__ dprev, SolveState* __restrict__ states,
                                                     T* __restrict__ pi_packed, dtm_solve_info* __restrict__ infos,
-                                                    KOpts o, int colw) {
+                                                    KOpts o, int colw, int32_t* __restrict__ live, int t,
+                                                    int min_items) {
   __shared__ double red[3 * BT / kWave];
+  if (!band_sweep_runs(live, t, min_items)) return;
   const int q = big[blockIdx.x];
   const PixelMeta m = metas[q];
   StopState s = states[q].s;
@@ -831,6 +852,7 @@ __global__ __launch_bounds__(BT) void k_band_finish(const PixelMeta* __restrict_
     out.sum_y = sy;
     out.pad = 0.0;
     states[q] = out;
+    if (min_items > 0 && !s.done) atomicAdd(live + t, m.bands * nb);  // this pixel's items in sweep t + 1
   }
 }
 
@@ -940,6 +962,7 @@ __global__ __launch_bounds__(BT) void k_refine_f64(const PixelMeta* __restrict__
   if (tid == 0) {
     dtm_solve_info info = make_info(st);
     info.iterations += prev.iterations;
+    info.dense_sweeps = prev.dense_sweeps;
     info.flags |= (prev.flags & ~(DTM_INFO_STALLED)) | DTM_INFO_REFINED;
     infos[m.index] = info;
   }
@@ -1334,7 +1357,7 @@ int single_solve(const T* P, int32_t n, int64_t ld, const KOpts& ko, int check_e
     info->iterations = hs.s.total_iter;
     info->status = hs.s.status;
     info->flags = hs.s.flags;
-    info->reserved = 0;
+    info->dense_sweeps = hs.s.total_iter;
     info->change_l1 = hs.s.c1;
     info->residual_l1 = hs.s.resid;
     info->rho_hat = hs.s.rho;
@@ -1440,9 +1463,10 @@ int launch_band_init(const dtm_plan* plan, const PixelMeta* metas, const T* x0, 
   T* xbuf = reinterpret_cast<T*>(w + plan->off_xbuf);
   double* dprev = reinterpret_cast<double*>(w + plan->off_dprev);
   SolveState* states = reinterpret_cast<SolveState*>(w + plan->off_state);
+  int32_t* live = reinterpret_cast<int32_t*>(w + plan->off_live);
   const int nbig = static_cast<int>(plan->big_sel.size());
   hipLaunchKernelGGL((k_band_init<T, BT>), dim3(nbig), dim3(BT), 0, st, metas, big, x0, xbuf, dprev,
-                     states, plan->kopts.start_flux);
+                     states, plan->kopts.start_flux, live, plan->tiles.dense_sweeps);
   return last_launch();
 }
 
@@ -1467,9 +1491,11 @@ int launch_banded(const dtm_plan* plan, int t0, int t1, const PixelMeta* metas, 
   const int ncitems = static_cast<int>(plan->citems.size());
   const int colw = plan->band_threads * Vec<T>::n * plan->band_cpt;
   const size_t lds = sizeof(T) * static_cast<size_t>(plan->tiles.band_rows);
+  int32_t* live = reinterpret_cast<int32_t*>(w + plan->off_live);
+  const int mi = plan->tiles.band_min_items;
   int rc = DTM_OK;
   void (*sweep)(const PixelMeta*, const BandItem*, const T*, const double*, const T*, T*, const T*,
-                const SolveState*, double*, int, int) = nullptr;
+                const SolveState*, double*, int, const int32_t*, int, int) = nullptr;
   switch (plan->band_cpt) {
     case 1: sweep = k_band_sweep<T, BT, 1>; break;
     case 2: sweep = k_band_sweep<T, BT, 2>; break;
@@ -1477,11 +1503,11 @@ int launch_banded(const dtm_plan* plan, int t0, int t1, const PixelMeta* metas, 
   }
   for (int t = t0; t < t1; ++t) {
     hipLaunchKernelGGL(sweep, dim3(nitems), dim3(BT), lds, st, metas, items, colf, scal, invs, pool,
-                       xbuf, states, part, plan->tiles.band_rows, t == 0 ? 1 : 0);
+                       xbuf, states, part, plan->tiles.band_rows, live, t, mi);
     hipLaunchKernelGGL((k_band_colsum<T, BT>), dim3(ncitems), dim3(BT), 0, st, metas, citems, part, xbuf,
-                       states, ybuf, bsum, colw);
+                       states, ybuf, bsum, colw, live, t, mi);
     hipLaunchKernelGGL((k_band_finish<T, BT>), dim3(nbig), dim3(BT), 0, st, metas, big, cbase, ybuf, bsum, xbuf,
-                       dprev, states, pi, infos, plan->kopts, colw);
+                       dprev, states, pi, infos, plan->kopts, colw, live, t, mi);
     rc = last_launch();
     if (rc) return rc;
   }

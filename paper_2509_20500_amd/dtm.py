@@ -88,7 +88,7 @@ class SolveOpts(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [
         ("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
-        ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_int32), ("dense_sweeps", ctypes.c_int32),
         ("change_l1", ctypes.c_double), ("residual_l1", ctypes.c_double),
         ("rho_hat", ctypes.c_double),
     ]
@@ -99,20 +99,21 @@ class TileConfig(ctypes.Structure):
         ("fused_threads", ctypes.c_int32), ("fused_unroll", ctypes.c_int32),
         ("fused_max_bins", ctypes.c_int32), ("band_rows", ctypes.c_int32),
         ("dense_sweeps", ctypes.c_int32), ("band_cpt", ctypes.c_int32), ("independent_paths", ctypes.c_int32),
-        ("fused_blocks", ctypes.c_int32),
+        ("fused_blocks", ctypes.c_int32), ("band_min_items", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {"fused_threads": self.fused_threads, "fused_unroll": self.fused_unroll,
                 "fused_max_bins": self.fused_max_bins, "band_rows": self.band_rows,
                 "dense_sweeps": self.dense_sweeps, "band_cpt": self.band_cpt,
-                "independent_paths": self.independent_paths, "fused_blocks": self.fused_blocks}
+                "independent_paths": self.independent_paths, "fused_blocks": self.fused_blocks,
+                "band_min_items": self.band_min_items}
 
 
 def tiles(fused_threads=0, fused_unroll=0, fused_max_bins=0, band_rows=0, dense_sweeps=0, band_cpt=0,
-          independent_paths=0, fused_blocks=0):
+          independent_paths=0, fused_blocks=0, band_min_items=0):
     return TileConfig(fused_threads, fused_unroll, fused_max_bins, band_rows, dense_sweeps, band_cpt,
-                      independent_paths, fused_blocks)
+                      independent_paths, fused_blocks, band_min_items)
 
 
 SPECTRAL_INFO_DTYPE = np.dtype([
@@ -124,7 +125,7 @@ assert SPECTRAL_INFO_DTYPE.itemsize == 64
 SPECTRAL_INFO_BYTES = SPECTRAL_INFO_DTYPE.itemsize
 
 SOLVE_INFO_DTYPE = np.dtype([
-    ("iterations", "<i4"), ("status", "<i4"), ("flags", "<i4"), ("reserved", "<i4"),
+    ("iterations", "<i4"), ("status", "<i4"), ("flags", "<i4"), ("dense_sweeps", "<i4"),
     ("change_l1", "<f8"), ("residual_l1", "<f8"), ("rho_hat", "<f8"),
 ])
 assert SOLVE_INFO_DTYPE.itemsize == ctypes.sizeof(SolveInfo) == 40

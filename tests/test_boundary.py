@@ -50,7 +50,7 @@ def test_struct_layouts(d):
     assert ctypes.sizeof(d.Scene) == sc.SCENE_DTYPE.itemsize == 56
     assert ctypes.sizeof(d.SolveOpts) == 32
     assert ctypes.sizeof(d.SolveInfo) == 40
-    assert ctypes.sizeof(d.TileConfig) == 32
+    assert ctypes.sizeof(d.TileConfig) == 36
     assert d.dtm_version() >= 10000
 
 
@@ -212,10 +212,10 @@ def test_tile_config_defaults_and_limits(d):
     scenes = sc.batched_uneven(64)
     plan = d.Plan(scenes, "f32")
     t = plan.tiles
-    assert (t.band_rows, t.band_cpt) == (1024, 1)
+    assert (t.band_rows, t.band_cpt, t.band_min_items) == (1024, 1, 0)
     plan.close()
     for bad in (d.tiles(band_cpt=3), d.tiles(band_cpt=8), d.tiles(band_rows=8208), d.tiles(band_rows=24),
-                d.tiles(fused_unroll=16), d.tiles(independent_paths=2)):
+                d.tiles(fused_unroll=16), d.tiles(independent_paths=2), d.tiles(band_min_items=-1)):
         with pytest.raises(d.DtmError):
             d.Plan(scenes, "f32", tiles=bad)
     t = d.tiles(band_rows=512, band_cpt=2, fused_blocks=-1)
@@ -224,6 +224,12 @@ def test_tile_config_defaults_and_limits(d):
     plan = d.Plan(scenes, "f32", tiles=d.tiles(independent_paths=1))
     assert plan.tiles.independent_paths == 1
     plan.close()
+    # one int32 per launched banded sweep (the live work-item counts) is in the workspace
+    p32 = d.Plan(scenes, "f32", tiles=d.tiles(dense_sweeps=32))
+    p512 = d.Plan(scenes, "f32", d.opts(max_iter=1000), tiles=d.tiles(dense_sweeps=512))
+    assert p512.workspace_bytes - p32.workspace_bytes == 2304 - 256  # 4 (n + 1) bytes in 256-byte units
+    p32.close()
+    p512.close()
 
 
 def test_model_shift_matches_oracle_variants(d):

@@ -18,6 +18,14 @@ ending unconverged: banded pixels and one-block pixels alike.
   DTM_OK within 1e-6 of the oracle, the continued ones flagged.
 * max_iter reached inside the continuation ends DTM_ENOTCONV with the last
   iterate (a probability vector) as pi.
+* The banded hand-off (band_min_items): once the running pixels have fewer
+  work items than the threshold, the banded sweeps stop and those pixels
+  continue in float64.  Every pixel ends DTM_OK within 1e-6 of the float64
+  reference, eager and graph-replayed bit for bit alike; a threshold of one
+  item changes nothing; a threshold above the batch's items hands every
+  pixel over after the building sweep.
+* Pixels above 8192 bins continue in the four-wave kernel (g, 1/S and the
+  vectors in the workspace) rather than in registers.
 """
 import numpy as np
 import pytest
@@ -104,6 +112,8 @@ def test_uneven_banded_pixels_with_three_launched_sweeps():
     assert np.all(info["status"] == 0), info[info["status"] != 0]
     cont = (info["flags"] & d.DTM_INFO_CONTINUED) != 0
     assert cont.mean() > 0.5  # the others stop within the three launched sweeps
+    assert np.all(info["dense_sweeps"][cont] == 3) and np.all(info["iterations"][cont] > 3)
+    assert np.all(info["dense_sweeps"][~cont] == info["iterations"][~cont])
     worst = 0.0
     for p in range(scenes.size):
         ref, ok = factored_power(scenes[p])
@@ -155,3 +165,72 @@ def test_both_paths_continue_in_one_plan(graph):
         worst = max(worst, float(np.abs(got[p] - ref).sum()))
     print(f"graph={graph}: {int(cont.sum())} of {scenes.size} continued, max L1 {worst:.3e}", flush=True)
     assert worst <= TOL_F32
+
+
+def _uneven_banded():
+    scenes = sc.batched_uneven()
+    return scenes[scenes["n_bins"] > 2048]
+
+
+@pytest.fixture(scope="module")
+def uneven_banded_refs():
+    scenes = _uneven_banded()
+    refs = []
+    for s in scenes:
+        ref, ok = factored_power(s)
+        assert ok
+        refs.append(ref)
+    return scenes, refs
+
+
+@pytest.mark.parametrize("min_items", [256, 1 << 20])
+def test_banded_hand_off_to_the_continuation(uneven_banded_refs, min_items):
+    d = lib()
+    scenes, refs = uneven_banded_refs
+    o = d.opts(tol=1e-6)
+    o.flags |= d.DTM_FLAG_START_FLUX
+    tiles = d.tiles(band_min_items=min_items)
+    got, info = _solve(scenes, o, tiles=tiles)
+    got_g, info_g = _solve(scenes, o, tiles=tiles, graph=True)
+    assert all(np.array_equal(a, b) for a, b in zip(got, got_g))
+    assert np.array_equal(info, info_g)
+    assert np.all(info["status"] == 0), info[info["status"] != 0]
+    cont = (info["flags"] & d.DTM_INFO_CONTINUED) != 0
+    if min_items > 1000:
+        assert np.all(cont), info  # every pixel after the building sweep
+        assert np.all(info["dense_sweeps"] == 1)
+    else:
+        assert np.any(cont) and not np.all(cont)
+        # handed over together, after the same sweep
+        assert np.unique(info["dense_sweeps"][cont]).size == 1
+        assert np.all(info["dense_sweeps"][cont] < info["iterations"][cont])
+        assert np.all(info["dense_sweeps"][~cont] <= info["dense_sweeps"][cont][0])
+    l1 = np.array([np.abs(g - r).sum() for g, r in zip(got, refs)])
+    print(f"band_min_items {min_items}: {int(cont.sum())} of {scenes.size} continued, "
+          f"sweeps {np.bincount(info['iterations']).tolist()}, max L1 {l1.max():.3e}", flush=True)
+    assert l1.max() <= TOL_F32, (int(np.argmax(l1)), l1.max())
+
+
+def test_banded_hand_off_of_one_item_changes_nothing():
+    """While a pixel runs, the items left are at least one: the threshold
+    of one item never stops a sweep, and the bits are the default's."""
+    d = lib()
+    scenes = sc.batched_uneven(96, seed=143)
+    o = d.opts(tol=1e-6)
+    ref, ref_info = _solve(scenes, o)
+    got, info = _solve(scenes, o, tiles=d.tiles(band_min_items=1))
+    assert all(np.array_equal(a, b) for a, b in zip(got, ref))
+    assert np.array_equal(info, ref_info)
+
+
+def test_continuation_above_8192_bins():
+    d = lib()
+    scenes = sc.scene(dead_time=75.0, center=30.0, sigma=0.5, signal=9.0, background=9.0, n_bins=12288)
+    got, info = _solve(scenes, d.opts(tol=1e-6), tiles=d.tiles(dense_sweeps=3))
+    assert info["status"][0] == 0 and info["flags"][0] & d.DTM_INFO_CONTINUED
+    assert info["iterations"][0] > 3
+    ref, ok = factored_power(scenes[0])
+    assert ok
+    l1 = float(np.abs(got[0] - ref).sum())
+    print(f"12288 bins: {info['iterations'][0]} sweeps, L1 {l1:.3e}", flush=True)
+    assert l1 <= TOL_F32

@@ -36,6 +36,7 @@ def test_factored_solver_matches_oracle(dt, tol, bar):
     info = d.infos_to_numpy(infos)
     got = pi.cpu().numpy().astype(np.float64)
     assert np.all(info["status"] == 0), info[info["status"] != 0]
+    assert np.all(info["dense_sweeps"] == 0)  # no matrix is stored
     for p, (s, v) in enumerate(zip(scenes, split(got, plan.pi_offsets))):
         assert np.abs(v - oracle_pi(s)).sum() <= bar, (p, s)
     # the dense solver cannot run on a plan without matrices

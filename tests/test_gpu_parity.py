@@ -85,6 +85,7 @@ def test_single_pixel_n1000_float64_change_rule():
     info = d.stationary_pdf(P, pi, ws, d.opts(tol=1e-12, stop_rule=d.DTM_STOP_CHANGE))
     assert info.status == d.DTM_OK
     assert info.change_l1 < 1e-12
+    assert info.dense_sweeps == info.iterations
     ref = oracle_pi(s)
     assert np.abs(pi.cpu().numpy() - ref).sum() <= TOL_F64
     # the oracle's own power iteration takes about as many sweeps
@@ -328,6 +329,11 @@ def test_float32_paper_grid_with_refinement():
         assert err <= TOL_F32, (p, s, err, info[p])
     refined = (info["flags"] & d.DTM_INFO_REFINED) != 0
     print("refined pixels:", int(refined.sum()), "of", len(scenes))
+    # the float64 sweeps of a refined or continued pixel regenerate the
+    # matrix: they are not dense sweeps
+    f64 = refined | ((info["flags"] & d.DTM_INFO_CONTINUED) != 0)
+    assert np.all(info["dense_sweeps"][f64] < info["iterations"][f64])
+    assert np.all(info["dense_sweeps"][~f64] == info["iterations"][~f64])
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
