@@ -1122,13 +1122,15 @@ def main():
                                          f"batched_uniform_n1024_{args.dtype}_start_{args.start}")
                         if (not uneven and plan.n_pixels == 4096 and not graph and not tiles
                             and args.variant == "paper")
-                        # the uneven batch: the bytes depend on the dense-sweep budget and on
-                        # the split into one-block and banded pixels (band partial sums), not
-                        # on the workgroup shapes or on graph replay
+                        # the uneven batch: the bytes depend on the dense-sweep budget, the
+                        # banded hand-off, and the split into one-block and banded pixels and
+                        # their work items (band partial sums), not on the one-block workgroup
+                        # shapes or on graph replay
                         else measured_traffic("k_solve_build+k_solve_sweeps+k_band_sweep",
                                               f"batched_uneven_{args.dtype}_start_{args.start}"
                                               f"_dense{plan.tiles.dense_sweeps}_fmax{plan.tiles.fused_max_bins}"
-                                              f"_band{plan.tiles.band_rows}")
+                                              f"_band{plan.tiles.band_rows}_cpt{plan.tiles.band_cpt}"
+                                              f"_mi{plan.tiles.band_min_items}")
                         if (uneven and plan.n_pixels == 2048 and args.variant == "paper") else None),
             "kernel": ("k_solve_build + k_solve_sweeps" if not uneven
                        else "k_solve_build + k_solve_sweeps + k_band_sweep"),
