@@ -24,6 +24,9 @@ ending unconverged: banded pixels and one-block pixels alike.
   reference, eager and graph-replayed bit for bit alike; a threshold of one
   item changes nothing; a threshold above the batch's items hands every
   pixel over after the building sweep.
+* The hand-off in float32 and float64 plans whose two paths do not wait
+  for each other, from a caller's warm start: every pixel within the
+  dtype's bar.
 * Pixels above 8192 bins continue in the four-wave kernel (g, 1/S and the
   vectors in the workspace) rather than in registers.
 """
@@ -35,7 +38,7 @@ from oracle import pool as opool
 from synth import scenes as sc
 
 from factored_ref import factored_power
-from gpu_helpers import TOL_F32, lib, split, tdtype
+from gpu_helpers import TOL_F32, TOL_F64, default_opts, lib, run_batched, split, tdtype
 
 pytestmark = pytest.mark.gpu
 
@@ -234,3 +237,40 @@ def test_continuation_above_8192_bins():
     l1 = float(np.abs(got[0] - ref).sum())
     print(f"12288 bins: {info['iterations'][0]} sweeps, L1 {l1:.3e}", flush=True)
     assert l1 <= TOL_F32
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_banded_hand_off_with_warm_start_and_independent_paths(dt):
+    """The hand-off in a mixed plan of both dtypes whose paths do not wait
+    for each other, from a caller's warm start (the oracle's pi of a nearby
+    scene, so some pixels stop early and others run long): every pixel ends
+    DTM_OK within the dtype's bar of the float64 reference."""
+    d = lib()
+    scenes = sc.batched_uneven(160, seed=144)
+    near = scenes.copy()
+    near["signal_flux"] *= 1.05
+    n = scenes["n_bins"]
+    small = np.flatnonzero(n <= 2048)
+    refs = [None] * scenes.size
+    for p, r in zip(small, opool.stationary_many(scenes[small])):
+        refs[p] = r
+    x0 = []
+    warm_small = opool.stationary_many(near[small])
+    for p in range(scenes.size):
+        if n[p] > 2048:
+            refs[p], ok = factored_power(scenes[p])
+            assert ok
+            x0.append(factored_power(near[p])[0])
+        else:
+            x0.append(warm_small[int(np.searchsorted(small, p))])
+    x0 = torch.tensor(np.concatenate(x0), dtype=tdtype(dt), device="cuda")
+    tiles = d.tiles(band_min_items=256, independent_paths=1, dense_sweeps=12)
+    pi, info, off = run_batched(scenes, dt, x0=x0, solve_opts=default_opts(dt), tiles=tiles)
+    assert np.all(info["status"] == 0), info[info["status"] != 0]
+    warm = (info["flags"] & (d.DTM_INFO_WARM_REJECTED | d.DTM_INFO_RESTARTED)) == 0
+    assert np.all(warm)
+    l1 = np.array([np.abs(v - r).sum() for v, r in zip(split(pi, off), refs)])
+    cont = (info["flags"] & d.DTM_INFO_CONTINUED) != 0
+    print(f"{dt}: {int(cont.sum())} of {scenes.size} continued, sweeps {np.bincount(info['iterations']).tolist()}, "
+          f"max L1 {l1.max():.3e}", flush=True)
+    assert l1.max() <= (TOL_F32 if dt == "f32" else TOL_F64), (int(np.argmax(l1)), l1.max())
