@@ -138,10 +138,12 @@ def autotune(scenes, dtype, solve_opts=None, cache_path=DEFAULT_CACHE, reps=3, v
     run(cands)
     second = banded_candidates(scenes, dtm.tiles(**best_of()[1]))
     if second:
-        p = dtm.Plan(scenes, dtype, solve_opts, second[0])
-        extra = p.workspace_bytes
-        p.close()
-        if extra > ws.numel():  # the hand-off counters do not change the size; column chunks may
+        extra = 0
+        for t in second:  # column chunks change the combine's bookkeeping a little
+            p = dtm.Plan(scenes, dtype, solve_opts, t)
+            extra = max(extra, p.workspace_bytes)
+            p.close()
+        if extra > ws.numel():
             del ws
             ws = torch.empty(extra, dtype=torch.uint8, device="cuda")
         run(second)
