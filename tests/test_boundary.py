@@ -314,3 +314,28 @@ def test_spectral_scratch_sizes(d):
     mix = 16 * 2 * 8 * 1100 * 1100
     assert mix <= extra < mix + 2 * 256 + 8 * 16
     big.close()
+
+
+def test_autotune_search_space(d):
+    """The autotuner's two stages, host only: the launch-shape grid is
+    pruned to shapes that differ for the batch, and the banded stage varies
+    only the column chunks and the hand-off threshold around the best shape
+    (nothing for a batch without banded pixels)."""
+    from paper_2509_20500_amd.autotune import banded_candidates, candidates
+    uniform, uneven = sc.batched_uniform(64), sc.batched_uneven(64)
+    assert len(candidates(uniform)) == 8  # threads x unroll x dense budget
+    first = candidates(uneven)
+    sigs = {tuple(sorted(t.as_dict().items())) for t in first}
+    assert len(sigs) == len(first) and all(t.band_cpt == 1 and t.band_min_items == 0 for t in first)
+    best = first[5]
+    second = banded_candidates(uneven, best)
+    pairs = {(t.band_cpt, t.band_min_items) for t in second}
+    assert len(second) == 8 and (best.band_cpt, best.band_min_items) not in pairs
+    assert pairs | {(1, 0)} == {(c, m) for c in (1, 2, 4) for m in (0, 128, 256)}
+    for t in second:  # only those two fields move
+        a, b = t.as_dict(), best.as_dict()
+        assert {k for k in a if a[k] != b[k]} <= {"band_cpt", "band_min_items"}
+    assert banded_candidates(uniform, candidates(uniform)[0]) == []
+    # every candidate makes a valid plan
+    for t in first[:4] + second:
+        d.Plan(uneven, "f32", tiles=t).close()
