@@ -9,7 +9,7 @@ L1 <= 1e-6.  One step = one dtm_solve_batched call over all pixels: bin
 tables, shifted transition matrices, power iteration, float64 check.  Inputs
 (scene metadata) are resident in HBM before the timed region.
 
-Prints one JSON line.  --gpus above 1 is refused: the build targets one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the solver runs on one GPU.
 """
 from __future__ import annotations
 

@@ -55,7 +55,7 @@ extern "C" {
 #define DTM_EHIP     (-3)  /* a HIP runtime call or kernel launch failed      */
 #define DTM_EALIAS   (-4)  /* input and output buffers overlap                */
 #define DTM_ENOSPACE (-5)  /* workspace too small                             */
-#define DTM_ENOTSUP  (-6)  /* valid request this build does not support       */
+#define DTM_ENOTSUP  (-6)  /* valid request the library does not support      */
 
 typedef void* dtm_stream_t; /* a hipStream_t */
 

@@ -183,7 +183,7 @@ const char* dtm_status_string(int status) {
     case DTM_EHIP: return "HIP runtime error";
     case DTM_EALIAS: return "input and output buffers overlap";
     case DTM_ENOSPACE: return "workspace too small";
-    case DTM_ENOTSUP: return "not supported by this build";
+    case DTM_ENOTSUP: return "not supported by the library";
     default: return "unknown status";
   }
 }
