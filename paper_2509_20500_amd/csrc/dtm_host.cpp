@@ -363,6 +363,12 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
       const int32_t cblocks = (m.n + colw - 1) / colw;
       for (int32_t b = 0; b < m.bands; ++b)
         for (int32_t cb = 0; cb < cblocks; ++cb) plan->items.push_back(BandItem{q, b, cb, 0});
+      if (plan->band_cpt > 1) {
+        const int32_t colw1 = plan->band_threads * vn;
+        const int32_t cblocks1 = (m.n + colw1 - 1) / colw1;
+        for (int32_t b = 0; b < m.bands; ++b)
+          for (int32_t cb = 0; cb < cblocks1; ++cb) plan->build_items.push_back(BandItem{q, b, cb, 0});
+      }
       // the combine's column blocks (stage 1) and where the pixel's start
       plan->cbase.push_back(static_cast<int32_t>(plan->citems.size()));
       for (int32_t cb = 0; cb < cblocks; ++cb) plan->citems.push_back(BandItem{q, 0, cb, 0});
@@ -395,6 +401,8 @@ int dtm_plan_create(const dtm_scene* scenes_host, int32_t n_pixels, dtm_dtype dt
   off = align_up(off + 256, 256);
   plan->off_live = off;
   off = align_up(off + sizeof(int32_t) * (static_cast<size_t>(plan->tiles.dense_sweeps) + 1), 256);
+  plan->off_build_items = off;
+  off = align_up(off + sizeof(BandItem) * (plan->build_items.size() + 1), 256);
   plan->off_citems = off;
   off = align_up(off + sizeof(BandItem) * (plan->citems.size() + 1), 256);
   plan->off_cbase = off;

@@ -163,6 +163,11 @@ struct dtm_plan {
   // pixels of the fused one-block kernel and of the banded multi-block path
   std::vector<int32_t> small_sel, big_sel;
   std::vector<dtm::BandItem> items;
+  // the building sweep's items when band_cpt > 1: the same bands in column
+  // blocks of one vector per thread (256 x 4 float / 2 double columns), so
+  // that the matrix writes are spread over four or two times as many
+  // workgroups; the partial sums they write are the same
+  std::vector<dtm::BandItem> build_items;
   // banded combine, stage 1: one item per column block of each banded pixel
   // (band 0), and each banded pixel's first column block in that list
   std::vector<dtm::BandItem> citems;
@@ -175,6 +180,7 @@ struct dtm_plan {
   size_t off_small, off_big, off_items, off_xbuf, off_dprev, off_part, off_fact;
   size_t off_citems, off_cbase, off_bsum, off_ybuf, off_queue;
   size_t off_live;     // banded path: int32 per launched sweep, the work items still running after it
+  size_t off_build_items;
   void* ws;            // bound workspace (device), or nullptr
   size_t ws_bytes;
   // created at bind: a second stream (default priority) and two events that

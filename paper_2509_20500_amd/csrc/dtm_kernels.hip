@@ -1502,8 +1502,16 @@ int launch_banded(const dtm_plan* plan, int t0, int t1, const PixelMeta* metas, 
     default: sweep = k_band_sweep<T, BT, 4>; break;
   }
   for (int t = t0; t < t1; ++t) {
-    hipLaunchKernelGGL(sweep, dim3(nitems), dim3(BT), lds, st, metas, items, colf, scal, invs, pool,
-                       xbuf, states, part, plan->tiles.band_rows, live, t, mi);
+    if (t == 0 && !plan->build_items.empty()) {
+      // the building sweep in one-vector column blocks: its writes spread
+      // over more workgroups; the same partial sums
+      hipLaunchKernelGGL((k_band_sweep<T, BT, 1>), dim3(static_cast<int>(plan->build_items.size())), dim3(BT),
+                         lds, st, metas, reinterpret_cast<const BandItem*>(w + plan->off_build_items), colf,
+                         scal, invs, pool, xbuf, states, part, plan->tiles.band_rows, live, t, mi);
+    } else {
+      hipLaunchKernelGGL(sweep, dim3(nitems), dim3(BT), lds, st, metas, items, colf, scal, invs, pool,
+                         xbuf, states, part, plan->tiles.band_rows, live, t, mi);
+    }
     hipLaunchKernelGGL((k_band_colsum<T, BT>), dim3(ncitems), dim3(BT), 0, st, metas, citems, part, xbuf,
                        states, ybuf, bsum, colw, live, t, mi);
     hipLaunchKernelGGL((k_band_finish<T, BT>), dim3(nbig), dim3(BT), 0, st, metas, big, cbase, ybuf, bsum, xbuf,
@@ -1809,6 +1817,10 @@ int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes, d
   if (!plan->items.empty() &&
       hipMemcpyAsync(w + plan->off_items, plan->items.data(), sizeof(BandItem) * plan->items.size(),
                      hipMemcpyHostToDevice, st) != hipSuccess)
+    return DTM_EHIP;
+  if (!plan->build_items.empty() &&
+      hipMemcpyAsync(w + plan->off_build_items, plan->build_items.data(),
+                     sizeof(BandItem) * plan->build_items.size(), hipMemcpyHostToDevice, st) != hipSuccess)
     return DTM_EHIP;
   if (!plan->citems.empty() &&
       (hipMemcpyAsync(w + plan->off_citems, plan->citems.data(), sizeof(BandItem) * plan->citems.size(),

@@ -145,6 +145,13 @@ int main() {
       const int32_t colw = 256 * (dt == DTM_F32 ? 4 : 2) * out.band_cpt;
       EXPECT(it.colblock >= 0 && static_cast<int64_t>(it.colblock) * colw < m.n);
     }
+    // the building sweep's finer items: only with column chunks, inside their pixel
+    EXPECT(p->build_items.empty() == (out.band_cpt == 1 || p->items.empty()));
+    for (const dtm::BandItem& it : p->build_items) {
+      const dtm::PixelMeta& m = p->meta[it.meta];
+      EXPECT(it.band >= 0 && it.band < m.bands && it.colblock >= 0 &&
+             static_cast<int64_t>(it.colblock) * 256 * (dt == DTM_F32 ? 4 : 2) < m.n);
+    }
     destroy(p);
   }
   // argument errors

@@ -129,3 +129,36 @@ def test_persistent_one_block_workgroups_give_the_same_bits(blocks):
     g.close()
     plan.close()
     assert np.all(d.infos_to_numpy(ref[1])["status"] == 0)
+
+
+def test_banded_column_chunks_agree():
+    """The banded sweep's column vectors per thread (1, 2, 4) change only
+    which workgroup adds which columns (every column's partial sum runs over
+    the band's rows in order; the building sweep of a plan with 2 or 4
+    vectors runs in one-vector column blocks) and how the combine groups
+    the column sums of y and |y - x|: the same sweeps and statuses, pi equal
+    to float32 rounding, and each plan bit for bit the same eager and
+    graph-replayed."""
+    d = lib()
+    scenes = np.concatenate([sc.batched_uneven(64, seed=116), sc.random_small(8, seed=117)])
+    ref = None
+    for cpt in (1, 2, 4):
+        _, plan, ws, pi, infos = _setup(scenes, "f32", d.tiles(band_cpt=cpt, fused_max_bins=1024))
+        plan.solve(pi, infos)
+        torch.cuda.synchronize()
+        got = (pi.clone(), infos.clone())
+        g = plan.graph(pi, infos)
+        pi.fill_(float("nan"))
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(pi, got[0]) and torch.equal(infos, got[1])
+        g.close()
+        plan.close()
+        if ref is None:
+            ref = got
+        else:
+            a, b = d.infos_to_numpy(got[1]), d.infos_to_numpy(ref[1])
+            assert np.array_equal(a["iterations"], b["iterations"]) and np.array_equal(a["status"], b["status"])
+            assert np.allclose(a["residual_l1"], b["residual_l1"], rtol=1e-9, atol=1e-15), cpt
+            assert float((got[0].double() - ref[0].double()).abs().max()) <= 2.0 ** -24, cpt
+    assert np.all(d.infos_to_numpy(ref[1])["status"] == 0)
