@@ -332,8 +332,10 @@ int dtm_plan_bind(dtm_plan* plan, void* workspace_dev, size_t workspace_bytes,
  * fused_max_bins take one workgroup each in two launches: every matrix is
  * written (with the first sweep taken on the way), then the remaining sweeps
  * read them; larger pixels take the banded launches.  A pixel still running
- * after dense_sweeps sweeps goes on in float64 on the factored product of the
- * same matrix (DTM_INFO_CONTINUED).  Writes pi
+ * after dense_sweeps sweeps, or a banded pixel still running once the banded
+ * pixels hold fewer than band_min_items work items, goes on in float64 on
+ * the factored product of the same matrix (DTM_INFO_CONTINUED; the report's
+ * dense_sweeps counts the sweeps before).  Writes pi
  * packed by pi_offsets (dtype of the plan) and one dtm_solve_info per pixel
  * to infos_dev (device memory, plan order = input order).  x0_packed_dev
  * (packed like pi, dtype of the plan) seeds the iteration; NULL = uniform.
