@@ -274,3 +274,25 @@ def test_banded_hand_off_with_warm_start_and_independent_paths(dt):
     print(f"{dt}: {int(cont.sum())} of {scenes.size} continued, sweeps {np.bincount(info['iterations']).tolist()}, "
           f"max L1 {l1.max():.3e}", flush=True)
     assert l1.max() <= (TOL_F32 if dt == "f32" else TOL_F64), (int(np.argmax(l1)), l1.max())
+
+
+@pytest.mark.parametrize("case", ["hand-off", "budget of max_iter"])
+def test_max_iter_with_the_register_continuation(case):
+    """max_iter on either side of the continuation: a slowly mixing
+    4096-bin pixel handed off after its building sweep runs out of sweeps
+    inside the continuation (flagged continued, one dense sweep); with a
+    dense budget of max_iter sweeps the banded launches themselves stop it
+    and the continuation leaves it alone.  Both end DTM_ENOTCONV with a
+    probability vector, their sweeps counted."""
+    d = lib()
+    scenes = sc.scene(dead_time=75.0, center=30.0, sigma=0.5, signal=10.0, background=10.0, n_bins=4096)
+    if case == "hand-off":
+        got, info = _solve(scenes, d.opts(tol=1e-6, max_iter=12), tiles=d.tiles(band_min_items=1 << 20))
+        assert info["iterations"][0] == 12 and info["dense_sweeps"][0] == 1
+        assert info["flags"][0] & d.DTM_INFO_CONTINUED
+    else:
+        got, info = _solve(scenes, d.opts(tol=1e-6, max_iter=3), tiles=d.tiles(dense_sweeps=3))
+        assert info["iterations"][0] == 3 and info["dense_sweeps"][0] == 3
+        assert not info["flags"][0] & d.DTM_INFO_CONTINUED
+    assert info["status"][0] == d.DTM_ENOTCONV
+    assert np.all(got[0] >= 0) and abs(got[0].sum() - 1.0) < 1e-5
